@@ -1,0 +1,296 @@
+/*
+ * FP64 CPU oracle for the guided filter and the Fast Guided Filter
+ * (He & Sun, "Fast Guided Filter", arXiv 1505.00996).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * statement of what the GPU library computes.  It is used by the tests, by the
+ * smoke check and by the benchmark's CPU-baseline leg, and by nothing else.
+ * It shares no code, header, table or constant with the HIP path.
+ *
+ * Everything is double precision, single threaded, with explicit loops.
+ * Images are dense row-major arrays: pixel (y, x) of an h-by-w image is at
+ * index y*w + x; channel k of a c-channel image starts at k*h*w.
+ *
+ * Conventions where the paper is silent (each is listed with its reason in
+ * the design notes of the repository):
+ *   - a window of radius r is the (2r+1)x(2r+1) square centred on a pixel
+ *     (Sec. 2, below Eq. 1);
+ *   - the mean filter f_mean averages over the part of the window that lies
+ *     inside the image (clip-normalised border), which makes the average of
+ *     the a_k over all windows containing pixel i (Eq. 4) a box mean;
+ *   - the variance is the population variance, corr_I - mean_I^2, exactly as
+ *     Algorithm 1 step 2 writes it; it is not clamped;
+ *   - the low-resolution radius is r/s rounded half up, at least 1 when r>0;
+ *   - low-resolution size is ceil(h/s) x ceil(w/s); geometry uses exactly s;
+ *   - nearest-neighbour subsampling takes full-res index s*y + floor(s/2),
+ *     clamped to the image; bilinear subsampling samples the low-res pixel
+ *     centre s*y + (s-1)/2 with two clamped taps (no antialias prefilter);
+ *   - bilinear upsampling uses half-pixel centres, u = (y+0.5)/s - 0.5, with
+ *     taps clamped to the low-res map;
+ *   - a multi-channel p is filtered channel by channel with the same gray I.
+ *
+ * Parity status: every function here is pinned by the CPU tests (brute-force
+ * window loops, scipy/torch special cases, a least-squares solve of the
+ * windowed ridge regression, and closed-form invariants of Eqs. 1-4).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_NEAREST 0
+#define ORACLE_BILINEAR 1
+
+static int imin(int a, int b) { return a < b ? a : b; }
+static int imax(int a, int b) { return a > b ? a : b; }
+static int iclamp(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* Low-resolution radius r' = r/s (Algorithm 2, step 1), rounded half up with
+ * integer arithmetic; at least 1 when r > 0 so a window never collapses. */
+int oracle_lowres_radius(int r, int s)
+{
+    if (r <= 0) return 0;
+    int rl = (2 * r + s) / (2 * s);
+    return rl < 1 ? 1 : rl;
+}
+
+/* Low-resolution extent of an n-pixel axis subsampled by s: ceil(n/s). */
+int oracle_lowres_size(int n, int s) { return (n + s - 1) / s; }
+
+/*
+ * f_mean(x, r) of Algorithm 1: for every pixel, the mean of x over the
+ * (2r+1)x(2r+1) window centred on it, restricted to the image and divided by
+ * the number of in-image pixels of that window.  The double sum over the
+ * window is taken as a sum over rows of sums along each row; the window
+ * count is the product of the clipped row and column extents.
+ */
+int oracle_box_mean(const double *x, int h, int w, int r, double *out)
+{
+    if (h <= 0 || w <= 0 || r < 0) return -1;
+    double *rowsum = (double *)malloc(sizeof(double) * (size_t)h * (size_t)w);
+    double *acc = (double *)malloc(sizeof(double) * (size_t)w);
+    if (!rowsum || !acc) { free(rowsum); free(acc); return -2; }
+
+    for (int y = 0; y < h; ++y) {
+        const double *src = x + (size_t)y * w;
+        double *dst = rowsum + (size_t)y * w;
+        for (int xx = 0; xx < w; ++xx) {
+            double s = 0.0;
+            for (int k = imax(0, xx - r); k <= imin(w - 1, xx + r); ++k) s += src[k];
+            dst[xx] = s;
+        }
+    }
+    for (int y = 0; y < h; ++y) {
+        int y0 = imax(0, y - r), y1 = imin(h - 1, y + r);
+        for (int xx = 0; xx < w; ++xx) acc[xx] = 0.0;
+        /* rows are added in ascending order, the same order as a plain
+         * per-pixel loop over the window rows */
+        for (int k = y0; k <= y1; ++k) {
+            const double *src = rowsum + (size_t)k * w;
+            for (int xx = 0; xx < w; ++xx) acc[xx] += src[xx];
+        }
+        double *dst = out + (size_t)y * w;
+        for (int xx = 0; xx < w; ++xx) {
+            int x0 = imax(0, xx - r), x1 = imin(w - 1, xx + r);
+            double count = (double)(y1 - y0 + 1) * (double)(x1 - x0 + 1);
+            dst[xx] = acc[xx] / count;
+        }
+    }
+    free(rowsum);
+    free(acc);
+    return 0;
+}
+
+/*
+ * f_subsample(x, s) of Algorithm 2, step 1 (the paper allows nearest-neighbour
+ * or bilinear).  Output is ceil(h/s) x ceil(w/s).
+ *   nearest : x(min(s*y + s/2, h-1), min(s*x + s/2, w-1)).
+ *   bilinear: point sample at the low-res pixel centre u = s*y + (s-1)/2
+ *             (half-pixel convention), taps floor(u), floor(u)+1 clamped.
+ */
+static void axis_sample(int j, int s, int n, int mode, int *t0, int *t1, double *wt)
+{
+    if (mode == ORACLE_NEAREST) {
+        *t0 = imin(s * j + s / 2, n - 1);
+        *t1 = *t0;
+        *wt = 0.0;
+        return;
+    }
+    double u = (double)s * j + 0.5 * (double)(s - 1);
+    double f = floor(u);
+    *wt = u - f;
+    *t0 = iclamp((int)f, 0, n - 1);
+    *t1 = iclamp((int)f + 1, 0, n - 1);
+}
+
+int oracle_subsample(const double *x, int h, int w, int s, int mode, double *out)
+{
+    if (h <= 0 || w <= 0 || s < 1) return -1;
+    if (mode != ORACLE_NEAREST && mode != ORACLE_BILINEAR) return -1;
+    int hl = oracle_lowres_size(h, s), wl = oracle_lowres_size(w, s);
+    for (int y = 0; y < hl; ++y) {
+        int ya, yb;
+        double wy;
+        axis_sample(y, s, h, mode, &ya, &yb, &wy);
+        for (int xx = 0; xx < wl; ++xx) {
+            int xa, xb;
+            double wx;
+            axis_sample(xx, s, w, mode, &xa, &xb, &wx);
+            double v00 = x[(size_t)ya * w + xa], v01 = x[(size_t)ya * w + xb];
+            double v10 = x[(size_t)yb * w + xa], v11 = x[(size_t)yb * w + xb];
+            out[(size_t)y * wl + xx] =
+                (1.0 - wy) * ((1.0 - wx) * v00 + wx * v01) + wy * ((1.0 - wx) * v10 + wx * v11);
+        }
+    }
+    return 0;
+}
+
+/*
+ * f_upsample(x, s) of Algorithm 2, step 6: bilinear interpolation of an
+ * hl x wl map back to h x w.  Full-res pixel y sits at low-res coordinate
+ * u = (y + 0.5)/s - 0.5; the taps floor(u) and floor(u)+1 are clamped to the
+ * low-res map, with weight u - floor(u) on the second.
+ */
+int oracle_upsample(const double *lo, int hl, int wl, int s, int h, int w, double *out)
+{
+    if (hl <= 0 || wl <= 0 || h <= 0 || w <= 0 || s < 1) return -1;
+    for (int y = 0; y < h; ++y) {
+        double u = ((double)y + 0.5) / (double)s - 0.5;
+        double fu = floor(u);
+        double wy = u - fu;
+        int ya = iclamp((int)fu, 0, hl - 1), yb = iclamp((int)fu + 1, 0, hl - 1);
+        for (int xx = 0; xx < w; ++xx) {
+            double v = ((double)xx + 0.5) / (double)s - 0.5;
+            double fv = floor(v);
+            double wx = v - fv;
+            int xa = iclamp((int)fv, 0, wl - 1), xb = iclamp((int)fv + 1, 0, wl - 1);
+            double v00 = lo[(size_t)ya * wl + xa], v01 = lo[(size_t)ya * wl + xb];
+            double v10 = lo[(size_t)yb * wl + xa], v11 = lo[(size_t)yb * wl + xb];
+            out[(size_t)y * w + xx] =
+                (1.0 - wy) * ((1.0 - wx) * v00 + wx * v01) + wy * ((1.0 - wx) * v10 + wx * v11);
+        }
+    }
+    return 0;
+}
+
+/*
+ * Algorithm 1, steps 1-3, for one channel of p: the per-window linear
+ * coefficients of Eqs. 2-3,
+ *   a = (mean(I.*p) - mean(I) mean(p)) / (var(I) + eps),  b = mean(p) - a mean(I),
+ * with every mean a clip-normalised box mean of radius r.
+ */
+int oracle_coefficients(const double *I, const double *p, int h, int w, int r, double eps,
+                        double *a, double *b)
+{
+    size_t n = (size_t)h * (size_t)w;
+    double *mean_I = (double *)malloc(sizeof(double) * n);
+    double *mean_p = (double *)malloc(sizeof(double) * n);
+    double *corr_I = (double *)malloc(sizeof(double) * n);
+    double *corr_Ip = (double *)malloc(sizeof(double) * n);
+    double *tmp = (double *)malloc(sizeof(double) * n);
+    int rc = 0;
+    if (!mean_I || !mean_p || !corr_I || !corr_Ip || !tmp) { rc = -2; goto done; }
+
+    /* step 1: four mean filters; the products are formed pixel by pixel first */
+    if ((rc = oracle_box_mean(I, h, w, r, mean_I))) goto done;
+    if ((rc = oracle_box_mean(p, h, w, r, mean_p))) goto done;
+    for (size_t i = 0; i < n; ++i) tmp[i] = I[i] * I[i];
+    if ((rc = oracle_box_mean(tmp, h, w, r, corr_I))) goto done;
+    for (size_t i = 0; i < n; ++i) tmp[i] = I[i] * p[i];
+    if ((rc = oracle_box_mean(tmp, h, w, r, corr_Ip))) goto done;
+
+    /* steps 2-3: variance, covariance, then the closed forms of Eqs. 2-3 */
+    for (size_t i = 0; i < n; ++i) {
+        double var_I = corr_I[i] - mean_I[i] * mean_I[i];
+        double cov_Ip = corr_Ip[i] - mean_I[i] * mean_p[i];
+        a[i] = cov_Ip / (var_I + eps);
+        b[i] = mean_p[i] - a[i] * mean_I[i];
+    }
+done:
+    free(mean_I); free(mean_p); free(corr_I); free(corr_Ip); free(tmp);
+    return rc;
+}
+
+/*
+ * Algorithm 1 (the guided filter) for a c-channel p with gray guide I.
+ * Per channel: a, b from Eqs. 2-3 (steps 1-3), their box means (step 4) and
+ * q = mean_a .* I + mean_b (step 5, Eq. 4).
+ * Optional outputs (may be NULL), c*h*w each: a, b, mean_a, mean_b.
+ */
+int oracle_guided_filter(const double *I, const double *p, int c, int h, int w, int r,
+                         double eps, double *q, double *a_out, double *b_out,
+                         double *mean_a_out, double *mean_b_out)
+{
+    if (h <= 0 || w <= 0 || c <= 0 || r < 0 || !(eps > 0.0)) return -1;
+    size_t n = (size_t)h * (size_t)w;
+    double *a = (double *)malloc(sizeof(double) * n);
+    double *b = (double *)malloc(sizeof(double) * n);
+    double *ma = (double *)malloc(sizeof(double) * n);
+    double *mb = (double *)malloc(sizeof(double) * n);
+    int rc = 0;
+    if (!a || !b || !ma || !mb) { rc = -2; goto done; }
+    for (int k = 0; k < c; ++k) {
+        const double *pk = p + (size_t)k * n;
+        double *qk = q + (size_t)k * n;
+        if ((rc = oracle_coefficients(I, pk, h, w, r, eps, a, b))) goto done;
+        if ((rc = oracle_box_mean(a, h, w, r, ma))) goto done;
+        if ((rc = oracle_box_mean(b, h, w, r, mb))) goto done;
+        for (size_t i = 0; i < n; ++i) qk[i] = ma[i] * I[i] + mb[i];
+        if (a_out) memcpy(a_out + (size_t)k * n, a, sizeof(double) * n);
+        if (b_out) memcpy(b_out + (size_t)k * n, b, sizeof(double) * n);
+        if (mean_a_out) memcpy(mean_a_out + (size_t)k * n, ma, sizeof(double) * n);
+        if (mean_b_out) memcpy(mean_b_out + (size_t)k * n, mb, sizeof(double) * n);
+    }
+done:
+    free(a); free(b); free(ma); free(mb);
+    return rc;
+}
+
+/*
+ * Algorithm 2 (the Fast Guided Filter) for a c-channel p with gray guide I.
+ *   step 1: I' = f_subsample(I, s), p' = f_subsample(p, s), r' = r/s;
+ *   steps 2-5: Algorithm 1 steps 1-4 on I', p' at radius r' -> mean_a, mean_b;
+ *   step 6: mean_a, mean_b bilinearly upsampled to h x w;
+ *   step 7: q = mean_a .* I + mean_b against the full-resolution I.
+ * Optional low-resolution outputs (may be NULL), c*hl*wl each: a, b,
+ * mean_a, mean_b before upsampling.
+ */
+int oracle_fast_guided_filter(const double *I, const double *p, int c, int h, int w, int r,
+                              int s, double eps, int mode, double *q, double *a_lo,
+                              double *b_lo, double *mean_a_lo, double *mean_b_lo)
+{
+    if (h <= 0 || w <= 0 || c <= 0 || r < 0 || s < 1 || !(eps > 0.0)) return -1;
+    if (mode != ORACLE_NEAREST && mode != ORACLE_BILINEAR) return -1;
+    int hl = oracle_lowres_size(h, s), wl = oracle_lowres_size(w, s);
+    int rl = oracle_lowres_radius(r, s);
+    size_t n = (size_t)h * (size_t)w, nl = (size_t)hl * (size_t)wl;
+    double *Il = (double *)malloc(sizeof(double) * nl);
+    double *pl = (double *)malloc(sizeof(double) * nl);
+    double *a = (double *)malloc(sizeof(double) * nl);
+    double *b = (double *)malloc(sizeof(double) * nl);
+    double *ma = (double *)malloc(sizeof(double) * nl);
+    double *mb = (double *)malloc(sizeof(double) * nl);
+    double *ua = (double *)malloc(sizeof(double) * n);
+    double *ub = (double *)malloc(sizeof(double) * n);
+    int rc = 0;
+    if (!Il || !pl || !a || !b || !ma || !mb || !ua || !ub) { rc = -2; goto done; }
+
+    if ((rc = oracle_subsample(I, h, w, s, mode, Il))) goto done;
+    for (int k = 0; k < c; ++k) {
+        const double *pk = p + (size_t)k * n;
+        double *qk = q + (size_t)k * n;
+        if ((rc = oracle_subsample(pk, h, w, s, mode, pl))) goto done;
+        if ((rc = oracle_coefficients(Il, pl, hl, wl, rl, eps, a, b))) goto done;
+        if ((rc = oracle_box_mean(a, hl, wl, rl, ma))) goto done;
+        if ((rc = oracle_box_mean(b, hl, wl, rl, mb))) goto done;
+        if ((rc = oracle_upsample(ma, hl, wl, s, h, w, ua))) goto done;
+        if ((rc = oracle_upsample(mb, hl, wl, s, h, w, ub))) goto done;
+        for (size_t i = 0; i < n; ++i) qk[i] = ua[i] * I[i] + ub[i];
+        if (a_lo) memcpy(a_lo + (size_t)k * nl, a, sizeof(double) * nl);
+        if (b_lo) memcpy(b_lo + (size_t)k * nl, b, sizeof(double) * nl);
+        if (mean_a_lo) memcpy(mean_a_lo + (size_t)k * nl, ma, sizeof(double) * nl);
+        if (mean_b_lo) memcpy(mean_b_lo + (size_t)k * nl, mb, sizeof(double) * nl);
+    }
+done:
+    free(Il); free(pl); free(a); free(b); free(ma); free(mb); free(ua); free(ub);
+    return rc;
+}

@@ -1,0 +1,209 @@
+"""ctypes wrapper around the FP64 CPU oracle (``gf_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
+and by the CPU-baseline leg of ``bench.py``.  The product path (the HIP
+library and its binding) never imports this module.
+
+Inputs are numpy arrays; they are converted to contiguous float64 (an exact
+upcast for float32, float16 and bfloat16 values) before the call.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "gf_oracle.c")
+LIB = os.path.join(_HERE, "liboracle.so")
+
+NEAREST = 0
+BILINEAR = 1
+_MODES = {"nearest": NEAREST, "bilinear": BILINEAR, NEAREST: NEAREST, BILINEAR: BILINEAR}
+
+# IEEE double arithmetic as written: no fast-math, no FMA contraction.
+CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off"]
+
+
+def build(out: str = LIB, src: str = SRC) -> str:
+    """Compile the oracle with gcc into a shared library (always recompiles)."""
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def _f64(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x), dtype=np.float64)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_DP)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"{what} failed with code {rc}")
+
+
+class Oracle:
+    """One loaded copy of the oracle library."""
+
+    def __init__(self, libpath: str = LIB):
+        lib = ctypes.CDLL(libpath)
+        i, d = ctypes.c_int, ctypes.c_double
+        sig = {
+            "oracle_lowres_radius": [i, i],
+            "oracle_lowres_size": [i, i],
+            "oracle_box_mean": [_DP, i, i, i, _DP],
+            "oracle_subsample": [_DP, i, i, i, i, _DP],
+            "oracle_upsample": [_DP, i, i, i, i, i, _DP],
+            "oracle_coefficients": [_DP, _DP, i, i, i, d, _DP, _DP],
+            "oracle_guided_filter": [_DP, _DP, i, i, i, i, d, _DP, _DP, _DP, _DP, _DP],
+            "oracle_fast_guided_filter": [_DP, _DP, i, i, i, i, i, d, i, _DP, _DP, _DP, _DP, _DP],
+        }
+        for name, args in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        self.lib = lib
+        self.path = libpath
+
+    def lowres_radius(self, r: int, s: int) -> int:
+        """r' = r/s rounded half up (at least 1 when r > 0)."""
+        return int(self.lib.oracle_lowres_radius(int(r), int(s)))
+
+    def lowres_size(self, n: int, s: int) -> int:
+        return int(self.lib.oracle_lowres_size(int(n), int(s)))
+
+    def box_mean(self, x, r: int) -> np.ndarray:
+        """Clip-normalised (2r+1)^2 box mean of a 2-D array."""
+        x = _f64(x)
+        h, w = x.shape
+        out = np.empty_like(x)
+        _check(self.lib.oracle_box_mean(_ptr(x), h, w, int(r), _ptr(out)), "oracle_box_mean")
+        return out
+
+    def subsample(self, x, s: int, mode="nearest") -> np.ndarray:
+        x = _f64(x)
+        h, w = x.shape
+        out = np.empty((self.lowres_size(h, s), self.lowres_size(w, s)))
+        _check(self.lib.oracle_subsample(_ptr(x), h, w, int(s), _MODES[mode], _ptr(out)),
+               "oracle_subsample")
+        return out
+
+    def upsample(self, lo, s: int, h: int, w: int) -> np.ndarray:
+        lo = _f64(lo)
+        hl, wl = lo.shape
+        out = np.empty((h, w))
+        _check(self.lib.oracle_upsample(_ptr(lo), hl, wl, int(s), h, w, _ptr(out)),
+               "oracle_upsample")
+        return out
+
+    def coefficients(self, I, p, r: int, eps: float):
+        """a, b of Eqs. 2-3 for a single-channel p (Algorithm 1 steps 1-3)."""
+        I, p = _f64(I), _f64(p)
+        h, w = I.shape
+        assert p.shape == (h, w)
+        a, b = np.empty_like(I), np.empty_like(I)
+        _check(self.lib.oracle_coefficients(_ptr(I), _ptr(p), h, w, int(r), float(eps),
+                                            _ptr(a), _ptr(b)), "oracle_coefficients")
+        return a, b
+
+    @staticmethod
+    def _as_chw(p, h, w):
+        p = _f64(p)
+        if p.ndim == 2:
+            return np.ascontiguousarray(p.reshape(1, h, w)), True
+        assert p.ndim == 3 and p.shape[1:] == (h, w), p.shape
+        return p, False
+
+    def guided_filter(self, I, p, r: int, eps: float, intermediates: bool = False):
+        """Algorithm 1.  ``I`` is (h, w); ``p`` is (h, w) or (c, h, w).
+
+        Returns q shaped like p, or (q, {a, b, mean_a, mean_b}).
+        """
+        I = _f64(I)
+        h, w = I.shape
+        p3, squeeze = self._as_chw(p, h, w)
+        c = p3.shape[0]
+        q = np.empty_like(p3)
+        ex = ({k: np.empty_like(p3) for k in ("a", "b", "mean_a", "mean_b")}
+              if intermediates else {})
+        _check(self.lib.oracle_guided_filter(
+            _ptr(I), _ptr(p3), c, h, w, int(r), float(eps), _ptr(q),
+            _ptr(ex.get("a")), _ptr(ex.get("b")), _ptr(ex.get("mean_a")),
+            _ptr(ex.get("mean_b"))), "oracle_guided_filter")
+        if squeeze:
+            q, ex = q[0], {k: v[0] for k, v in ex.items()}
+        return (q, ex) if intermediates else q
+
+    def fast_guided_filter(self, I, p, r: int, s: int, eps: float, mode="nearest",
+                           intermediates: bool = False):
+        """Algorithm 2.  Low-resolution intermediates (a, b, mean_a, mean_b)
+        come back at ceil(h/s) x ceil(w/s) when ``intermediates`` is set."""
+        I = _f64(I)
+        h, w = I.shape
+        p3, squeeze = self._as_chw(p, h, w)
+        c = p3.shape[0]
+        hl, wl = self.lowres_size(h, s), self.lowres_size(w, s)
+        q = np.empty_like(p3)
+        ex = ({k: np.empty((c, hl, wl)) for k in ("a", "b", "mean_a", "mean_b")}
+              if intermediates else {})
+        _check(self.lib.oracle_fast_guided_filter(
+            _ptr(I), _ptr(p3), c, h, w, int(r), int(s), float(eps), _MODES[mode], _ptr(q),
+            _ptr(ex.get("a")), _ptr(ex.get("b")), _ptr(ex.get("mean_a")),
+            _ptr(ex.get("mean_b"))), "oracle_fast_guided_filter")
+        if squeeze:
+            q, ex = q[0], {k: v[0] for k, v in ex.items()}
+        return (q, ex) if intermediates else q
+
+
+_default: Oracle | None = None
+
+
+def default() -> Oracle:
+    """The oracle built from ``gf_oracle.c`` (compiled here if absent or stale)."""
+    global _default
+    if _default is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        _default = Oracle(LIB)
+    return _default
+
+
+def lowres_radius(r, s):
+    return default().lowres_radius(r, s)
+
+
+def lowres_size(n, s):
+    return default().lowres_size(n, s)
+
+
+def box_mean(x, r):
+    return default().box_mean(x, r)
+
+
+def subsample(x, s, mode="nearest"):
+    return default().subsample(x, s, mode)
+
+
+def upsample(lo, s, h, w):
+    return default().upsample(lo, s, h, w)
+
+
+def coefficients(I, p, r, eps):
+    return default().coefficients(I, p, r, eps)
+
+
+def guided_filter(I, p, r, eps, intermediates=False):
+    return default().guided_filter(I, p, r, eps, intermediates)
+
+
+def fast_guided_filter(I, p, r, s, eps, mode="nearest", intermediates=False):
+    return default().fast_guided_filter(I, p, r, s, eps, mode, intermediates)

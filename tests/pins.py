@@ -1,0 +1,376 @@
+"""Pins for the FP64 oracle: checks against things other than the oracle itself.
+
+Each ``pin_*`` takes a loaded oracle (``oracle.oracle.Oracle``) and raises
+AssertionError when the oracle disagrees with:
+  * brute-force window loops on tiny images (dyadic values make the sums exact),
+  * library routines for the special cases they cover (scipy's uniform filter,
+    torch's interpolate, numpy's least-squares solver),
+  * closed-form consequences of the local linear model (Eqs. 1-4).
+
+The same pins run against the real oracle (tests/test_oracle.py) and against
+deliberately broken copies of it (tests/test_oracle_mutants.py), which shows
+that a plausible slip anywhere in the oracle fails at least one of them.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.ndimage as ndi
+import torch
+import torch.nn.functional as F
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _dyadic(g, shape):
+    return g.integers(0, 257, size=shape).astype(np.float64) / 256.0
+
+
+def _close(got, exp, tol, what):
+    got, exp = np.asarray(got), np.asarray(exp)
+    assert got.shape == exp.shape, f"{what}: shape {got.shape} != {exp.shape}"
+    err = float(np.max(np.abs(got - exp))) if got.size else 0.0
+    assert np.all(np.isfinite(got)), f"{what}: non-finite values"
+    assert err <= tol, f"{what}: max abs err {err:.3e} > {tol:.1e}"
+
+
+def _window(n, i, r):
+    return max(0, i - r), min(n - 1, i + r)
+
+
+def scipy_box(x, r):
+    """Clip-normalised box mean from scipy's zero-padded uniform filter."""
+    x = np.asarray(x, dtype=np.float64)
+    size = 2 * r + 1
+    num = ndi.uniform_filter(x, size=size, mode="constant", cval=0.0)
+    den = ndi.uniform_filter(np.ones_like(x), size=size, mode="constant", cval=0.0)
+    return num / den
+
+
+def torch_nearest_sub(x, s):
+    """torch 'nearest-exact' downscale by s (sizes divisible by s)."""
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64))[None, None]
+    h, w = x.shape
+    return F.interpolate(t, size=(h // s, w // s), mode="nearest-exact")[0, 0].numpy()
+
+
+def torch_bilinear_sub(x, s):
+    """torch bilinear downscale by s, half-pixel centres, no antialias (s | h, w)."""
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64))[None, None]
+    h, w = x.shape
+    return F.interpolate(t, size=(h // s, w // s), mode="bilinear", align_corners=False,
+                         antialias=False)[0, 0].numpy()
+
+
+def torch_upsample(lo, s, h, w):
+    """torch bilinear upscale by exactly s (half-pixel centres), cropped to h x w."""
+    t = torch.from_numpy(np.ascontiguousarray(lo, dtype=np.float64))[None, None]
+    up = F.interpolate(t, scale_factor=float(s), mode="bilinear", align_corners=False,
+                       recompute_scale_factor=False)[0, 0].numpy()
+    return up[:h, :w]
+
+
+def torch_sub(x, s, mode):
+    """Subsample by s via torch on the largest divisible crop, then fill the
+    ragged last row/column by the same rule applied to the clamped index."""
+    h, w = x.shape
+    hl, wl = -(-h // s), -(-w // s)
+    out = np.empty((hl, wl))
+    hd, wd = (h // s) * s, (w // s) * s
+    if hd and wd:
+        out[: h // s, : w // s] = (torch_nearest_sub if mode == "nearest" else torch_bilinear_sub)(
+            x[:hd, :wd], s)
+    # Ragged border: pad by edge replication to a divisible size and let torch
+    # sample it; replication is what clamping taps to the image means.
+    xp = np.pad(x, ((0, hl * s - h), (0, wl * s - w)), mode="edge")
+    full = (torch_nearest_sub if mode == "nearest" else torch_bilinear_sub)(xp, s)
+    out[h // s:, :] = full[h // s:, :]
+    out[:, w // s:] = full[:, w // s:]
+    return out
+
+
+def composed_fast(I, p, r, s, eps, mode):
+    """Algorithm 2 assembled from library primitives: torch subsample, scipy
+    box means, numpy elementwise steps, torch upsample."""
+    h, w = I.shape
+    rl = 0 if r == 0 else max(1, int(math.floor(r / s + 0.5)))
+    Il, pl = torch_sub(I, s, mode), torch_sub(p, s, mode)
+    mI, mp = scipy_box(Il, rl), scipy_box(pl, rl)
+    cI, cIp = scipy_box(Il * Il, rl), scipy_box(Il * pl, rl)
+    a = (cIp - mI * mp) / (cI - mI * mI + eps)
+    b = mp - a * mI
+    ua = torch_upsample(scipy_box(a, rl), s, h, w)
+    ub = torch_upsample(scipy_box(b, rl), s, h, w)
+    return ua * I + ub
+
+
+# ---------------------------------------------------------------- pins
+
+def pin_lowres_rules(orc):
+    """r' = r/s rounded half up (min 1 for r>0) and ceil(n/s) sizes."""
+    table = {(8, 4): 2, (16, 4): 4, (32, 8): 4, (10, 4): 3, (3, 8): 1, (0, 4): 0, (5, 1): 5,
+             (60, 4): 15, (4, 4): 1, (2, 4): 1, (6, 4): 2, (1, 1): 1, (7, 2): 4, (9, 8): 1}
+    for (r, s), exp in table.items():
+        assert orc.lowres_radius(r, s) == exp, (r, s, orc.lowres_radius(r, s), exp)
+    for n, s, exp in [(512, 4, 128), (3000, 4, 750), (10, 4, 3), (1, 8, 1), (9, 8, 2), (7, 1, 7)]:
+        assert orc.lowres_size(n, s) == exp, (n, s)
+
+
+def pin_box_bruteforce(orc):
+    """Box mean equals the literal clipped-window average (bit-exact on k/256 data)."""
+    g = _rng(11)
+    for h, w in [(1, 1), (1, 7), (6, 1), (3, 5), (8, 8), (12, 9), (5, 12)]:
+        x = _dyadic(g, (h, w))
+        for r in [0, 1, 2, 3, 6, 13]:
+            exp = np.empty_like(x)
+            for y in range(h):
+                y0, y1 = _window(h, y, r)
+                for xx in range(w):
+                    x0, x1 = _window(w, xx, r)
+                    blk = x[y0:y1 + 1, x0:x1 + 1]
+                    exp[y, xx] = blk.sum() / blk.size
+            got = orc.box_mean(x, r)
+            assert np.array_equal(got, exp), (h, w, r, np.max(np.abs(got - exp)))
+
+
+def pin_box_scipy(orc):
+    """Box mean equals scipy's zero-padded uniform filter normalised by that of ones."""
+    g = _rng(12)
+    x = g.uniform(-1, 2, size=(41, 57))
+    for r in [0, 1, 3, 10, 30, 70]:
+        _close(orc.box_mean(x, r), scipy_box(x, r), 1e-12, f"box r={r}")
+
+
+def pin_coefficients_lstsq(orc):
+    """a_k, b_k minimise sum_{i in w_k} (a I_i + b - p_i)^2 + |w_k| eps a^2
+    (the ridge regression whose normal equations are Eqs. 2-3)."""
+    g = _rng(13)
+    h, w = 9, 11
+    I = g.uniform(0, 1, size=(h, w))
+    p = 0.7 * I + g.uniform(0, 0.5, size=(h, w))
+    for r, eps in [(1, 1e-2), (2, 0.3), (4, 1e-3)]:
+        a, b = orc.coefficients(I, p, r, eps)
+        for ky in range(h):
+            y0, y1 = _window(h, ky, r)
+            for kx in range(w):
+                x0, x1 = _window(w, kx, r)
+                Iw = I[y0:y1 + 1, x0:x1 + 1].ravel()
+                pw = p[y0:y1 + 1, x0:x1 + 1].ravel()
+                n = Iw.size
+                A = np.vstack([np.stack([Iw, np.ones(n)], 1), [[math.sqrt(n * eps), 0.0]]])
+                rhs = np.concatenate([pw, [0.0]])
+                sol = np.linalg.lstsq(A, rhs, rcond=None)[0]
+                assert abs(a[ky, kx] - sol[0]) < 1e-10, (r, eps, ky, kx, a[ky, kx], sol[0])
+                assert abs(b[ky, kx] - sol[1]) < 1e-10, (r, eps, ky, kx, b[ky, kx], sol[1])
+
+
+def pin_eq4_average(orc):
+    """Eq. 4: mean_a(i), mean_b(i) average a_k, b_k over every window k that
+    contains i, and q_i = mean_a(i) I_i + mean_b(i)."""
+    g = _rng(14)
+    h, w, r, eps = 7, 10, 2, 0.05
+    I = g.uniform(0, 1, size=(h, w))
+    p = g.uniform(0, 1, size=(2, h, w))
+    q, ex = orc.guided_filter(I, p, r, eps, intermediates=True)
+    for c in range(2):
+        a, b = orc.coefficients(I, p[c], r, eps)
+        _close(ex["a"][c], a, 0.0, "a")
+        for iy in range(h):
+            for ix in range(w):
+                ks = [(ky, kx) for ky in range(h) for kx in range(w)
+                      if abs(ky - iy) <= r and abs(kx - ix) <= r]
+                ma = sum(a[k] for k in ks) / len(ks)
+                mb = sum(b[k] for k in ks) / len(ks)
+                assert abs(ex["mean_a"][c, iy, ix] - ma) < 1e-13
+                assert abs(ex["mean_b"][c, iy, ix] - mb) < 1e-13
+                assert abs(q[c, iy, ix] - (ma * I[iy, ix] + mb)) < 1e-13
+
+
+def pin_subsample_torch(orc):
+    """Nearest = torch 'nearest-exact' (index s*y + floor(s/2)); bilinear =
+    torch bilinear without antialias; ragged borders clamp to the image."""
+    g = _rng(15)
+    for h, w in [(16, 24), (13, 10), (9, 17), (1, 9)]:
+        x = g.uniform(0, 1, size=(h, w))
+        for s in [1, 2, 3, 4, 5, 8]:
+            for mode in ("nearest", "bilinear"):
+                _close(orc.subsample(x, s, mode), torch_sub(x, s, mode), 1e-15,
+                       f"subsample {mode} s={s} {h}x{w}")
+
+
+def pin_upsample_torch(orc):
+    """Upsample = torch bilinear x s (half-pixel centres), cropped to h x w."""
+    g = _rng(16)
+    for (h, w), s in [((16, 12), 4), ((10, 7), 4), ((9, 13), 2), ((11, 6), 3), ((17, 8), 8),
+                      ((1, 10), 4), ((5, 5), 1)]:
+        lo = g.uniform(-1, 1, size=(-(-h // s), -(-w // s)))
+        _close(orc.upsample(lo, s, h, w), torch_upsample(lo, s, h, w), 1e-14,
+               f"upsample s={s} {h}x{w}")
+
+
+def pin_composition(orc):
+    """The whole fast filter equals Algorithm 2 assembled from library routines."""
+    g = _rng(17)
+    for (h, w), r, s, eps, mode in [((37, 45), 8, 4, 1e-2, "nearest"),
+                                    ((37, 45), 8, 4, 1e-2, "bilinear"),
+                                    ((30, 21), 5, 2, 1e-3, "nearest"),
+                                    ((29, 33), 6, 3, 1e-1, "bilinear"),
+                                    ((40, 40), 3, 1, 1e-2, "nearest")]:
+        I = g.uniform(0, 1, size=(h, w))
+        p = np.clip(I + g.normal(0, 0.1, size=(h, w)), 0, 1)
+        _close(orc.fast_guided_filter(I, p, r, s, eps, mode), composed_fast(I, p, r, s, eps, mode),
+               1e-11, f"fast {h}x{w} r={r} s={s} {mode}")
+
+
+def pin_bruteforce_eqs(orc):
+    """Eqs. 2-4 by explicit per-window loops (no box filter) on tiny images."""
+    g = _rng(18)
+    h, w, r, eps = 6, 8, 2, 0.02
+    I = g.uniform(0, 1, size=(h, w))
+    p = g.uniform(0, 1, size=(h, w))
+    a = np.empty((h, w))
+    b = np.empty((h, w))
+    for ky in range(h):
+        for kx in range(w):
+            pts = [(y, x) for y in range(h) for x in range(w) if abs(y - ky) <= r and abs(x - kx) <= r]
+            n = len(pts)
+            mu = sum(I[t] for t in pts) / n
+            pbar = sum(p[t] for t in pts) / n
+            var = sum((I[t] - mu) ** 2 for t in pts) / n
+            a[ky, kx] = (sum(I[t] * p[t] for t in pts) / n - mu * pbar) / (var + eps)
+            b[ky, kx] = pbar - a[ky, kx] * mu
+    q = np.empty((h, w))
+    for iy in range(h):
+        for ix in range(w):
+            ks = [(y, x) for y in range(h) for x in range(w) if abs(y - iy) <= r and abs(x - ix) <= r]
+            q[iy, ix] = sum(a[k] * I[iy, ix] + b[k] for k in ks) / len(ks)
+    _close(orc.guided_filter(I, p, r, eps), q, 1e-13, "brute-force Eqs. 2-4")
+
+
+def pin_constant_input(orc):
+    """p constant => q equals that constant (a = 0, b = p)."""
+    g = _rng(19)
+    I = g.uniform(0, 1, size=(23, 31))
+    for cval, tol in [(0.5, 0.0), (0.3, 1e-15)]:
+        p = np.full_like(I, cval)
+        _close(orc.guided_filter(I, p, 4, 1e-3), p, tol, "plain const p")
+        for mode in ("nearest", "bilinear"):
+            _close(orc.fast_guided_filter(I, p, 8, 4, 1e-3, mode), p, tol, "fast const p")
+
+
+def pin_constant_guide(orc):
+    """I constant => var = cov = 0, a = 0, and q = up(B(B(p'))): the input
+    box-filtered twice at the low-res radius, then upsampled."""
+    g = _rng(20)
+    h, w = 26, 35
+    I = np.full((h, w), 0.5)
+    p = g.uniform(0, 1, size=(h, w))
+    _, ex = orc.guided_filter(I, p, 3, 1e-3, intermediates=True)
+    assert np.all(ex["a"] == 0.0)
+    _close(orc.guided_filter(I, p, 3, 1e-3), scipy_box(scipy_box(p, 3), 3), 1e-14, "plain const I")
+    for s, r, mode in [(4, 8, "nearest"), (2, 3, "bilinear"), (3, 7, "nearest")]:
+        rl = max(1, int(math.floor(r / s + 0.5)))
+        exp = torch_upsample(scipy_box(scipy_box(torch_sub(p, s, mode), rl), rl), s, h, w)
+        _close(orc.fast_guided_filter(I, p, r, s, 1e-3, mode), exp, 1e-14, f"fast const I s={s}")
+
+
+def pin_fast_s1_is_plain(orc):
+    """At s = 1 subsample and upsample are identities: fast == plain bit for bit."""
+    g = _rng(21)
+    I = g.uniform(0, 1, size=(19, 27))
+    p = g.uniform(0, 1, size=(3, 19, 27))
+    for mode in ("nearest", "bilinear"):
+        assert np.array_equal(orc.fast_guided_filter(I, p, 4, 1, 1e-2, mode),
+                              orc.guided_filter(I, p, 4, 1e-2))
+
+
+def pin_r0_identity(orc):
+    """r = 0: every window is one pixel, var = cov = 0, so q = p exactly."""
+    g = _rng(22)
+    I = g.uniform(0, 1, size=(9, 14))
+    p = g.uniform(0, 1, size=(9, 14))
+    assert np.array_equal(orc.guided_filter(I, p, 0, 1e-3), p)
+    assert np.array_equal(orc.fast_guided_filter(I, p, 0, 1, 1e-3), p)
+
+
+def pin_linearity(orc):
+    """q is linear in p: q(al p1 + be p2) = al q(p1) + be q(p2)."""
+    g = _rng(23)
+    I = g.uniform(0, 1, size=(33, 29))
+    p1, p2 = g.uniform(0, 1, size=(2, 33, 29))
+    lhs = orc.fast_guided_filter(I, 0.7 * p1 - 1.3 * p2, 6, 2, 1e-2, "bilinear")
+    rhs = 0.7 * orc.fast_guided_filter(I, p1, 6, 2, 1e-2, "bilinear") - 1.3 * orc.fast_guided_filter(
+        I, p2, 6, 2, 1e-2, "bilinear")
+    _close(lhs, rhs, 1e-13, "linearity")
+
+
+def pin_offset(orc):
+    """q(I, p + c) = q(I, p) + c (needs the clip normalisation to be a mean)."""
+    g = _rng(24)
+    I = g.uniform(0, 1, size=(31, 22))
+    p = g.uniform(0, 1, size=(31, 22))
+    _close(orc.guided_filter(I, p + 0.25, 5, 1e-2), orc.guided_filter(I, p, 5, 1e-2) + 0.25,
+           1e-14, "offset plain")
+    _close(orc.fast_guided_filter(I, p + 0.25, 9, 4, 1e-2),
+           orc.fast_guided_filter(I, p, 9, 4, 1e-2) + 0.25, 1e-14, "offset fast")
+
+
+def pin_guide_shift_scale(orc):
+    """q(I + c, p) = q(I, p); q(2 I, p; 4 eps) = q(I, p; eps) bit for bit."""
+    g = _rng(25)
+    I = g.uniform(0, 1, size=(27, 30))
+    p = g.uniform(0, 1, size=(27, 30))
+    base = orc.fast_guided_filter(I, p, 6, 2, 1e-2)
+    _close(orc.fast_guided_filter(I + 0.375, p, 6, 2, 1e-2), base, 1e-13, "guide shift")
+    assert np.array_equal(orc.fast_guided_filter(2 * I, p, 6, 2, 4e-2), base)
+    assert np.array_equal(orc.guided_filter(2 * I, p, 3, 4e-2), orc.guided_filter(I, p, 3, 1e-2))
+
+
+def pin_affine_reproduction(orc):
+    """Eq. 1: if p = al I + be and eps -> 0 (no flat window), a = al and
+    b = be everywhere, so q = al I + be for the plain and the fast filter
+    (the output uses the full-resolution I)."""
+    g = _rng(26)
+    I = g.uniform(0, 1, size=(41, 38))
+    p = 0.8 * I + 0.1
+    _close(orc.guided_filter(I, p, 3, 1e-14), p, 1e-8, "affine plain")
+    for s, mode in [(4, "nearest"), (2, "bilinear"), (3, "nearest")]:
+        _close(orc.fast_guided_filter(I, p, 8, s, 1e-14, mode), p, 1e-8, f"affine fast s={s}")
+
+
+def pin_large_eps(orc):
+    """eps -> infinity: a -> 0 and q -> up(B(B(p'))) as for a constant guide."""
+    g = _rng(27)
+    h, w = 24, 28
+    I = g.uniform(0, 1, size=(h, w))
+    p = g.uniform(0, 1, size=(h, w))
+    exp = torch_upsample(scipy_box(scipy_box(torch_sub(p, 4, "nearest"), 2), 2), 4, h, w)
+    _close(orc.fast_guided_filter(I, p, 8, 4, 1e30), exp, 1e-12, "large eps")
+
+
+def pin_transpose(orc):
+    """Transposing I and p transposes q."""
+    g = _rng(28)
+    I = g.uniform(0, 1, size=(21, 34))
+    p = g.uniform(0, 1, size=(21, 34))
+    for s, mode in [(1, "nearest"), (4, "nearest"), (2, "bilinear")]:
+        _close(orc.fast_guided_filter(I.T, p.T, 7, s, 1e-2, mode),
+               orc.fast_guided_filter(I, p, 7, s, 1e-2, mode).T, 1e-14, f"transpose s={s}")
+
+
+def pin_degenerate_shapes(orc):
+    """1xN, Nx1, sizes not divisible by s, and r' larger than the low-res map."""
+    g = _rng(29)
+    for (h, w), r, s, mode in [((1, 37), 4, 4, "nearest"), ((29, 1), 6, 2, "bilinear"),
+                               ((7, 9), 40, 4, "nearest"), ((3, 3), 9, 8, "bilinear"),
+                               ((13, 18), 5, 3, "nearest"), ((1, 1), 2, 4, "nearest")]:
+        I = g.uniform(0, 1, size=(h, w))
+        p = g.uniform(0, 1, size=(h, w))
+        _close(orc.fast_guided_filter(I, p, r, s, 1e-2, mode), composed_fast(I, p, r, s, 1e-2, mode),
+               1e-11, f"degenerate {h}x{w} r={r} s={s}")
+
+
+ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

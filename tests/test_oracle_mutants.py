@@ -1,0 +1,60 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case copies ``oracle/gf_oracle.c``, makes one plausible slip in the copy
+(a dropped term, a wrong sign, an off-by-one window, a swapped operand, a
+wrong sampling index), builds it with gcc in a temporary directory, and runs
+every pin against it: at least one pin has to fail.  The real oracle source
+is never modified.  CPU only.
+"""
+import os
+
+import pytest
+
+import pins
+from oracle import oracle
+
+MUTANTS = {
+    "count_off_by_one": ("(double)(y1 - y0 + 1) * (double)(x1 - x0 + 1)",
+                         "(double)(y1 - y0 + 2) * (double)(x1 - x0 + 1)"),
+    "window_too_narrow": ("k <= imin(w - 1, xx + r); ++k", "k <= imin(w - 1, xx + r - 1); ++k"),
+    "row_window_unclipped_low": ("int y0 = imax(0, y - r), y1", "int y0 = imax(1, y - r), y1"),
+    "variance_sign": ("corr_I[i] - mean_I[i] * mean_I[i]", "corr_I[i] + mean_I[i] * mean_I[i]"),
+    "covariance_wrong_mean": ("corr_Ip[i] - mean_I[i] * mean_p[i]", "corr_Ip[i] - mean_I[i] * mean_I[i]"),
+    "eps_halved": ("cov_Ip / (var_I + eps)", "cov_Ip / (var_I + 0.5 * eps)"),
+    "b_sign": ("mean_p[i] - a[i] * mean_I[i]", "mean_p[i] + a[i] * mean_I[i]"),
+    "corr_Ip_is_corr_I": ("tmp[i] = I[i] * p[i]", "tmp[i] = I[i] * I[i]"),
+    "mean_b_from_a": ("oracle_box_mean(b, h, w, r, mb)", "oracle_box_mean(a, h, w, r, mb)"),
+    "plain_output_swapped": ("qk[i] = ma[i] * I[i] + mb[i]", "qk[i] = mb[i] * I[i] + ma[i]"),
+    "fast_uses_full_radius": ("oracle_coefficients(Il, pl, hl, wl, rl, eps, a, b)",
+                              "oracle_coefficients(Il, pl, hl, wl, r, eps, a, b)"),
+    "fast_skips_coefficient_mean": ("oracle_box_mean(a, hl, wl, rl, ma)", "oracle_box_mean(a, hl, wl, 0, ma)"),
+    "lowres_radius_truncates": ("int rl = (2 * r + s) / (2 * s);", "int rl = r / s;"),
+    "nearest_top_left": ("*t0 = imin(s * j + s / 2, n - 1);", "*t0 = imin(s * j, n - 1);"),
+    "bilinear_centre": ("double u = (double)s * j + 0.5 * (double)(s - 1);",
+                        "double u = (double)s * j + 0.5 * (double)s;"),
+    "upsample_no_half_pixel": ("double u = ((double)y + 0.5) / (double)s - 0.5;",
+                               "double u = (double)y / (double)s;"),
+    "upsample_axes_swapped": ("(1.0 - wy) * ((1.0 - wx) * v00 + wx * v01) + wy * ((1.0 - wx) * v10 + wx * v11);\n        }\n    }\n    return 0;\n}\n\n/*\n * Algorithm 1",
+                              "(1.0 - wx) * ((1.0 - wy) * v00 + wy * v01) + wx * ((1.0 - wy) * v10 + wy * v11);\n        }\n    }\n    return 0;\n}\n\n/*\n * Algorithm 1"),
+    "upsample_wrong_tap": ("int ya = iclamp((int)fu, 0, hl - 1)", "int ya = iclamp((int)fu + 1, 0, hl - 1)"),
+    "fast_output_uses_mean_b_twice": ("qk[i] = ua[i] * I[i] + ub[i]", "qk[i] = ub[i] * I[i] + ub[i]"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(oracle.SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
+    mpath = os.path.join(tmp_path, "mutant.c")
+    with open(mpath, "w") as f:
+        f.write(src.replace(old, new))
+    lib = oracle.build(os.path.join(tmp_path, "libmutant.so"), mpath)
+    orc = oracle.Oracle(lib)
+    failed = []
+    for pin in pins.ALL_PINS:
+        try:
+            pin(orc)
+        except (AssertionError, RuntimeError, ValueError, FloatingPointError):
+            failed.append(pin.__name__)
+    assert failed, f"mutant {name} passed every pin"
