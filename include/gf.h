@@ -1,0 +1,221 @@
+/*
+ * gf.h - C ABI of the MI355X (gfx950) guided-filter library, libgf.so.
+ *
+ * Implements the guided filter and the Fast Guided Filter of
+ * K. He and J. Sun, "Fast Guided Filter", arXiv 1505.00996:
+ *   - gf_plain : Algorithm 1 (Eqs. 2-4): four box means of I, p, I*I, I*p at
+ *                radius r, the coefficients a = cov(I,p)/(var(I)+eps) and
+ *                b = mean(p) - a mean(I), their box means, q = mean_a*I + mean_b.
+ *   - gf_fast  : Algorithm 2: the same steps on I and p subsampled by s at
+ *                radius r/s, with mean_a and mean_b bilinearly upsampled and
+ *                applied to the full-resolution guide I (Sec. 2).
+ *   - gf_fast_batched : Algorithm 2 for many images of different sizes in one
+ *                launch.
+ *   - gf_submit / gf_poll : an asynchronous request interface that batches the
+ *                requests in flight (same result as gf_fast per request).
+ *
+ * Conventions (where the paper leaves a choice):
+ *   - window of radius r = (2r+1)x(2r+1) square; box means are taken over the
+ *     part of the window inside the image and divided by its pixel count
+ *     (GF_BORDER_CLIP), which makes Eq. 4's "average over the windows that
+ *     contain pixel i" a box mean;
+ *   - variance is the population variance mean(I*I) - mean(I)^2, clamped at 0;
+ *   - r' = r/s rounded half up, at least 1 when r > 0;
+ *   - the low-resolution maps are ceil(h/s) x ceil(w/s);
+ *   - GF_SUB_NEAREST takes full-res pixel s*y + floor(s/2) (clamped);
+ *     GF_SUB_BILINEAR samples the low-res pixel centre s*y + (s-1)/2 with two
+ *     clamped taps per axis (no antialias prefilter);
+ *   - upsampling is bilinear with half-pixel centres, u = (y+0.5)/s - 0.5,
+ *     taps clamped to the low-res map;
+ *   - a multi-channel p is filtered channel by channel with the same gray I.
+ *
+ * Arithmetic: all window sums, coefficients and interpolation in FP32
+ * (window sums of mean-shifted values, tile by tile); images may be stored as
+ * FP32, FP16 or BF16, and 16-bit outputs are rounded to nearest even.
+ *
+ * Memory and ownership: every image pointer is DEVICE memory owned by the
+ * caller, which keeps it alive and unmodified until the work has completed
+ * (stream order for gf_plain/gf_fast/gf_fast_batched; a terminal gf_poll for
+ * gf_submit).  The library only owns workspace: either the caller passes one
+ * (device memory of at least the size the *_workspace_bytes call returns) or,
+ * with workspace == NULL, the context's own buffer is used.  Calls that share
+ * one context's buffer must not overlap on different streams.
+ *
+ * Errors: status codes only.  Arguments are validated on the host before any
+ * HIP call; an invalid call returns GF_EINVAL (or GF_ENOTSUP) and launches
+ * nothing.  gf_last_error() returns a message for the last failing call on
+ * the calling thread.  Launch failures return GF_EDEVICE; faults inside a
+ * kernel surface at the next synchronisation of the stream.
+ *
+ * Every entry point may be called with ctx == NULL except gf_submit and
+ * gf_poll; it then runs on the current HIP device and needs an explicit
+ * workspace.
+ */
+#ifndef GF_H
+#define GF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GF_OK = 0,
+    GF_PENDING = 1,     /* gf_poll: the request has not finished yet */
+    GF_EINVAL = -1,     /* invalid argument, shape, stride, aliasing or ticket */
+    GF_ENOMEM = -2,     /* workspace too small, or the request can never fit the arena */
+    GF_EBUSY = -3,      /* request queue full; try again after polling */
+    GF_ENOTSUP = -4,    /* valid but unsupported option (border, radius too large) */
+    GF_EDEVICE = -5,    /* a HIP call failed */
+    GF_ETIMEDOUT = -6   /* gf_poll: wait time elapsed */
+} gf_status;
+
+typedef enum { GF_F32 = 0, GF_F16 = 1, GF_BF16 = 2 } gf_dtype;
+
+typedef enum {
+    GF_BORDER_CLIP = 0  /* window clipped to the image, mean over in-image pixels */
+} gf_border;
+
+typedef enum { GF_SUB_NEAREST = 0, GF_SUB_BILINEAR = 1 } gf_subsample;
+
+/*
+ * A c x h x w image in device memory.  Element (k, y, x) is at
+ * data + k*plane_stride + y*row_stride + x, strides counted in ELEMENTS.
+ * Requirements: c >= 1, h >= 1, w >= 1, row_stride >= w,
+ * plane_stride >= h*row_stride when c > 1.  For I, c must be 1.
+ */
+typedef struct {
+    void *data;
+    gf_dtype dtype;
+    int32_t c, h, w;
+    int64_t row_stride;
+    int64_t plane_stride;
+} gf_image;
+
+/* Filter parameters: full-resolution radius r >= 0, subsampling ratio
+ * s >= 1 (s = 1 is Algorithm 1), regulariser eps > 0 and finite (in units of
+ * I^2), border convention, subsampling kind. */
+typedef struct {
+    int32_t r;
+    int32_t s;
+    double eps;
+    gf_border border;
+    gf_subsample sub;
+} gf_params;
+
+/* Per-request timestamps (seconds on the host's monotonic clock). */
+typedef struct {
+    double t_submit;  /* gf_submit accepted the request */
+    double t_admit;   /* workspace reserved and work queued for launch */
+    double t_start;   /* the launch carrying the request was issued */
+    double t_done;    /* completion observed by the library */
+} gf_req_stats;
+
+typedef struct gf_ctx gf_ctx;
+
+/* Create a context on HIP device `device`.  `arena_bytes` of device memory
+ * are reserved for requests of gf_submit (0 = no request interface);
+ * `max_inflight` bounds the requests held at once (queued or running).
+ * Ownership: the context is released with gf_ctx_destroy, which waits for
+ * the work it launched. */
+gf_status gf_ctx_create(gf_ctx **out, int device, size_t arena_bytes, int max_inflight);
+void gf_ctx_destroy(gf_ctx *ctx);
+
+/* Message of the last failing call on this thread (never NULL). */
+const char *gf_last_error(const gf_ctx *ctx);
+
+/* Device workspace (bytes) gf_fast needs for an h x w image with c channels
+ * of p: 4c low-resolution FP32 maps (a, b and their box means).  Returns 0
+ * for invalid arguments. */
+size_t gf_workspace_bytes(int32_t h, int32_t w, int32_t c, const gf_params *params);
+
+/*
+ * Algorithm 1 (guided filter) at full resolution: q = mean_a .* I + mean_b.
+ * I: 1 x h x w; p, q: c x h x w; all three of one dtype; q must not overlap
+ * I or p.  Enqueued on `hip_stream` (a hipStream_t; NULL = default stream);
+ * returns after enqueue.  workspace: device memory of at least
+ * gf_workspace_bytes(h, w, c, {r, 1, eps}) bytes, or NULL for the context's.
+ */
+gf_status gf_plain(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
+                   int32_t r, double eps, gf_border border,
+                   void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/*
+ * Algorithm 2 (Fast Guided Filter): subsample I and p by params->s, solve
+ * Eqs. 2-3 and smooth a, b at radius r' = r/s on the low-resolution maps,
+ * upsample mean_a, mean_b bilinearly and output q = mean_a .* I + mean_b
+ * against the full-resolution I.  Same shapes, ownership and stream rules as
+ * gf_plain.  With params->s == 1 it is gf_plain.
+ */
+gf_status gf_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
+                  const gf_params *params, void *workspace, size_t workspace_bytes,
+                  void *hip_stream);
+
+/* Workspace (bytes) of gf_fast_batched for n images (device memory). */
+size_t gf_batched_workspace_bytes(int32_t n, const gf_image *I, const gf_image *p,
+                                  const gf_params *params);
+
+/*
+ * Algorithm 2 for n independent images (arrays of n descriptors and n
+ * parameter sets; sizes, c, r, s and eps may differ, the dtype may not) in
+ * ONE persistent launch over a queue of tiles.  Each q[k] equals what gf_fast
+ * writes for image k.  Descriptor arrays are host memory, read during the
+ * call.  workspace: at least gf_batched_workspace_bytes(...) of device memory,
+ * or NULL for the context's.
+ */
+gf_status gf_fast_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_image *p,
+                          gf_image *q, const gf_params *params,
+                          void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/*
+ * Asynchronous request: filter (I, p) into q like gf_fast.  The request is
+ * admitted when the context's arena has room for its workspace, batched with
+ * the other requests in flight, and run on the context's own streams.
+ * Returns GF_OK with *ticket set, GF_ENOMEM if it can never fit the arena,
+ * GF_EBUSY if `max_inflight` requests are held, GF_EINVAL for bad arguments.
+ * I, p, q must stay valid until gf_poll returns a terminal status.
+ */
+gf_status gf_submit(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
+                    const gf_params *params, uint64_t *ticket);
+
+/*
+ * Status of a request: GF_PENDING while queued or running, GF_OK when q is
+ * complete (the ticket is then retired), or the request's error.  Waits up
+ * to `wait_ms` milliseconds for completion (0 = do not wait, negative = wait
+ * without limit); GF_ETIMEDOUT if it is still pending after a positive wait.
+ * `stats` (may be NULL) receives the request's timestamps on GF_OK.
+ * Unknown or already retired tickets return GF_EINVAL.
+ */
+gf_status gf_poll(gf_ctx *ctx, uint64_t ticket, int32_t wait_ms, gf_req_stats *stats);
+
+/*
+ * Kernel timing for measurement.  While enabled on a context, every launch
+ * made through it (gf_plain, gf_fast, gf_fast_batched) records a pair of HIP
+ * events around each of its kernels on the caller's stream.
+ * gf_ctx_profile_read waits for the recorded events, writes per-kernel
+ * totals into out[0..GF_NKERNELS-1] (indexed by gf_kernel_id) and clears
+ * them.  Enabling adds two event records per kernel; results are unchanged.
+ */
+typedef enum {
+    GF_K_COEFF = 0,   /* subsample + window sums + a, b (Alg. 2 steps 1-4) */
+    GF_K_BOX = 1,     /* box means of a, b (step 5) */
+    GF_K_OUTPUT = 2,  /* bilinear upsample + q = mean_a*I + mean_b (steps 6-7) */
+    GF_K_BATCHED = 3, /* the persistent kernel of gf_fast_batched */
+    GF_NKERNELS = 4
+} gf_kernel_id;
+
+typedef struct {
+    double total_ms;  /* summed event-to-event durations */
+    int64_t launches;
+} gf_kernel_time;
+
+gf_status gf_ctx_profile(gf_ctx *ctx, int enable);
+gf_status gf_ctx_profile_read(gf_ctx *ctx, gf_kernel_time *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF_H */

@@ -1,0 +1,295 @@
+"""Python binding of libgf.so, the MI355X guided-filter library (include/gf.h).
+
+Argument marshalling only: torch tensors on the GPU are described to the C ABI
+as ``gf_image`` views (pointer, dtype, shape, strides in elements) and the
+current torch stream is passed as the ``hipStream_t``; every step of the
+filter runs in the library's HIP kernels.  The functions carry the names of
+the C entry points: ``gf_plain``, ``gf_fast``, ``gf_fast_batched``,
+``gf_submit`` and ``gf_poll`` (the latter two through ``Context``).
+
+There is no fallback: if libgf.so is missing or fails to load, every call
+raises.  Build it with ``python -m paper_1505_00996_amd.build``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgf.so")
+
+GF_OK, GF_PENDING = 0, 1
+GF_EINVAL, GF_ENOMEM, GF_EBUSY, GF_ENOTSUP, GF_EDEVICE, GF_ETIMEDOUT = -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "GF_OK", 1: "GF_PENDING", -1: "GF_EINVAL", -2: "GF_ENOMEM", -3: "GF_EBUSY",
+                -4: "GF_ENOTSUP", -5: "GF_EDEVICE", -6: "GF_ETIMEDOUT"}
+GF_F32, GF_F16, GF_BF16 = 0, 1, 2
+GF_BORDER_CLIP = 0
+GF_SUB_NEAREST, GF_SUB_BILINEAR = 0, 1
+SUBSAMPLE = {"nearest": GF_SUB_NEAREST, "bilinear": GF_SUB_BILINEAR}
+
+# Every symbol include/gf.h declares.
+EXPORTS = ("gf_ctx_create", "gf_ctx_destroy", "gf_last_error", "gf_workspace_bytes", "gf_plain",
+           "gf_fast", "gf_batched_workspace_bytes", "gf_fast_batched", "gf_submit", "gf_poll",
+           "gf_ctx_profile", "gf_ctx_profile_read")
+KERNELS = ("coeff", "box", "output", "batched")
+
+
+class gf_image(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int), ("c", ctypes.c_int32),
+                ("h", ctypes.c_int32), ("w", ctypes.c_int32), ("row_stride", ctypes.c_int64),
+                ("plane_stride", ctypes.c_int64)]
+
+
+class gf_params(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("s", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("border", ctypes.c_int), ("sub", ctypes.c_int)]
+
+
+class gf_req_stats(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class gf_kernel_time(ctypes.Structure):
+    _fields_ = [("total_ms", ctypes.c_double), ("launches", ctypes.c_int64)]
+
+
+class GfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with "
+                              "`python -m paper_1505_00996_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, D, VP, SZ = (ctypes.POINTER, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                  ctypes.c_void_p, ctypes.c_size_t)
+        img_p, par_p = P(gf_image), P(gf_params)
+        sig = {
+            "gf_ctx_create": (ctypes.c_int, [P(VP), ctypes.c_int, SZ, ctypes.c_int]),
+            "gf_ctx_destroy": (None, [VP]),
+            "gf_last_error": (ctypes.c_char_p, [VP]),
+            "gf_workspace_bytes": (SZ, [I32, I32, I32, par_p]),
+            "gf_plain": (ctypes.c_int, [VP, img_p, img_p, img_p, I32, D, ctypes.c_int, VP, SZ, VP]),
+            "gf_fast": (ctypes.c_int, [VP, img_p, img_p, img_p, par_p, VP, SZ, VP]),
+            "gf_batched_workspace_bytes": (SZ, [I32, img_p, img_p, par_p]),
+            "gf_fast_batched": (ctypes.c_int, [VP, I32, img_p, img_p, img_p, par_p, VP, SZ, VP]),
+            "gf_submit": (ctypes.c_int, [VP, img_p, img_p, img_p, par_p, P(ctypes.c_uint64)]),
+            "gf_poll": (ctypes.c_int, [VP, ctypes.c_uint64, I32, P(gf_req_stats)]),
+            "gf_ctx_profile": (ctypes.c_int, [VP, ctypes.c_int]),
+            "gf_ctx_profile_read": (ctypes.c_int, [VP, P(gf_kernel_time)]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error(ctx=None) -> str:
+    return (lib().gf_last_error(ctx._h if ctx else None) or b"").decode()
+
+
+def _check(st: int, ctx=None) -> int:
+    if st < 0:
+        raise GfError(st, last_error(ctx))
+    return st
+
+
+def _dtype_code(t) -> int:
+    import torch
+    codes = {torch.float32: GF_F32, torch.float16: GF_F16, torch.bfloat16: GF_BF16}
+    if t.dtype not in codes:
+        raise TypeError(f"unsupported dtype {t.dtype}; use float32, float16 or bfloat16")
+    return codes[t.dtype]
+
+
+def image(t) -> gf_image:
+    """Describe a (H, W) or (C, H, W) device tensor as a gf_image (no copy)."""
+    if not t.is_cuda:
+        raise ValueError("gf images must be GPU tensors")
+    if t.dim() == 2:
+        c, (h, w) = 1, t.shape
+        rs, ps = t.stride(0), t.stride(0) * h
+        if t.stride(1) != 1:
+            raise ValueError("rows must be contiguous (stride 1 along W)")
+    elif t.dim() == 3:
+        c, h, w = t.shape
+        ps, rs, cs = t.stride()
+        if cs != 1:
+            raise ValueError("rows must be contiguous (stride 1 along W)")
+    else:
+        raise ValueError("expected a (H, W) or (C, H, W) tensor")
+    return gf_image(t.data_ptr(), _dtype_code(t), c, h, w, rs, ps)
+
+
+def params(r: int, s: int, eps: float, sub: str | int = "nearest") -> gf_params:
+    return gf_params(int(r), int(s), float(eps), GF_BORDER_CLIP,
+                     SUBSAMPLE[sub] if isinstance(sub, str) else int(sub))
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def workspace_bytes(h: int, w: int, c: int, r: int, s: int, eps: float, sub="nearest") -> int:
+    return int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(params(r, s, eps, sub))))
+
+
+def _workspace(nbytes: int, device):
+    import torch
+    ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    if ws.data_ptr() % 256:
+        raise RuntimeError("workspace allocation is not 256-byte aligned")
+    return ws
+
+
+def _out_like(p, q):
+    import torch
+    if q is None:
+        return torch.empty_like(p, memory_format=torch.contiguous_format)
+    return q
+
+
+def gf_fast(I, p, r: int, s: int, eps: float, sub: str = "nearest", q=None, ctx=None,
+            workspace=None, stream=None):
+    """Algorithm 2 on the GPU: returns q (shape of p).  ``I`` is (H, W);
+    ``p`` is (H, W) or (C, H, W); same dtype (float32 / float16 / bfloat16)."""
+    q = _out_like(p, q)
+    pr = params(r, s, eps, sub)
+    h, w = I.shape[-2:]
+    c = 1 if p.dim() == 2 else p.shape[0]
+    need = int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(pr)))
+    if workspace is None:
+        workspace = _workspace(need, p.device)
+    _check(lib().gf_fast(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p)),
+                         ctypes.byref(image(q)), ctypes.byref(pr), ctypes.c_void_p(workspace.data_ptr()),
+                         workspace.numel() * workspace.element_size(), _stream(stream)), ctx)
+    return q
+
+
+def gf_plain(I, p, r: int, eps: float, q=None, ctx=None, workspace=None, stream=None):
+    """Algorithm 1 on the GPU (full resolution): returns q (shape of p)."""
+    q = _out_like(p, q)
+    pr = params(r, 1, eps)
+    h, w = I.shape[-2:]
+    c = 1 if p.dim() == 2 else p.shape[0]
+    need = int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(pr)))
+    if workspace is None:
+        workspace = _workspace(need, p.device)
+    _check(lib().gf_plain(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p)),
+                          ctypes.byref(image(q)), int(r), float(eps), GF_BORDER_CLIP,
+                          ctypes.c_void_p(workspace.data_ptr()),
+                          workspace.numel() * workspace.element_size(), _stream(stream)), ctx)
+    return q
+
+
+def _arrays(Is, ps, qs, prs):
+    n = len(Is)
+    if not (len(ps) == len(qs) == len(prs) == n):
+        raise ValueError("I, p, q and params lists must have the same length")
+    return ((gf_image * n)(*[image(t) for t in Is]), (gf_image * n)(*[image(t) for t in ps]),
+            (gf_image * n)(*[image(t) for t in qs]), (gf_params * n)(*prs))
+
+
+def batched_workspace_bytes(Is, ps, prs) -> int:
+    n = len(Is)
+    aI, ap, _, apr = _arrays(Is, ps, ps, prs)
+    return int(lib().gf_batched_workspace_bytes(n, aI, ap, apr))
+
+
+def gf_fast_batched(Is, ps, prs, qs=None, ctx=None, workspace=None, stream=None):
+    """Algorithm 2 for a list of images in one persistent launch.  ``prs`` is
+    a list of ``params(r, s, eps, sub)``.  Returns the list of outputs."""
+    if qs is None:
+        qs = [_out_like(p, None) for p in ps]
+    n = len(Is)
+    aI, ap, aq, apr = _arrays(Is, ps, qs, prs)
+    if workspace is None:
+        workspace = _workspace(lib().gf_batched_workspace_bytes(n, aI, ap, apr), ps[0].device)
+    _check(lib().gf_fast_batched(ctx._h if ctx else None, n, aI, ap, aq, apr,
+                                 ctypes.c_void_p(workspace.data_ptr()),
+                                 workspace.numel() * workspace.element_size(), _stream(stream)), ctx)
+    return qs
+
+
+@dataclass
+class ReqStats:
+    t_submit: float
+    t_admit: float
+    t_start: float
+    t_done: float
+
+
+class Context:
+    """A gf_ctx: device, optional request arena (gf_submit / gf_poll)."""
+
+    def __init__(self, device: int = 0, arena_bytes: int = 0, max_inflight: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().gf_ctx_create(ctypes.byref(h), int(device), int(arena_bytes), int(max_inflight)))
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if self._h:
+            lib().gf_ctx_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, enable: bool = True):
+        """Record HIP events around every kernel this context launches."""
+        _check(lib().gf_ctx_profile(self._h, int(bool(enable))), self)
+
+    def profile_read(self) -> dict:
+        """{kernel: (total_ms, launches)} since the last read (waits for the events)."""
+        out = (gf_kernel_time * len(KERNELS))()
+        _check(lib().gf_ctx_profile_read(self._h, out), self)
+        return {k: (out[i].total_ms, out[i].launches) for i, k in enumerate(KERNELS)}
+
+    def gf_submit(self, I, p, q, r: int, s: int, eps: float, sub: str = "nearest") -> int:
+        """Queue a request; returns its ticket.  I, p, q are kept alive here
+        until gf_poll reports the request finished."""
+        t = ctypes.c_uint64()
+        _check(lib().gf_submit(self._h, ctypes.byref(image(I)), ctypes.byref(image(p)),
+                               ctypes.byref(image(q)), ctypes.byref(params(r, s, eps, sub)),
+                               ctypes.byref(t)), self)
+        self._keep[t.value] = (I, p, q)
+        return t.value
+
+    def gf_poll(self, ticket: int, wait_ms: int = 0):
+        """Returns (status, ReqStats or None); raises on a failed request."""
+        st = gf_req_stats()
+        rc = lib().gf_poll(self._h, ctypes.c_uint64(ticket), int(wait_ms), ctypes.byref(st))
+        if rc == GF_PENDING or rc == GF_ETIMEDOUT:
+            return rc, None
+        self._keep.pop(ticket, None)
+        _check(rc, self)
+        return rc, ReqStats(st.t_submit, st.t_admit, st.t_start, st.t_done)

@@ -1,0 +1,259 @@
+// Host side of libgf.so: argument validation, geometry, workspace layout,
+// tile heuristics and the gf_plain / gf_fast entry points of include/gf.h.
+// Validation is pure host code and runs before any HIP call, so an invalid
+// call is reported without touching a device.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "gf_api_internal.h"
+#include "gf_internal.h"
+
+namespace gf {
+
+static thread_local char t_err[512] = "";
+
+gf_status fail(gf_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(t_err, sizeof t_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+const char *last_error() { return t_err; }
+
+static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+int lowres_radius(int r, int s) {
+    if (r <= 0) return 0;
+    const int rl = (2 * r + s) / (2 * s);  // r/s rounded half up
+    return rl < 1 ? 1 : rl;
+}
+
+Geo make_geo(int H, int W, int C, int r, int s, double eps, int sub) {
+    Geo g;
+    g.H = H;
+    g.W = W;
+    g.s = s;
+    g.Hl = (H + s - 1) / s;
+    g.Wl = (W + s - 1) / s;
+    g.R = lowres_radius(r, s);
+    g.C = C;
+    g.sub = sub;
+    g.eps = (float)eps;
+    g.lrs = round_up(g.Wl, 16);
+    g.lps = round_up((int64_t)g.Hl * g.lrs, 64);
+    return g;
+}
+
+size_t coeff_lds_bytes(int th, int stage, int R) {
+    const size_t SH = th + 2 * R, SW = kTileW + 2 * R;
+    return sizeof(float) * ((stage ? 2 * SH * SW : 0) + 2 * SH * kTileW);
+}
+
+size_t box_lds_bytes(int th, int stage, int R) {
+    const size_t SH = th + 2 * R, SW = kTileW + 2 * R;
+    return sizeof(float) * ((stage ? SH * SW : 0) + SH * kTileW);
+}
+
+static const size_t kLdsMax = 160 * 1024;
+static const size_t kStageMax = 96 * 1024;
+
+TileCfg default_tiles(const Geo &g) {
+    TileCfg t;
+    t.coeff_th = g.R <= 8 ? 32 : 16;
+    t.coeff_stage = coeff_lds_bytes(t.coeff_th, 1, g.R) <= kStageMax;
+    t.box_th = g.R <= 8 ? 32 : 16;
+    t.box_stage = box_lds_bytes(t.box_th, 1, g.R) <= kStageMax;
+    t.out_rows = 8;
+    return t;
+}
+
+bool tiles_fit(const Geo &g, const TileCfg &t) {
+    return coeff_lds_bytes(t.coeff_th, t.coeff_stage, g.R) <= kLdsMax &&
+           box_lds_bytes(t.box_th, t.box_stage, g.R) <= kLdsMax;
+}
+
+size_t workspace_bytes(const Geo &g) {
+    // a, b (2C planes) and their box means (2C planes), FP32
+    return sizeof(float) * (size_t)(4 * g.C) * (size_t)g.lps;
+}
+
+static size_t elem_size(gf_dtype d) { return d == GF_F32 ? 4 : 2; }
+
+// Byte range [lo, hi) touched by an image view.
+static void extent(const gf_image *im, uintptr_t *lo, uintptr_t *hi) {
+    const size_t es = elem_size(im->dtype);
+    *lo = (uintptr_t)im->data;
+    const int64_t last = (int64_t)(im->c - 1) * im->plane_stride +
+                         (int64_t)(im->h - 1) * im->row_stride + im->w;
+    *hi = *lo + (uintptr_t)(last * (int64_t)es);
+}
+
+static bool overlaps(const gf_image *a, const gf_image *b) {
+    uintptr_t a0, a1, b0, b1;
+    extent(a, &a0, &a1);
+    extent(b, &b0, &b1);
+    return a0 < b1 && b0 < a1;
+}
+
+static gf_status check_image(const gf_image *im, const char *name) {
+    if (!im) return fail(GF_EINVAL, "%s: null descriptor", name);
+    if (!im->data) return fail(GF_EINVAL, "%s: null data pointer", name);
+    if (im->dtype != GF_F32 && im->dtype != GF_F16 && im->dtype != GF_BF16)
+        return fail(GF_EINVAL, "%s: unknown dtype %d", name, (int)im->dtype);
+    if (im->c < 1 || im->h < 1 || im->w < 1)
+        return fail(GF_EINVAL, "%s: empty or negative shape %dx%dx%d", name, im->c, im->h, im->w);
+    if (im->row_stride < im->w)
+        return fail(GF_EINVAL, "%s: row_stride %lld < w %d", name, (long long)im->row_stride, im->w);
+    if (im->c > 1 && im->plane_stride < (int64_t)im->h * im->row_stride)
+        return fail(GF_EINVAL, "%s: plane_stride %lld < h*row_stride", name,
+                    (long long)im->plane_stride);
+    if ((uintptr_t)im->data % elem_size(im->dtype))
+        return fail(GF_EINVAL, "%s: data pointer not aligned to its element size", name);
+    return GF_OK;
+}
+
+gf_status validate(const gf_image *I, const gf_image *p, const gf_image *q,
+                   const gf_params *pr) {
+    gf_status st;
+    if ((st = check_image(I, "I")) != GF_OK) return st;
+    if ((st = check_image(p, "p")) != GF_OK) return st;
+    if ((st = check_image(q, "q")) != GF_OK) return st;
+    if (!pr) return fail(GF_EINVAL, "params: null");
+    if (I->c != 1) return fail(GF_ENOTSUP, "I: colour guidance (c=%d) is not supported; I must be gray", I->c);
+    if (p->h != I->h || p->w != I->w || q->h != I->h || q->w != I->w)
+        return fail(GF_EINVAL, "shape mismatch: I %dx%d, p %dx%d, q %dx%d", I->h, I->w, p->h,
+                    p->w, q->h, q->w);
+    if (p->c != q->c) return fail(GF_EINVAL, "channel mismatch: p has %d, q has %d", p->c, q->c);
+    if (p->dtype != I->dtype || q->dtype != I->dtype)
+        return fail(GF_EINVAL, "dtype mismatch between I, p and q");
+    if (overlaps(q, I) || overlaps(q, p)) return fail(GF_EINVAL, "q overlaps I or p");
+    if (pr->r < 0) return fail(GF_EINVAL, "r = %d < 0", pr->r);
+    if (pr->s < 1) return fail(GF_EINVAL, "s = %d < 1", pr->s);
+    if (!(pr->eps > 0.0) || !isfinite(pr->eps) || !((float)pr->eps > 0.0f) ||
+        !isfinite((float)pr->eps))
+        return fail(GF_EINVAL, "eps = %g must be positive and finite (in FP32)", pr->eps);
+    if (pr->border != GF_BORDER_CLIP) return fail(GF_ENOTSUP, "border %d not supported", (int)pr->border);
+    if (pr->sub != GF_SUB_NEAREST && pr->sub != GF_SUB_BILINEAR)
+        return fail(GF_EINVAL, "unknown subsampling mode %d", (int)pr->sub);
+    if (I->h > (1 << 24) || I->w > (1 << 24)) return fail(GF_ENOTSUP, "image side above 2^24");
+    if (lowres_radius(pr->r, pr->s) > kMaxRadius)
+        return fail(GF_ENOTSUP, "low-res radius %d above %d", lowres_radius(pr->r, pr->s), kMaxRadius);
+    return GF_OK;
+}
+
+// 16-byte (fp32) or 8-byte (16-bit) accesses of 4 pixels need the row starts
+// of I and of every q plane aligned to that size.
+bool vector_ok(const gf_image *I, const gf_image *q) {
+    const size_t es = elem_size(I->dtype), vb = 4 * es;
+    auto aligned = [&](const gf_image *im) {
+        return (uintptr_t)im->data % vb == 0 && (im->row_stride * (int64_t)es) % (int64_t)vb == 0 &&
+               (im->c == 1 || (im->plane_stride * (int64_t)es) % (int64_t)vb == 0);
+    };
+    return aligned(I) && aligned(q);
+}
+
+gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
+                   const gf_params *pr, void *ws, size_t ws_bytes, hipStream_t st,
+                   const TileCfg *tiles) {
+    const Geo g = make_geo(I->h, I->w, p->c, pr->r, pr->s, pr->eps, (int)pr->sub);
+    const TileCfg t = tiles ? *tiles : default_tiles(g);
+    if (!tiles_fit(g, t)) return fail(GF_ENOTSUP, "tile shapes do not fit in LDS for r'=%d", g.R);
+    const size_t need = workspace_bytes(g);
+    if (!ws) return fail(GF_EINVAL, "no workspace");
+    if (ws_bytes < need)
+        return fail(GF_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    if ((uintptr_t)ws % 256) return fail(GF_EINVAL, "workspace not 256-byte aligned");
+    float *coef = (float *)ws;
+    float *mean = coef + (size_t)(2 * g.C) * g.lps;
+    const View vI{I->data, I->row_stride, I->plane_stride};
+    const View vP{p->data, p->row_stride, p->plane_stride};
+    const View vQ{q->data, q->row_stride, q->plane_stride};
+    hipError_t e;
+    {
+        ProfScope ps(ctx, GF_K_COEFF, st);
+        e = launch_coeff(I->dtype, vI, vP, coef, g, t, st);
+    }
+    if (e == hipSuccess) {
+        ProfScope ps(ctx, GF_K_BOX, st);
+        e = launch_box(coef, mean, g, t, st);
+    }
+    if (e == hipSuccess) {
+        ProfScope ps(ctx, GF_K_OUTPUT, st);
+        e = launch_output(I->dtype, vI, vQ, mean, g, t, vector_ok(I, q), st);
+    }
+    if (e != hipSuccess) return fail(GF_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return GF_OK;
+}
+
+// Context-owned workspace, grown on demand.  Growing frees the old buffer
+// after the device has finished with it.
+gf_status ctx_workspace(gf_ctx *ctx, size_t need, void **ws) {
+    if (ctx->ws_bytes < need) {
+        if (ctx->ws) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return fail(GF_EDEVICE, "hipDeviceSynchronize: %s", hipGetErrorString(e));
+            (void)hipFree(ctx->ws);
+            ctx->ws = nullptr;
+            ctx->ws_bytes = 0;
+        }
+        hipError_t e = hipMalloc(&ctx->ws, need);
+        if (e != hipSuccess) {
+            ctx->ws = nullptr;
+            return fail(GF_ENOMEM, "hipMalloc(%zu): %s", need, hipGetErrorString(e));
+        }
+        ctx->ws_bytes = need;
+    }
+    *ws = ctx->ws;
+    return GF_OK;
+}
+
+}  // namespace gf
+
+using namespace gf;
+
+extern "C" {
+
+const char *gf_last_error(const gf_ctx *) { return gf::last_error(); }
+
+size_t gf_workspace_bytes(int32_t h, int32_t w, int32_t c, const gf_params *pr) {
+    if (!pr || h < 1 || w < 1 || c < 1 || pr->s < 1 || pr->r < 0) return 0;
+    return workspace_bytes(make_geo(h, w, c, pr->r, pr->s, pr->eps, (int)pr->sub));
+}
+
+gf_status gf_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
+                  const gf_params *pr, void *ws, size_t ws_bytes, void *stream) {
+    gf_status st = validate(I, p, q, pr);
+    if (st != GF_OK) return st;
+    if (!ws) {
+        if (!ctx) return fail(GF_EINVAL, "workspace is NULL and there is no context");
+        const Geo g = make_geo(I->h, I->w, p->c, pr->r, pr->s, pr->eps, (int)pr->sub);
+        if ((st = ctx_use_device(ctx)) != GF_OK) return st;
+        ws_bytes = workspace_bytes(g);
+        if ((st = ctx_workspace(ctx, ws_bytes, &ws)) != GF_OK) return st;
+    } else if (ctx && (st = ctx_use_device(ctx)) != GF_OK) {
+        return st;
+    }
+    return run_fast(ctx, I, p, q, pr, ws, ws_bytes, (hipStream_t)stream,
+                    ctx ? ctx_tiles(ctx, I, p, pr) : nullptr);
+}
+
+gf_status gf_plain(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q, int32_t r,
+                   double eps, gf_border border, void *ws, size_t ws_bytes, void *stream) {
+    gf_params pr;
+    pr.r = r;
+    pr.s = 1;
+    pr.eps = eps;
+    pr.border = border;
+    pr.sub = GF_SUB_NEAREST;
+    return gf_fast(ctx, I, p, q, &pr, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// Host-side internals shared by the API translation units (not public ABI).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "gf.h"
+#include "gf_internal.h"
+
+namespace gf {
+class Engine;
+}
+
+struct gf_ctx {
+    int device = 0;
+    void *ws = nullptr;      // workspace for calls that pass none
+    size_t ws_bytes = 0;
+    std::mutex tune_mu;      // guards `tuned`
+    std::unordered_map<uint64_t, gf::TileCfg> tuned;  // tile shapes picked by gf_tune
+    gf::Engine *engine = nullptr;  // request interface (gf_submit / gf_poll)
+    // kernel timing (gf_ctx_profile)
+    bool profiling = false;
+    struct Mark {
+        int kernel;
+        hipEvent_t start, end;
+    };
+    std::mutex prof_mu;
+    std::vector<Mark> marks;
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace gf {
+
+gf_status fail(gf_status st, const char *fmt, ...);
+const char *last_error();
+int lowres_radius(int r, int s);
+bool tiles_fit(const Geo &g, const TileCfg &t);
+size_t workspace_bytes(const Geo &g);
+gf_status validate(const gf_image *I, const gf_image *p, const gf_image *q, const gf_params *pr);
+bool vector_ok(const gf_image *I, const gf_image *q);
+gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
+                   const gf_params *pr, void *ws, size_t ws_bytes, hipStream_t st,
+                   const TileCfg *tiles);
+
+// Event pair around one kernel when the context is profiling (no-op otherwise).
+struct ProfScope {
+    gf_ctx *ctx;
+    int kernel;
+    hipStream_t st;
+    hipEvent_t start = nullptr;
+    ProfScope(gf_ctx *c, int k, hipStream_t s);
+    ~ProfScope();
+};
+gf_status ctx_use_device(gf_ctx *ctx);
+const TileCfg *ctx_tiles(gf_ctx *ctx, const gf_image *I, const gf_image *p, const gf_params *pr);
+uint64_t tile_key(gf_dtype dt, int C, int s, int R);
+gf_status engine_start(gf_ctx *ctx, size_t arena_bytes, int max_inflight);
+void engine_stop(gf_ctx *ctx);
+
+}  // namespace gf

@@ -1,0 +1,60 @@
+// Internal declarations shared by the host API (gf_api.cpp) and the HIP
+// kernels (gf_kernels.hip, gf_batched.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gf.h"
+
+namespace gf {
+
+// Geometry of one filtering problem.  Full-res H x W, low-res Hl x Wl
+// (ceil(H/s) x ceil(W/s)), low-res radius R, C channels of p.  The
+// low-resolution FP32 maps live in a workspace as planes of Hl rows with
+// row stride lrs (a multiple of 16 floats) and plane stride lps (a multiple
+// of 64 floats), so every plane and row start is 64-byte aligned.
+struct Geo {
+    int H, W;
+    int Hl, Wl;
+    int s, R, C, sub;
+    float eps;
+    int64_t lrs, lps;
+};
+
+// Strided view of a device image: element (k, y, x) at data + k*ps + y*rs + x.
+struct View {
+    void *data;
+    int64_t rs, ps;
+};
+
+// Tile shapes for one call (picked by the host heuristic or the tuner).
+struct TileCfg {
+    int coeff_th;     // rows per tile of the coefficient kernel (16 or 32)
+    int coeff_stage;  // 1: stage the low-res tile in LDS, 0: read through the caches
+    int box_th;       // rows per tile of the box-mean kernel (16 or 32)
+    int box_stage;
+    int out_rows;     // full-res rows per wave of the output kernel
+};
+
+constexpr int kThreads = 256;   // threads per workgroup for every kernel
+constexpr int kTileW = 64;      // low-res tile width of the window-sum kernels
+constexpr int kRun = 8;         // consecutive outputs per thread in a row pass
+constexpr int kOutPx = 4;       // full-res pixels per lane in the output kernel
+constexpr int kOutTileW = 64 * kOutPx;  // full-res columns per output tile
+constexpr int kMaxRadius = 150; // largest low-res radius the LDS row buffers hold
+
+Geo make_geo(int H, int W, int C, int r, int s, double eps, int sub);
+size_t coeff_lds_bytes(int th, int stage, int R);
+size_t box_lds_bytes(int th, int stage, int R);
+TileCfg default_tiles(const Geo &g);
+
+// Kernel launchers (gf_kernels.hip).  All return the launch status.
+hipError_t launch_coeff(gf_dtype dt, const View &I, const View &P, float *coef,
+                        const Geo &g, const TileCfg &t, hipStream_t st);
+hipError_t launch_box(const float *src, float *dst, const Geo &g, const TileCfg &t,
+                      hipStream_t st);
+hipError_t launch_output(gf_dtype dt, const View &I, const View &Q, const float *mean,
+                         const Geo &g, const TileCfg &t, bool vec, hipStream_t st);
+
+}  // namespace gf

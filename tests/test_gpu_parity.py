@@ -1,0 +1,162 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances: max|q_gpu - q_oracle| <= 1e-5 with FP32 storage; <= 2e-3 with
+16-bit storage (bf16 outputs with |q| >= 1: half a bf16 ulp + 1e-4, since the
+store's rounding alone exceeds 2e-3 there).  The oracle reads the stored
+input values upcast exactly to FP64.
+"""
+import numpy as np
+import pytest
+
+import gpuutil
+import synth
+from oracle import oracle
+
+pytestmark = pytest.mark.gpu
+
+gfp = gpuutil.ensure_built()
+
+
+def run_fast(I, p, r, s, eps, sub="nearest", dtype="f32", **kw):
+    import torch
+    dI, dp = gpuutil.to_device(I, dtype), gpuutil.to_device(p, dtype)
+    q = gfp.gf_fast(dI, dp, r, s, eps, sub, **kw)
+    torch.cuda.synchronize()
+    return dI, dp, q
+
+
+def check(I, p, r, s, eps, sub="nearest", dtype="f32", plain=False, label=""):
+    import torch
+    dI, dp = gpuutil.to_device(I, dtype), gpuutil.to_device(p, dtype)
+    if plain:
+        q = gfp.gf_plain(dI, dp, r, eps)
+    else:
+        q = gfp.gf_fast(dI, dp, r, s, eps, sub)
+    torch.cuda.synchronize()
+    Is, ps = gpuutil.stored_f64(dI), gpuutil.stored_f64(dp)
+    if plain:
+        exp = oracle.guided_filter(Is, ps, r, eps)
+    else:
+        exp = oracle.fast_guided_filter(Is, ps, r, s, eps, sub)
+    got = gpuutil.stored_f64(q)
+    tol = gpuutil.tolerance(dtype, exp)
+    err = np.abs(got - exp)
+    bad = err > tol
+    e, where = gpuutil.max_err(got, exp)
+    assert not bad.any(), f"{label}: {int(bad.sum())} elements out of tolerance; max err {e:.3e} at {where}"
+    return e
+
+
+@pytest.mark.parametrize("sub", ["nearest", "bilinear"])
+def test_small_workload(sub):
+    """512x512 rectangles + noise; r=8, s=4, eps=0.01."""
+    I, p = synth.workload_small()
+    check(I, p, 8, 4, 0.01, sub, label=f"512x512 {sub}")
+
+
+@pytest.mark.parametrize("h,w,c,r,s,sub", [
+    (37, 45, 1, 8, 4, "nearest"),        # ragged in both axes, < one tile
+    (130, 301, 3, 5, 2, "bilinear"),     # W not a multiple of 4 (scalar tail)
+    (257, 513, 2, 12, 4, "nearest"),     # several tiles + ragged tail, C=2
+    (200, 180, 5, 9, 3, "bilinear"),     # odd s (bilinear = nearest), C=5 (channel groups)
+    (1, 301, 1, 4, 4, "nearest"),        # single row
+    (301, 1, 3, 4, 2, "bilinear"),       # single column
+    (7, 9, 1, 40, 4, "nearest"),         # r' larger than the low-res map
+    (1, 1, 1, 3, 8, "nearest"),          # one pixel
+    (96, 640, 1, 3, 8, "nearest"),       # s=8
+    (150, 150, 3, 7, 5, "nearest"),      # runtime s (no compile-time variant)
+    (64, 64, 1, 0, 4, "nearest"),        # r=0
+])
+def test_shapes(h, w, c, r, s, sub):
+    g = np.random.Generator(np.random.PCG64(h * 1000 + w))
+    I = synth.photo_guide(h, w, seed=h + w)
+    p = np.clip(I[None] * g.uniform(0.6, 1.2, size=(c, 1, 1)) + g.normal(0, 0.05, size=(c, h, w)),
+                0, 1).astype(np.float32)
+    check(I, p, r, s, 1e-2, sub, label=f"{h}x{w} c={c} r={r} s={s}")
+
+
+@pytest.mark.parametrize("h,w,c,r", [(64, 64, 1, 2), (97, 203, 3, 16), (120, 90, 1, 30),
+                                     (33, 1000, 2, 8)])
+def test_plain(h, w, c, r):
+    I = synth.photo_guide(h, w, seed=5)
+    p = synth.colour_input(I, c, seed=6)
+    check(I, p, r, 1, 1e-3, plain=True, label=f"plain {h}x{w} r={r}")
+
+
+def test_large_radius_unstaged():
+    """A radius whose tile does not fit the LDS staging buffers."""
+    I = synth.photo_guide(300, 280, seed=9)
+    p = synth.colour_input(I, 1, seed=10)
+    check(I, p, 60, 1, 1e-4, plain=True, label="plain r=60")
+    check(I, p, 60, 4, 1e-6, label="fast r=60 s=4")
+
+
+def test_fast_s1_is_plain_bitwise():
+    import torch
+    I = synth.photo_guide(123, 257, seed=3)
+    p = synth.colour_input(I, 3, seed=4)
+    dI, dp = gpuutil.to_device(I), gpuutil.to_device(p)
+    a = gfp.gf_fast(dI, dp, 6, 1, 1e-3, "bilinear")
+    b = gfp.gf_plain(dI, dp, 6, 1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_deterministic():
+    import torch
+    I, p = synth.workload_small()
+    dI, dp = gpuutil.to_device(I), gpuutil.to_device(p)
+    a = gfp.gf_fast(dI, dp, 8, 4, 1e-2)
+    b = gfp.gf_fast(dI, dp, 8, 4, 1e-2)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_strided_views():
+    """Row and plane strides larger than the image (a crop of a bigger
+    buffer) and a misaligned start: exercises the element-wise path."""
+    import torch
+    I = synth.photo_guide(150, 203, seed=11)
+    p = synth.colour_input(I, 3, seed=12)
+    bigI = torch.zeros(160, 260, device="cuda")
+    bigI[5:155, 1:204] = gpuutil.to_device(I)
+    bigP = torch.zeros(3, 170, 256, device="cuda")
+    bigP[:, 3:153, 7:210] = gpuutil.to_device(p)
+    vI, vP = bigI[5:155, 1:204], bigP[:, 3:153, 7:210]
+    outbuf = torch.full((3, 151, 240), 7.0, device="cuda")
+    vQ = outbuf[:, :150, 2:205]
+    gfp.gf_fast(vI, vP, 8, 4, 1e-2, q=vQ)
+    torch.cuda.synchronize()
+    exp = oracle.fast_guided_filter(I.astype(np.float64), p.astype(np.float64), 8, 4, 1e-2)
+    e, where = gpuutil.max_err(gpuutil.stored_f64(vQ), exp)
+    assert e <= 1e-5, (e, where)
+    # nothing outside the view was written
+    ob = gpuutil.stored_f64(outbuf)
+    mask = np.ones_like(ob, dtype=bool)
+    mask[:, :150, 2:205] = False
+    assert np.all(ob[mask] == 7.0)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_16bit_storage(dtype):
+    I = synth.photo_guide(256, 384, seed=13)
+    p = synth.colour_input(I, 3, seed=14)
+    check(I, p, 16, 4, 1e-3, dtype=dtype, label=f"{dtype} 256x384")
+    check(I, p, 8, 1, 1e-3, dtype=dtype, plain=True, label=f"{dtype} plain")
+
+
+def test_12mp_fast_and_plain():
+    """4000x3000 gray guide, RGB input, r=16, eps=1e-3: fast at s=4 and
+    plain (s=1), compared with the oracle on every element."""
+    I, p = synth.workload_12mp()
+    check(I, p, 16, 4, 1e-3, label="12MP s=4")
+    check(I, p, 16, 1, 1e-3, plain=True, label="12MP plain")
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_24mp_16bit(dtype):
+    """6000x4000 with near-flat [0.49, 0.51] blocks, RGB, r=32, s=8,
+    eps=1e-4 and 1e-6 (cancellation stress for the variance)."""
+    I, p = synth.workload_24mp()
+    for eps in (1e-4, 1e-6):
+        check(I, p, 32, 8, eps, dtype=dtype, label=f"24MP {dtype} eps={eps}")
