@@ -65,9 +65,15 @@ _lib = None
 
 
 def lib() -> ctypes.CDLL:
-    """Load libgf.so (raises if it has not been built)."""
+    """Load libgf.so (raises if it has not been built).
+
+    torch is imported first so that libgf.so binds to the HIP runtime torch
+    already loaded (same soname): the streams and device pointers torch hands
+    over are only valid in that runtime, and a second HIP runtime in the
+    process would not know them."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (loads torch's HIP runtime before libgf.so)
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing; build it with "
                               "`python -m paper_1505_00996_amd.build`")
