@@ -52,31 +52,39 @@ Geo make_geo(int H, int W, int C, int r, int s, double eps, int sub) {
     return g;
 }
 
-size_t coeff_lds_bytes(int th, int stage, int R) {
-    const size_t SH = th + 2 * R, SW = kTileW + 2 * R;
-    return sizeof(float) * ((stage ? 2 * SH * SW : 0) + 2 * SH * kTileW);
+size_t coeff_lds_bytes(int th, int tw, int stage, int R) {
+    // 8 planes of compensated row sums, plus the staged u and v samples
+    const size_t SH = th + 2 * R, SW = tw + 2 * R;
+    return sizeof(float) * (8 * SH * tw + (stage ? 2 * SH * SW : 0));
 }
 
 size_t box_lds_bytes(int th, int stage, int R) {
     const size_t SH = th + 2 * R, SW = kTileW + 2 * R;
-    return sizeof(float) * ((stage ? SH * SW : 0) + SH * kTileW);
+    return sizeof(float) * (SH * kTileW + (stage ? SH * SW : 0));
 }
 
 static const size_t kLdsMax = 160 * 1024;
-static const size_t kStageMax = 96 * 1024;
+static const size_t kStageMax = 64 * 1024;
 
 TileCfg default_tiles(const Geo &g) {
     TileCfg t;
-    t.coeff_th = g.R <= 8 ? 32 : 16;
-    t.coeff_stage = coeff_lds_bytes(t.coeff_th, 1, g.R) <= kStageMax;
+    t.coeff_th = 16;
+    t.coeff_tw = g.R <= 8 ? 64 : 32;
+    t.coeff_stage = coeff_lds_bytes(t.coeff_th, t.coeff_tw, 1, g.R) <= kStageMax;
+    if (!t.coeff_stage && coeff_lds_bytes(t.coeff_th, t.coeff_tw, 0, g.R) > kLdsMax) t.coeff_th = 8;
     t.box_th = g.R <= 8 ? 32 : 16;
     t.box_stage = box_lds_bytes(t.box_th, 1, g.R) <= kStageMax;
+    if (!t.box_stage && box_lds_bytes(t.box_th, 0, g.R) > kLdsMax) t.box_th = 8;
     t.out_rows = 8;
     return t;
 }
 
 bool tiles_fit(const Geo &g, const TileCfg &t) {
-    return coeff_lds_bytes(t.coeff_th, t.coeff_stage, g.R) <= kLdsMax &&
+    const bool shapes = (t.coeff_th == 8 || t.coeff_th == 16 || t.coeff_th == 32) &&
+                        (t.coeff_tw == 32 || t.coeff_tw == 64) &&
+                        (t.box_th == 8 || t.box_th == 16 || t.box_th == 32) && t.out_rows >= 1 &&
+                        t.out_rows <= 64;
+    return shapes && coeff_lds_bytes(t.coeff_th, t.coeff_tw, t.coeff_stage, g.R) <= kLdsMax &&
            box_lds_bytes(t.box_th, t.box_stage, g.R) <= kLdsMax;
 }
 

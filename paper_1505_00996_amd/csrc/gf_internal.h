@@ -30,9 +30,10 @@ struct View {
 
 // Tile shapes for one call (picked by the host heuristic or the tuner).
 struct TileCfg {
-    int coeff_th;     // rows per tile of the coefficient kernel (16 or 32)
+    int coeff_th;     // rows per tile of the coefficient kernel (8, 16 or 32)
+    int coeff_tw;     // columns per tile of the coefficient kernel (32 or 64)
     int coeff_stage;  // 1: stage the low-res tile in LDS, 0: read through the caches
-    int box_th;       // rows per tile of the box-mean kernel (16 or 32)
+    int box_th;       // rows per tile of the box-mean kernel (8, 16 or 32)
     int box_stage;
     int out_rows;     // full-res rows per wave of the output kernel
 };
@@ -42,10 +43,10 @@ constexpr int kTileW = 64;      // low-res tile width of the window-sum kernels
 constexpr int kRun = 8;         // consecutive outputs per thread in a row pass
 constexpr int kOutPx = 4;       // full-res pixels per lane in the output kernel
 constexpr int kOutTileW = 64 * kOutPx;  // full-res columns per output tile
-constexpr int kMaxRadius = 150; // largest low-res radius the LDS row buffers hold
+constexpr int kMaxRadius = 72;  // largest low-res radius the LDS row buffers hold
 
 Geo make_geo(int H, int W, int C, int r, int s, double eps, int sub);
-size_t coeff_lds_bytes(int th, int stage, int R);
+size_t coeff_lds_bytes(int th, int tw, int stage, int R);
 size_t box_lds_bytes(int th, int stage, int R);
 TileCfg default_tiles(const Geo &g);
 

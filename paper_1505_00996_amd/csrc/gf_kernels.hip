@@ -121,78 +121,90 @@ __device__ __forceinline__ float subsample_at(const T *__restrict__ img, int64_t
     return 0.5f * (0.5f * v00 + 0.5f * v01) + 0.5f * (0.5f * v10 + 0.5f * v11);
 }
 
-// ------------------------------------------------------- window-sum passes
+// ------------------------------------------------------- compensated sums
 //
-// A tile produces TH x kTileW low-res outputs from a region of
-// (TH + 2R) x (kTileW + 2R) samples.  The row pass writes, for every region
-// row, the horizontal window sums of two derived maps into LDS (rA, rB); each
-// thread owns kRun consecutive outputs of one row and slides its window.
-// The column pass gives every thread one column and TH/4 consecutive rows.
+// Window sums of the statistics are kept as unevaluated pairs hi + lo of
+// FP32 numbers (TwoSum / FMA-based TwoProduct).  This carries about 48
+// significant bits through the sums, so mean(I*I) - mean(I)^2 and
+// mean(I*p) - mean(I) mean(p) keep their accuracy when the window is almost
+// flat: a flat window gives var = cov = 0 up to ~1e-14 relative, far below
+// any eps.  FMA contraction is turned off inside these helpers because the
+// error terms rely on each operation being rounded on its own.
 
-// Row pass.  fu(ry, rx), fv(ry, rx) return region samples.  PAIR = false:
-// rA = sum u, rB = sum u*u.  PAIR = true: rA = sum v, rB = sum u*v.
-template <bool PAIR, class FU, class FV>
-__device__ __forceinline__ void row_pass(FU fu, FV fv, float *rA, float *rB, int SH, int R) {
-    constexpr int runs = kTileW / kRun;
-    for (int it = threadIdx.x; it < SH * runs; it += kThreads) {
-        const int ry = it / runs, j0 = (it % runs) * kRun;
-        float A = 0.f, B = 0.f;
-        for (int k = 0; k <= 2 * R; ++k) {
-            const float u = fu(ry, j0 + k);
-            if (PAIR) {
-                const float v = fv(ry, j0 + k);
-                A += v;
-                B += u * v;
-            } else {
-                A += u;
-                B += u * u;
-            }
-        }
-        float *oa = rA + ry * kTileW + j0, *ob = rB + ry * kTileW + j0;
-        oa[0] = A;
-        ob[0] = B;
-#pragma unroll
-        for (int t = 1; t < kRun; ++t) {
-            const float ui = fu(ry, j0 + t + 2 * R), uo = fu(ry, j0 + t - 1);
-            if (PAIR) {
-                const float vi = fv(ry, j0 + t + 2 * R), vo = fv(ry, j0 + t - 1);
-                A += vi - vo;
-                B += ui * vi - uo * vo;
-            } else {
-                A += ui - uo;
-                B += ui * ui - uo * uo;
-            }
-            oa[t] = A;
-            ob[t] = B;
-        }
-    }
+// (hi, lo) += x; the rounding error of hi + x goes to lo.
+__device__ __forceinline__ void df_add(float &hi, float &lo, float x) {
+#pragma clang fp contract(off)
+    const float s = hi + x;
+    const float bb = s - hi;
+    lo += (hi - (s - bb)) + (x - bb);
+    hi = s;
 }
 
-// Single-map row pass: rA = sum x.
-template <class FX>
-__device__ __forceinline__ void row_pass1(FX fx, float *rA, int SH, int R) {
-    constexpr int runs = kTileW / kRun;
-    for (int it = threadIdx.x; it < SH * runs; it += kThreads) {
-        const int ry = it / runs, j0 = (it % runs) * kRun;
-        float A = 0.f;
-        for (int k = 0; k <= 2 * R; ++k) A += fx(ry, j0 + k);
-        float *oa = rA + ry * kTileW + j0;
-        oa[0] = A;
+// (hi, lo) += u*v, the product split exactly as p + e with an FMA.
+__device__ __forceinline__ void df_add_prod(float &hi, float &lo, float u, float v) {
+#pragma clang fp contract(off)
+    const float p = u * v;
+    const float e = __builtin_fmaf(u, v, -p);
+    df_add(hi, lo, p);
+    lo += e;
+}
+
+// n*A - B*C for pairs A, B, C, evaluated with the leading products exact.
+__device__ __forceinline__ float df_det(float n, float ah, float al, float bh, float bl, float ch,
+                                        float cl) {
+#pragma clang fp contract(off)
+    const float p = n * ah;
+    const float pe = __builtin_fmaf(n, ah, -p);
+    const float q = bh * ch;
+    const float qe = __builtin_fmaf(bh, ch, -q);
+    const float s = p - q;
+    const float bb = s - p;
+    const float se = (p - (s - bb)) + (-q - bb);
+    const float lo = se + pe - qe + n * al - (bh * cl + bl * ch);
+    return s + lo;
+}
+
+// ------------------------------------------------------- staging helpers
+
+// Fill an SH x SW LDS region, wave w taking rows w, w+4, ...; loads are
+// issued in batches of kBatch before any LDS store so several global loads
+// are in flight per lane.
+constexpr int kBatch = 8;
+
+template <class F>
+__device__ __forceinline__ void fill_region(float *dst, int SH, int SW, F f) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ncol = (SW + 63) >> 6;
+    const int nitems = ((SH + 3 - wave) >> 2) * ncol;  // rows wave, wave+4, ... times column chunks
+    for (int base = 0; base < nitems; base += kBatch) {
+        float v[kBatch];
 #pragma unroll
-        for (int t = 1; t < kRun; ++t) {
-            A += fx(ry, j0 + t + 2 * R) - fx(ry, j0 + t - 1);
-            oa[t] = A;
+        for (int b = 0; b < kBatch; ++b) {
+            const int it = base + b;
+            const int ry = wave + 4 * (it / ncol), rx = lane + 64 * (it % ncol);
+            v[b] = (it < nitems && rx < SW) ? f(ry, rx) : 0.f;
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int it = base + b;
+            const int ry = wave + 4 * (it / ncol), rx = lane + 64 * (it % ncol);
+            if (it < nitems && rx < SW) dst[ry * SW + rx] = v[b];
         }
     }
 }
 
 // ---------------------------------------------------------------- k_coeff
 //
-// One workgroup = one low-res tile of TH x 64 outputs.  LDS holds the
-// mean-shifted samples of I' and of one channel of p' (when STAGE), and the
-// two row-sum buffers.  Channels of p are processed one after the other;
-// mean(I) and 1/(var+eps) stay in registers across them.
-template <typename T, int TH, bool STAGE>
+// One workgroup = one TH x TW tile of low-res outputs for ONE channel of p
+// (blockIdx.y).  Region: (TH + 2R) x (TW + 2R) samples of u = I' - cI and
+// v = p'_c - cP, where cI, cP are the samples at the tile's first output
+// (a per-tile mean shift).  Row pass: each thread slides a (2R+1)-wide
+// window over kRun consecutive outputs of one region row and writes the
+// compensated sums of u, u*u, v, u*v (8 floats) to LDS.  Column pass: each
+// thread owns one column and LC consecutive output rows, slides the same
+// sums down, and forms var, cov, a = cov/(var+eps), b = mean(p) - a mean(I)
+// (Eqs. 2-3), written to the coefficient planes a_c, b_c.
+template <typename T, int TH, int TW, bool STAGE>
 __global__ __launch_bounds__(kThreads) void k_coeff(const T *__restrict__ I, int64_t Irs,
                                                     const T *__restrict__ P, int64_t Prs, int64_t Pps,
                                                     float *__restrict__ coef, Geo g, int ntx,
@@ -200,119 +212,131 @@ __global__ __launch_bounds__(kThreads) void k_coeff(const T *__restrict__ I, int
     extern __shared__ float lds[];
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;  // uniform per workgroup: no barrier is skipped by part of it
-    constexpr int LC = TH / 4;   // rows per thread in the column pass
-    const int R = g.R, SH = TH + 2 * R, SW = kTileW + 2 * R;
-    const int ty0 = (tile / ntx) * TH, tx0 = (tile % ntx) * kTileW;
+    constexpr int RUNS = TW / kRun;           // row-pass runs per region row
+    constexpr int NG = kThreads / TW;         // column-pass row groups
+    constexpr int LC = TH / NG;               // output rows per thread in the column pass
+    static_assert(LC * NG == TH && RUNS * kRun == TW, "tile shape");
+    const int c = blockIdx.y;
+    const int R = g.R, SH = TH + 2 * R, SW = TW + 2 * R;
+    const int ty0 = (tile / ntx) * TH, tx0 = (tile % ntx) * TW;
     const int oy = ty0 - R, ox = tx0 - R;  // region origin in low-res coordinates
+    const T *Pc = P + (int64_t)c * Pps;
 
-    float *sI = lds;
-    float *sP = STAGE ? sI + SH * SW : nullptr;
-    float *rA = STAGE ? sP + SH * SW : lds;
-    float *rB = rA + SH * kTileW;
+    float *rs = lds;                      // 8 row-sum planes of SH x TW
+    float *sU = rs + 8 * SH * TW;         // staged u, v (STAGE only)
+    float *sV = sU + SH * SW;
+    const int plane = SH * TW;
 
-    // Mean-shift references: the samples at the tile's first output.
     const float cI = subsample_at(I, Irs, ty0, tx0, g);
-
+    const float cP = subsample_at(Pc, Prs, ty0, tx0, g);
     auto inside = [&](int ry, int rx) {
         const int ly = oy + ry, lx = ox + rx;
         return ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
     };
-    auto gI = [&](int ry, int rx) -> float {
+    auto gU = [&](int ry, int rx) -> float {
         return inside(ry, rx) ? subsample_at(I, Irs, oy + ry, ox + rx, g) - cI : 0.f;
     };
-    auto fill = [&](float *dst, const T *src, int64_t rs, float c) {
-        for (int e = threadIdx.x; e < SH * SW; e += kThreads) {
-            const int ry = e / SW, rx = e - ry * SW;
-            dst[e] = inside(ry, rx) ? subsample_at(src, rs, oy + ry, ox + rx, g) - c : 0.f;
-        }
+    auto gV = [&](int ry, int rx) -> float {
+        return inside(ry, rx) ? subsample_at(Pc, Prs, oy + ry, ox + rx, g) - cP : 0.f;
     };
+    auto lU = [&](int ry, int rx) -> float { return sU[ry * SW + rx]; };
+    auto lV = [&](int ry, int rx) -> float { return sV[ry * SW + rx]; };
 
-    const int col = threadIdx.x & 63, r0 = (threadIdx.x >> 6) * LC;
+    if (STAGE) {
+        fill_region(sU, SH, SW, gU);
+        fill_region(sV, SH, SW, gV);
+        __syncthreads();
+    }
+
+    // ---- row pass
+    for (int it = threadIdx.x; it < SH * RUNS; it += kThreads) {
+        const int ry = it / RUNS, j0 = (it % RUNS) * kRun;
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        auto add = [&](float u, float v) {
+            df_add(s[0], s[1], u);
+            df_add_prod(s[2], s[3], u, u);
+            df_add(s[4], s[5], v);
+            df_add_prod(s[6], s[7], u, v);
+        };
+        auto sub = [&](float u, float v) {  // remove the sample leaving the window
+            df_add(s[0], s[1], -u);
+            df_add_prod(s[2], s[3], -u, u);
+            df_add(s[4], s[5], -v);
+            df_add_prod(s[6], s[7], -u, v);
+        };
+        auto tap = [&](int rx, float &u, float &v) {
+            if (STAGE) {
+                u = lU(ry, rx);
+                v = lV(ry, rx);
+            } else {
+                u = gU(ry, rx);
+                v = gV(ry, rx);
+            }
+        };
+        for (int k = 0; k <= 2 * R; ++k) {
+            float u, v;
+            tap(j0 + k, u, v);
+            add(u, v);
+        }
+        float *o = rs + ry * TW + j0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) o[m * plane] = s[m];
+#pragma unroll
+        for (int t = 1; t < kRun; ++t) {
+            float ui, vi, uo, vo;
+            tap(j0 + t + 2 * R, ui, vi);
+            tap(j0 + t - 1, uo, vo);
+            add(ui, vi);
+            sub(uo, vo);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) o[t + m * plane] = s[m];
+        }
+    }
+    __syncthreads();
+
+    // ---- column pass
+    const int col = threadIdx.x % TW, r0 = (threadIdx.x / TW) * LC;
     const int lx = tx0 + col;
     const int nx = clip_len(lx, R, g.Wl);
-
-    // mean(I) and 1 / (var(I) + eps) for this thread's outputs
-    float mI[LC], inv[LC];
-    if (STAGE) {
-        fill(sI, I, Irs, cI);
-        __syncthreads();
-        row_pass<false>([&](int y, int x) { return sI[y * SW + x]; }, [](int, int) { return 0.f; },
-                        rA, rB, SH, R);
-    } else {
-        row_pass<false>(gI, [](int, int) { return 0.f; }, rA, rB, SH, R);
-    }
-    __syncthreads();
-    {
-        float A = 0.f, B = 0.f;
-        for (int k = 0; k <= 2 * R; ++k) {
-            A += rA[(r0 + k) * kTileW + col];
-            B += rB[(r0 + k) * kTileW + col];
-        }
+    float S[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    auto radd = [&](int row, float sign) {
+        const float *src = rs + row * TW + col;
 #pragma unroll
-        for (int t = 0; t < LC; ++t) {
-            if (t) {
-                A += rA[(r0 + t + 2 * R) * kTileW + col] - rA[(r0 + t - 1) * kTileW + col];
-                B += rB[(r0 + t + 2 * R) * kTileW + col] - rB[(r0 + t - 1) * kTileW + col];
-            }
-            const int n = max(1, clip_len(ty0 + r0 + t, R, g.Hl) * nx);
-            const float invn = 1.0f / (float)n;
-            const float m = A * invn;
-            const float var = fmaxf(B * invn - m * m, 0.f);
-            mI[t] = m;
-            inv[t] = 1.0f / (var + g.eps);
+        for (int m = 0; m < 8; m += 2) {
+            df_add(S[m], S[m + 1], sign * src[m * plane]);
+            S[m + 1] += sign * src[(m + 1) * plane];
         }
-    }
-    __syncthreads();
-
-    for (int c = 0; c < g.C; ++c) {
-        const T *Pc = P + (int64_t)c * Pps;
-        const float cP = subsample_at(Pc, Prs, ty0, tx0, g);
-        if (STAGE) {
-            fill(sP, Pc, Prs, cP);
-            __syncthreads();
-            row_pass<true>([&](int y, int x) { return sI[y * SW + x]; },
-                           [&](int y, int x) { return sP[y * SW + x]; }, rA, rB, SH, R);
-        } else {
-            row_pass<true>(gI,
-                           [&](int ry, int rx) -> float {
-                               return inside(ry, rx) ? subsample_at(Pc, Prs, oy + ry, ox + rx, g) - cP
-                                                     : 0.f;
-                           },
-                           rA, rB, SH, R);
-        }
-        __syncthreads();
-        float A = 0.f, B = 0.f;
-        for (int k = 0; k <= 2 * R; ++k) {
-            A += rA[(r0 + k) * kTileW + col];
-            B += rB[(r0 + k) * kTileW + col];
-        }
-        float *ac = coef + (int64_t)c * g.lps;
-        float *bc = coef + (int64_t)(g.C + c) * g.lps;
+    };
+    for (int k = 0; k <= 2 * R; ++k) radd(r0 + k, 1.f);
+    float *ac = coef + (int64_t)c * g.lps;
+    float *bc = coef + (int64_t)(g.C + c) * g.lps;
 #pragma unroll
-        for (int t = 0; t < LC; ++t) {
-            if (t) {
-                A += rA[(r0 + t + 2 * R) * kTileW + col] - rA[(r0 + t - 1) * kTileW + col];
-                B += rB[(r0 + t + 2 * R) * kTileW + col] - rB[(r0 + t - 1) * kTileW + col];
-            }
-            const int ly = ty0 + r0 + t;
-            if (ly < g.Hl && lx < g.Wl) {
-                const int n = clip_len(ly, R, g.Hl) * nx;
-                const float invn = 1.0f / (float)n;
-                const float mp = A * invn;                   // mean of p - cP
-                const float cov = B * invn - mI[t] * mp;     // Eq. 2 numerator
-                const float a = cov * inv[t];                // Eq. 2
-                const float b = (cP + mp) - a * (cI + mI[t]);  // Eq. 3
-                ac[(int64_t)ly * g.lrs + lx] = a;
-                bc[(int64_t)ly * g.lrs + lx] = b;
-            }
+    for (int t = 0; t < LC; ++t) {
+        if (t) {
+            radd(r0 + t + 2 * R, 1.f);
+            radd(r0 + t - 1, -1.f);
         }
-        __syncthreads();  // rA/rB (and sP) are rewritten by the next channel
+        const int ly = ty0 + r0 + t;
+        if (ly < g.Hl && lx < g.Wl) {
+            const float n = (float)(clip_len(ly, R, g.Hl) * nx);
+            const float n2 = n * n;
+            const float var = fmaxf(df_det(n, S[2], S[3], S[0], S[1], S[0], S[1]) / n2, 0.f);
+            const float cov = df_det(n, S[6], S[7], S[0], S[1], S[4], S[5]) / n2;  // Eq. 2 numerator
+            const float mI = cI + (S[0] + S[1]) / n;
+            const float mp = cP + (S[4] + S[5]) / n;
+            const float a = cov / (var + g.eps);  // Eq. 2
+            const float b = mp - a * mI;          // Eq. 3
+            ac[(int64_t)ly * g.lrs + lx] = a;
+            bc[(int64_t)ly * g.lrs + lx] = b;
+        }
     }
 }
 
 // ---------------------------------------------------------------- k_box
 //
-// Clip-normalised box mean of one low-res FP32 plane per blockIdx.y.
+// Clip-normalised box mean of one low-res FP32 plane per blockIdx.y (the
+// coefficient maps a_c, b_c: Algorithm 2 step 5).  Same row / column pass
+// structure as k_coeff with plain FP32 sums (no cancellation here).
 template <int TH, bool STAGE>
 __global__ __launch_bounds__(kThreads) void k_box(const float *__restrict__ src,
                                                   float *__restrict__ dst, Geo g, int ntx,
@@ -320,39 +344,46 @@ __global__ __launch_bounds__(kThreads) void k_box(const float *__restrict__ src,
     extern __shared__ float lds[];
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;
-    constexpr int LC = TH / 4;
-    const int R = g.R, SH = TH + 2 * R, SW = kTileW + 2 * R;
-    const int ty0 = (tile / ntx) * TH, tx0 = (tile % ntx) * kTileW;
+    constexpr int TW = kTileW, RUNS = TW / kRun, NG = kThreads / TW, LC = TH / NG;
+    const int R = g.R, SH = TH + 2 * R, SW = TW + 2 * R;
+    const int ty0 = (tile / ntx) * TH, tx0 = (tile % ntx) * TW;
     const int oy = ty0 - R, ox = tx0 - R;
     const float *S = src + (int64_t)blockIdx.y * g.lps;
     float *D = dst + (int64_t)blockIdx.y * g.lps;
 
-    float *sX = lds;
-    float *rA = STAGE ? sX + SH * SW : lds;
+    float *rA = lds;
+    float *sX = rA + SH * TW;
     auto gX = [&](int ry, int rx) -> float {
         const int ly = oy + ry, lx = ox + rx;
         return (ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl) ? S[(int64_t)ly * g.lrs + lx] : 0.f;
     };
     if (STAGE) {
-        for (int e = threadIdx.x; e < SH * SW; e += kThreads) {
-            const int ry = e / SW, rx = e - ry * SW;
-            sX[e] = gX(ry, rx);
-        }
+        fill_region(sX, SH, SW, gX);
         __syncthreads();
-        row_pass1([&](int y, int x) { return sX[y * SW + x]; }, rA, SH, R);
-    } else {
-        row_pass1(gX, rA, SH, R);
+    }
+    for (int it = threadIdx.x; it < SH * RUNS; it += kThreads) {
+        const int ry = it / RUNS, j0 = (it % RUNS) * kRun;
+        auto x = [&](int rx) -> float { return STAGE ? sX[ry * SW + rx] : gX(ry, rx); };
+        float A = 0.f;
+        for (int k = 0; k <= 2 * R; ++k) A += x(j0 + k);
+        float *oa = rA + ry * TW + j0;
+        oa[0] = A;
+#pragma unroll
+        for (int t = 1; t < kRun; ++t) {
+            A += x(j0 + t + 2 * R) - x(j0 + t - 1);
+            oa[t] = A;
+        }
     }
     __syncthreads();
 
-    const int col = threadIdx.x & 63, r0 = (threadIdx.x >> 6) * LC;
+    const int col = threadIdx.x % TW, r0 = (threadIdx.x / TW) * LC;
     const int lx = tx0 + col;
     const int nx = clip_len(lx, R, g.Wl);
     float A = 0.f;
-    for (int k = 0; k <= 2 * R; ++k) A += rA[(r0 + k) * kTileW + col];
+    for (int k = 0; k <= 2 * R; ++k) A += rA[(r0 + k) * TW + col];
 #pragma unroll
     for (int t = 0; t < LC; ++t) {
-        if (t) A += rA[(r0 + t + 2 * R) * kTileW + col] - rA[(r0 + t - 1) * kTileW + col];
+        if (t) A += rA[(r0 + t + 2 * R) * TW + col] - rA[(r0 + t - 1) * TW + col];
         const int ly = ty0 + r0 + t;
         if (ly < g.Hl && lx < g.Wl) {
             const int n = clip_len(ly, R, g.Hl) * nx;
@@ -364,46 +395,59 @@ __global__ __launch_bounds__(kThreads) void k_box(const float *__restrict__ src,
 // ---------------------------------------------------------------- k_output
 //
 // One workgroup = 4 waves; a wave covers 256 full-res columns (4 per lane)
-// and `rows` consecutive rows.  Each lane computes its horizontal taps and
-// weights once, keeps the horizontally interpolated mean_a, mean_b of the
-// two low-res rows that bracket the current full-res row in registers, and
-// reloads them only when the bracket moves (every s rows).  q = a*I + b is
-// written with non-temporal 16-byte stores.  CC channels, starting at c0.
-// S is the compile-time ratio (0 = read g.s at run time).
-template <typename T, int CC, int S>
+// and ROWS = 8 consecutive rows starting at a multiple of 8.  A lane first
+// loads its 8 x 4 guide pixels (all loads in flight together); then, channel
+// by channel, it loads the low-res rows and columns of mean_a, mean_b that
+// its pixels interpolate from, interpolates them horizontally once, and for
+// every row finishes the bilinear weights and writes q = a*I + b with
+// non-temporal 16-byte stores.
+//
+// Upsampling geometry (half-pixel centres): full-res x maps to low-res
+// u = (x + 0.5)/s - 0.5 = (2x + 1 - s) / (2s), taps floor(u), floor(u) + 1
+// clamped to the map.  For s in {2, 4, 8}, lanes start at x0 = 0 mod 4 and
+// waves at y = 0 mod 8, so which low-res rows/columns each pixel uses,
+// relative to the first one, is known at compile time.
+
+// floor((2x + 1 - s) / (2s)) for compile-time use
+constexpr int cfloor_u(int x, int s) {
+    return (2 * x + 1 - s) >= 0 ? (2 * x + 1 - s) / (2 * s) : -((2 * s - 1 - (2 * x + 1 - s)) / (2 * s));
+}
+constexpr float cfrac_u(int x, int s) {
+    return (float)((2 * x + 1 - s) - 2 * s * cfloor_u(x, s)) / (float)(2 * s);
+}
+
+template <typename T, int CC, int S, int ROWS>
 __global__ __launch_bounds__(kThreads) void k_output(const T *__restrict__ I, int64_t Irs,
                                                      T *__restrict__ Q, int64_t Qrs, int64_t Qps,
                                                      const float *__restrict__ M, Geo g, int c0,
-                                                     int ntx, int ntiles, int rows, int vec) {
+                                                     int ntx, int ntiles, int vec) {
+    static_assert(ROWS == 8, "row patterns assume waves start at multiples of 8");
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int x0 = (tile % ntx) * kOutTileW + lane * kOutPx;
-    const int yb = (tile / ntx) * (4 * rows) + wave * rows;
-    const int ye = min(yb + rows, g.H);
-    if (x0 >= g.W || yb >= ye) return;  // no barriers below
+    const int yb = (tile / ntx) * (4 * ROWS) + wave * ROWS;
+    const int nrows = min(ROWS, g.H - yb);
+    if (x0 >= g.W || nrows <= 0) return;  // no barriers below
     const bool full = vec && (x0 + 3 < g.W);
 
-    const float *Ma[CC], *Mb[CC];
-    T *Qc[CC];
+    f32x4 iv[ROWS];
 #pragma unroll
-    for (int c = 0; c < CC; ++c) {
-        Ma[c] = M + (int64_t)(c0 + c) * g.lps;
-        Mb[c] = M + (int64_t)(g.C + c0 + c) * g.lps;
-        Qc[c] = Q + (int64_t)c * Qps;
+    for (int i = 0; i < ROWS; ++i) {
+        iv[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (i < nrows) {
+            const T *row = I + (int64_t)(yb + i) * Irs + x0;
+            if (full) {
+                iv[i] = ld4(row);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (x0 + j < g.W) iv[i][j] = ld(row + j);
+            }
+        }
     }
-
-    auto load_I = [&](int y) -> f32x4 {
-        const T *row = I + (int64_t)y * Irs + x0;
-        if (full) return ld4(row);
-        f32x4 v = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (x0 + j < g.W) v[j] = ld(row + j);
-        return v;
-    };
-    auto store_q = [&](int c, int y, f32x4 v) {
-        T *row = Qc[c] + (int64_t)y * Qrs + x0;
+    auto store_q = [&](T *plane, int y, f32x4 v) {
+        T *row = plane + (int64_t)y * Qrs + x0;
         if (full) {
             st4(row, v);
         } else {
@@ -416,21 +460,82 @@ __global__ __launch_bounds__(kThreads) void k_output(const T *__restrict__ I, in
     if constexpr (S == 1) {
         // Algorithm 1: the maps are full resolution; rows are padded to a
         // multiple of 16 floats, so the 16-byte read at x0 stays in the row.
-        for (int y = yb; y < ye; ++y) {
-            const f32x4 iv = load_I(y);
+#pragma unroll 1
+        for (int c = 0; c < CC; ++c) {
+            const float *Ma = M + (int64_t)(c0 + c) * g.lps;
+            const float *Mb = M + (int64_t)(g.C + c0 + c) * g.lps;
+            T *Qc = Q + (int64_t)c * Qps;
 #pragma unroll
-            for (int c = 0; c < CC; ++c) {
-                const f32x4 a = ld4(Ma[c] + (int64_t)y * g.lrs + x0);
-                const f32x4 b = ld4(Mb[c] + (int64_t)y * g.lrs + x0);
-                store_q(c, y, a * iv + b);
+            for (int i = 0; i < ROWS; ++i) {
+                if (i < nrows) {
+                    const int y = yb + i;
+                    const f32x4 a = ld4(Ma + (int64_t)y * g.lrs + x0);
+                    const f32x4 b = ld4(Mb + (int64_t)y * g.lrs + x0);
+                    store_q(Qc, y, a * iv[i] + b);
+                }
             }
         }
-        return;
+    } else if constexpr (S == 2 || S == 4 || S == 8) {
+        // low-res rows base_y .. base_y + NL - 1 and columns base_x .. base_x + NC - 1
+        constexpr int NL = cfloor_u(ROWS - 1, S) - cfloor_u(0, S) + 2;
+        constexpr int NC = cfloor_u(3, S) - cfloor_u(0, S) + 2;
+        const int base_y = floordiv(2 * yb + 1 - S, 2 * S);
+        const int base_x = floordiv(2 * x0 + 1 - S, 2 * S);
+        int ry[NL], cx[NC];
+#pragma unroll
+        for (int m = 0; m < NL; ++m) ry[m] = clampi(base_y + m, 0, g.Hl - 1);
+#pragma unroll
+        for (int m = 0; m < NC; ++m) cx[m] = clampi(base_x + m, 0, g.Wl - 1);
+        // horizontal weights: compile time when s divides 4; for s = 8 they
+        // depend on whether the lane starts at 0 or 4 mod 8
+        float wx[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            wx[j] = (S == 8) ? (float)((2 * ((x0 & 7) + j) + 1 - 8) & 15) * (1.0f / 16.0f)
+                             : cfrac_u(j, S);
+#pragma unroll 1
+        for (int c = 0; c < CC; ++c) {
+            const float *Ma = M + (int64_t)(c0 + c) * g.lps;
+            const float *Mb = M + (int64_t)(g.C + c0 + c) * g.lps;
+            T *Qc = Q + (int64_t)c * Qps;
+            float ha[NL][4], hb[NL][4];
+#pragma unroll
+            for (int m = 0; m < NL; ++m) {
+                const float *ra = Ma + (int64_t)ry[m] * g.lrs;
+                const float *rb = Mb + (int64_t)ry[m] * g.lrs;
+                float va[NC], vb[NC];
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    va[k] = ra[cx[k]];
+                    vb[k] = rb[cx[k]];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k0 = cfloor_u(j, S) - cfloor_u(0, S);  // 0 for s = 8 as well
+                    ha[m][j] = va[k0] + wx[j] * (va[k0 + 1] - va[k0]);
+                    hb[m][j] = vb[k0] + wx[j] * (vb[k0 + 1] - vb[k0]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < ROWS; ++i) {
+                if (i < nrows) {
+                    const int m0 = cfloor_u(i, S) - cfloor_u(0, S);
+                    const float wy = cfrac_u(i, S);
+                    f32x4 out;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float a = ha[m0][j] + wy * (ha[m0 + 1][j] - ha[m0][j]);
+                        const float b = hb[m0][j] + wy * (hb[m0 + 1][j] - hb[m0][j]);
+                        out[j] = a * iv[i][j] + b;
+                    }
+                    store_q(Qc, yb + i, out);
+                }
+            }
+        }
     } else {
-        const int s = S ? S : g.s;
-        const int s2 = 2 * s;
+        // any other ratio: taps computed per pixel and per row at run time
+        const int s = g.s, s2 = 2 * s;
         const float inv2s = 1.0f / (float)s2;
-        // Horizontal taps: u = (x + 0.5)/s - 0.5 = (2x + 1 - s) / (2s).
         int xa[4], xb[4];
         float wx[4];
 #pragma unroll
@@ -441,65 +546,34 @@ __global__ __launch_bounds__(kThreads) void k_output(const T *__restrict__ I, in
             xa[j] = clampi(l, 0, g.Wl - 1);
             xb[j] = clampi(l + 1, 0, g.Wl - 1);
         }
-        // h[c][j]: mean_a, mean_b of low-res row k interpolated at column x0+j
-        float ha0[CC][4], hb0[CC][4], ha1[CC][4], hb1[CC][4];
-        auto hrow = [&](int k, float (&ha)[CC][4], float (&hb)[CC][4]) {
+#pragma unroll 1
+        for (int c = 0; c < CC; ++c) {
+            const float *Ma = M + (int64_t)(c0 + c) * g.lps;
+            const float *Mb = M + (int64_t)(g.C + c0 + c) * g.lps;
+            T *Qc = Q + (int64_t)c * Qps;
+#pragma unroll 1
+            for (int i = 0; i < nrows; ++i) {
+                const int y = yb + i;
+                const int num = 2 * y + 1 - s;
+                const int l = floordiv(num, s2);
+                const float wy = (float)(num - s2 * l) * inv2s;
+                const int k0 = clampi(l, 0, g.Hl - 1), k1 = clampi(l + 1, 0, g.Hl - 1);
+                const float *ra0 = Ma + (int64_t)k0 * g.lrs, *ra1 = Ma + (int64_t)k1 * g.lrs;
+                const float *rb0 = Mb + (int64_t)k0 * g.lrs, *rb1 = Mb + (int64_t)k1 * g.lrs;
+                f32x4 iy = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int c = 0; c < CC; ++c) {
-                const float *ra = Ma[c] + (int64_t)k * g.lrs;
-                const float *rb = Mb[c] + (int64_t)k * g.lrs;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float a0 = ra[xa[j]], a1 = ra[xb[j]];
-                    const float b0 = rb[xa[j]], b1 = rb[xb[j]];
-                    ha[c][j] = a0 + wx[j] * (a1 - a0);
-                    hb[c][j] = b0 + wx[j] * (b1 - b0);
-                }
-            }
-        };
-        int k0c = -1, k1c = -1;
-        for (int y = yb; y < ye; ++y) {
-            const f32x4 iv = load_I(y);
-            const int num = 2 * y + 1 - s;
-            const int l = floordiv(num, s2);
-            const float wy = (float)(num - s2 * l) * inv2s;
-            const int k0 = clampi(l, 0, g.Hl - 1), k1 = clampi(l + 1, 0, g.Hl - 1);
-            if (k0 != k0c || k1 != k1c) {  // uniform across the wave
-                if (k0 == k1c) {
-#pragma unroll
-                    for (int c = 0; c < CC; ++c)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            ha0[c][j] = ha1[c][j];
-                            hb0[c][j] = hb1[c][j];
-                        }
-                } else {
-                    hrow(k0, ha0, hb0);
-                }
-                if (k1 == k0) {
-#pragma unroll
-                    for (int c = 0; c < CC; ++c)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            ha1[c][j] = ha0[c][j];
-                            hb1[c][j] = hb0[c][j];
-                        }
-                } else {
-                    hrow(k1, ha1, hb1);
-                }
-                k0c = k0;
-                k1c = k1;
-            }
-#pragma unroll
-            for (int c = 0; c < CC; ++c) {
+                for (int r = 0; r < ROWS; ++r)
+                    if (r == i) iy = iv[r];
                 f32x4 out;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const float a = ha0[c][j] + wy * (ha1[c][j] - ha0[c][j]);
-                    const float b = hb0[c][j] + wy * (hb1[c][j] - hb0[c][j]);
-                    out[j] = a * iv[j] + b;
+                    const float a0 = ra0[xa[j]] + wx[j] * (ra0[xb[j]] - ra0[xa[j]]);
+                    const float a1 = ra1[xa[j]] + wx[j] * (ra1[xb[j]] - ra1[xa[j]]);
+                    const float b0 = rb0[xa[j]] + wx[j] * (rb0[xb[j]] - rb0[xa[j]]);
+                    const float b1 = rb1[xa[j]] + wx[j] * (rb1[xb[j]] - rb1[xa[j]]);
+                    out[j] = (a0 + wy * (a1 - a0)) * iy[j] + (b0 + wy * (b1 - b0));
                 }
-                store_q(c, y, out);
+                store_q(Qc, y, out);
             }
         }
     }
@@ -520,21 +594,28 @@ void allow_lds(K kernel, size_t bytes) {
 template <typename T>
 hipError_t coeff_t(const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
                    hipStream_t st) {
-    const int ntx = (g.Wl + kTileW - 1) / kTileW;
+    const int ntx = (g.Wl + t.coeff_tw - 1) / t.coeff_tw;
     const int nty = (g.Hl + t.coeff_th - 1) / t.coeff_th;
     const int ntiles = ntx * nty;
-    const size_t lds = coeff_lds_bytes(t.coeff_th, t.coeff_stage, g.R);
+    const size_t lds = coeff_lds_bytes(t.coeff_th, t.coeff_tw, t.coeff_stage, g.R);
     const T *Ip = (const T *)I.data, *Pp = (const T *)P.data;
-    const dim3 grid(grid8(ntiles)), block(kThreads);
-#define GF_COEFF(TH, STG)                                                                     \
-    allow_lds(k_coeff<T, TH, STG>, lds);                                                      \
-    hipLaunchKernelGGL((k_coeff<T, TH, STG>), grid, block, lds, st, Ip, I.rs, Pp, P.rs, P.ps, \
-                       coef, g, ntx, ntiles)
-    if (t.coeff_th == 32) {
-        if (t.coeff_stage) { GF_COEFF(32, true); } else { GF_COEFF(32, false); }
-    } else {
-        if (t.coeff_stage) { GF_COEFF(16, true); } else { GF_COEFF(16, false); }
+    const dim3 grid(grid8(ntiles), g.C), block(kThreads);
+#define GF_COEFF(TH, TW, STG)                                                                     \
+    {                                                                                             \
+        allow_lds(k_coeff<T, TH, TW, STG>, lds);                                                  \
+        hipLaunchKernelGGL((k_coeff<T, TH, TW, STG>), grid, block, lds, st, Ip, I.rs, Pp, P.rs,  \
+                           P.ps, coef, g, ntx, ntiles);                                           \
     }
+#define GF_COEFF_S(TH, TW) \
+    if (t.coeff_stage) GF_COEFF(TH, TW, true) else GF_COEFF(TH, TW, false)
+    if (t.coeff_th == 32) {
+        if (t.coeff_tw == 64) GF_COEFF_S(32, 64) else GF_COEFF_S(32, 32)
+    } else if (t.coeff_th == 16) {
+        if (t.coeff_tw == 64) GF_COEFF_S(16, 64) else GF_COEFF_S(16, 32)
+    } else {
+        if (t.coeff_tw == 64) GF_COEFF_S(8, 64) else GF_COEFF_S(8, 32)
+    }
+#undef GF_COEFF_S
 #undef GF_COEFF
     return hipGetLastError();
 }
@@ -542,15 +623,17 @@ hipError_t coeff_t(const View &I, const View &P, float *coef, const Geo &g, cons
 template <typename T, int CC>
 hipError_t output_cc(const View &I, const View &Q, const float *mean, const Geo &g, int c0,
                      const TileCfg &t, bool vec, hipStream_t st) {
+    constexpr int ROWS = 8;
     const int ntx = (g.W + kOutTileW - 1) / kOutTileW;
-    const int nty = (g.H + 4 * t.out_rows - 1) / (4 * t.out_rows);
+    const int nty = (g.H + 4 * ROWS - 1) / (4 * ROWS);
     const int ntiles = ntx * nty;
     const T *Ip = (const T *)I.data;
     T *Qp = (T *)Q.data + (int64_t)c0 * Q.ps;
     const dim3 grid(grid8(ntiles)), block(kThreads);
-#define GF_OUT(SS)                                                                         \
-    hipLaunchKernelGGL((k_output<T, CC, SS>), grid, block, 0, st, Ip, I.rs, Qp, Q.rs, Q.ps, \
-                       mean, g, c0, ntx, ntiles, t.out_rows, (int)vec)
+    (void)t;
+#define GF_OUT(SS)                                                                               \
+    hipLaunchKernelGGL((k_output<T, CC, SS, ROWS>), grid, block, 0, st, Ip, I.rs, Qp, Q.rs, Q.ps, \
+                       mean, g, c0, ntx, ntiles, (int)vec)
     switch (g.s) {
         case 1: GF_OUT(1); break;
         case 2: GF_OUT(2); break;
@@ -593,13 +676,17 @@ hipError_t launch_box(const float *src, float *dst, const Geo &g, const TileCfg 
     const int ntiles = ntx * nty;
     const size_t lds = box_lds_bytes(t.box_th, t.box_stage, g.R);
     const dim3 grid(grid8(ntiles), 2 * g.C), block(kThreads);
-#define GF_BOX(TH, STG)                 \
-    allow_lds(k_box<TH, STG>, lds); \
-    hipLaunchKernelGGL((k_box<TH, STG>), grid, block, lds, st, src, dst, g, ntx, ntiles)
+#define GF_BOX(TH, STG)                                                                    \
+    {                                                                                      \
+        allow_lds(k_box<TH, STG>, lds);                                                    \
+        hipLaunchKernelGGL((k_box<TH, STG>), grid, block, lds, st, src, dst, g, ntx, ntiles); \
+    }
     if (t.box_th == 32) {
-        if (t.box_stage) { GF_BOX(32, true); } else { GF_BOX(32, false); }
+        if (t.box_stage) GF_BOX(32, true) else GF_BOX(32, false)
+    } else if (t.box_th == 16) {
+        if (t.box_stage) GF_BOX(16, true) else GF_BOX(16, false)
     } else {
-        if (t.box_stage) { GF_BOX(16, true); } else { GF_BOX(16, false); }
+        if (t.box_stage) GF_BOX(8, true) else GF_BOX(8, false)
     }
 #undef GF_BOX
     return hipGetLastError();
