@@ -52,40 +52,63 @@ Geo make_geo(int H, int W, int C, int r, int s, double eps, int sub) {
     return g;
 }
 
-size_t coeff_lds_bytes(int th, int tw, int stage, int R) {
-    // 8 planes of compensated row sums, plus the staged u and v samples
-    const size_t SH = th + 2 * R, SW = tw + 2 * R;
-    return sizeof(float) * (8 * SH * tw + (stage ? 2 * SH * SW : 0));
+size_t coeff_lds_bytes(const TileCfg &t, int R) {
+    if (t.coeff_slide) {  // staged u, v for 64 + 2R columns and 4*th + 2R rows
+        const size_t SH = 4 * t.coeff_th + 2 * R, SW = 64 + 2 * R;
+        return sizeof(float) * 2 * SH * SW;
+    }
+    // 4 planes of FP64 row sums, plus the staged u and v samples
+    const size_t SH = t.coeff_th + 2 * R, SW = t.coeff_tw + 2 * R;
+    return sizeof(double) * 4 * SH * t.coeff_tw + (t.coeff_stage ? sizeof(float) * 2 * SH * SW : 0);
 }
 
-size_t box_lds_bytes(int th, int stage, int R) {
-    const size_t SH = th + 2 * R, SW = kTileW + 2 * R;
-    return sizeof(float) * (SH * kTileW + (stage ? SH * SW : 0));
+size_t box_lds_bytes(const TileCfg &t, int R) {
+    if (t.box_slide) {
+        const size_t SH = 4 * t.box_th + 2 * R, SW = 64 + 2 * R;
+        return sizeof(float) * SH * SW;
+    }
+    const size_t SH = t.box_th + 2 * R, SW = kTileW + 2 * R;
+    return sizeof(double) * SH * kTileW + (t.box_stage ? sizeof(float) * SH * SW : 0);
 }
 
 static const size_t kLdsMax = 160 * 1024;
-static const size_t kStageMax = 64 * 1024;
+static const size_t kStageMax = 100 * 1024;
+static const int kSlideMaxR = 8;  // above this the separable passes do fewer operations
 
 TileCfg default_tiles(const Geo &g) {
     TileCfg t;
-    t.coeff_th = 16;
-    t.coeff_tw = g.R <= 8 ? 64 : 32;
-    t.coeff_stage = coeff_lds_bytes(t.coeff_th, t.coeff_tw, 1, g.R) <= kStageMax;
-    if (!t.coeff_stage && coeff_lds_bytes(t.coeff_th, t.coeff_tw, 0, g.R) > kLdsMax) t.coeff_th = 8;
-    t.box_th = g.R <= 8 ? 32 : 16;
-    t.box_stage = box_lds_bytes(t.box_th, 1, g.R) <= kStageMax;
-    if (!t.box_stage && box_lds_bytes(t.box_th, 0, g.R) > kLdsMax) t.box_th = 8;
-    t.out_rows = 8;
+    t.coeff_slide = g.R <= kSlideMaxR;
+    t.box_slide = g.R <= kSlideMaxR;
+    if (t.coeff_slide) {
+        t.coeff_th = 8;
+        t.coeff_tw = 64;
+        t.coeff_stage = 1;
+    } else {
+        t.coeff_th = 16;
+        t.coeff_tw = 32;
+        t.coeff_stage = 1;
+        if (coeff_lds_bytes(t, g.R) > kStageMax) t.coeff_stage = 0;
+        if (coeff_lds_bytes(t, g.R) > kLdsMax) t.coeff_th = 8;
+    }
+    if (t.box_slide) {
+        t.box_th = 8;
+        t.box_stage = 1;
+    } else {
+        t.box_th = 16;
+        t.box_stage = 1;
+        if (box_lds_bytes(t, g.R) > kStageMax) t.box_stage = 0;
+        if (box_lds_bytes(t, g.R) > kLdsMax) t.box_th = 8;
+    }
     return t;
 }
 
 bool tiles_fit(const Geo &g, const TileCfg &t) {
-    const bool shapes = (t.coeff_th == 8 || t.coeff_th == 16 || t.coeff_th == 32) &&
-                        (t.coeff_tw == 32 || t.coeff_tw == 64) &&
-                        (t.box_th == 8 || t.box_th == 16 || t.box_th == 32) && t.out_rows >= 1 &&
-                        t.out_rows <= 64;
-    return shapes && coeff_lds_bytes(t.coeff_th, t.coeff_tw, t.coeff_stage, g.R) <= kLdsMax &&
-           box_lds_bytes(t.box_th, t.box_stage, g.R) <= kLdsMax;
+    const bool cs = t.coeff_slide ? (t.coeff_th == 4 || t.coeff_th == 8 || t.coeff_th == 16)
+                                  : ((t.coeff_th == 8 || t.coeff_th == 16 || t.coeff_th == 32) &&
+                                     (t.coeff_tw == 32 || t.coeff_tw == 64));
+    const bool bs = t.box_slide ? (t.box_th == 4 || t.box_th == 8 || t.box_th == 16)
+                                : (t.box_th == 8 || t.box_th == 16 || t.box_th == 32);
+    return cs && bs && coeff_lds_bytes(t, g.R) <= kLdsMax && box_lds_bytes(t, g.R) <= kLdsMax;
 }
 
 size_t workspace_bytes(const Geo &g) {

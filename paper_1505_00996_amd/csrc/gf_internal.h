@@ -30,12 +30,13 @@ struct View {
 
 // Tile shapes for one call (picked by the host heuristic or the tuner).
 struct TileCfg {
-    int coeff_th;     // rows per tile of the coefficient kernel (8, 16 or 32)
-    int coeff_tw;     // columns per tile of the coefficient kernel (32 or 64)
-    int coeff_stage;  // 1: stage the low-res tile in LDS, 0: read through the caches
-    int box_th;       // rows per tile of the box-mean kernel (8, 16 or 32)
+    int coeff_slide;  // 1: sliding-window kernel (tile 64 x 4*coeff_th), 0: separable passes
+    int coeff_th;     // slide: rows per wave (4, 8, 16); separable: tile rows (8, 16, 32)
+    int coeff_tw;     // separable: tile columns (32 or 64)
+    int coeff_stage;  // separable: 1 = stage the samples in LDS, 0 = read through the caches
+    int box_slide;    // same choices for the box-mean kernel (tile width 64)
+    int box_th;
     int box_stage;
-    int out_rows;     // full-res rows per wave of the output kernel
 };
 
 constexpr int kThreads = 256;   // threads per workgroup for every kernel
@@ -43,11 +44,11 @@ constexpr int kTileW = 64;      // low-res tile width of the window-sum kernels
 constexpr int kRun = 8;         // consecutive outputs per thread in a row pass
 constexpr int kOutPx = 4;       // full-res pixels per lane in the output kernel
 constexpr int kOutTileW = 64 * kOutPx;  // full-res columns per output tile
-constexpr int kMaxRadius = 72;  // largest low-res radius the LDS row buffers hold
+constexpr int kMaxRadius = 64;  // largest low-res radius the LDS row buffers hold
 
 Geo make_geo(int H, int W, int C, int r, int s, double eps, int sub);
-size_t coeff_lds_bytes(int th, int tw, int stage, int R);
-size_t box_lds_bytes(int th, int stage, int R);
+size_t coeff_lds_bytes(const TileCfg &t, int R);
+size_t box_lds_bytes(const TileCfg &t, int R);
 TileCfg default_tiles(const Geo &g);
 
 // Kernel launchers (gf_kernels.hip).  All return the launch status.

@@ -2,10 +2,12 @@
 //
 // Three kernels carry Algorithm 2 of He & Sun, "Fast Guided Filter":
 //   k_coeff  : subsample I and p (step 1) while loading a low-res tile plus an
-//              r' halo, form the window sums of I', I'^2, p', I'p' with a
-//              separable row pass (LDS) and column pass (registers) (step 2),
-//              then var, cov (step 3) and a, b of Eqs. 2-3 (step 4).
-//   k_box    : clip-normalised box mean of the 2C coefficient maps (step 5).
+//              r' halo into LDS, form the window sums of I', I'^2, p', I'p'
+//              (step 2), then var, cov (step 3) and a, b of Eqs. 2-3 (step 4).
+//              Two variants: a sliding-window walk for small r', a separable
+//              row pass + column pass for large r'.
+//   k_box    : clip-normalised box mean of the 2C coefficient maps (step 5),
+//              with the same two variants.
 //   k_output : bilinear upsampling of mean_a, mean_b fused with
 //              q = mean_a * I + mean_b against the full-resolution I
 //              (steps 6-7).  This is the HBM-bound pass: I is read once and q
@@ -14,11 +16,9 @@
 // Algorithm 1 is the same three kernels at s = 1, where subsampling and
 // upsampling are identities and k_output reads mean_a, mean_b directly.
 //
-// Numerics: window sums are FP32.  Each k_coeff tile subtracts a reference
-// value (its first low-res sample of I and of each p channel) before
-// summing, so var = E[(I-c)^2] - E[I-c]^2 does not cancel two numbers near
-// mean(I)^2; sums are restarted every tile and slide over at most kRun
-// outputs, so rounding does not drift across the image.
+// Numerics: samples and coefficients are FP32; window sums are accumulated
+// in FP64 (see the coefficient section) and restarted in every tile, so
+// rounding neither cancels in flat windows nor drifts across the image.
 #include <hip/hip_runtime.h>
 
 #include "gf_internal.h"
@@ -121,49 +121,6 @@ __device__ __forceinline__ float subsample_at(const T *__restrict__ img, int64_t
     return 0.5f * (0.5f * v00 + 0.5f * v01) + 0.5f * (0.5f * v10 + 0.5f * v11);
 }
 
-// ------------------------------------------------------- compensated sums
-//
-// Window sums of the statistics are kept as unevaluated pairs hi + lo of
-// FP32 numbers (TwoSum / FMA-based TwoProduct).  This carries about 48
-// significant bits through the sums, so mean(I*I) - mean(I)^2 and
-// mean(I*p) - mean(I) mean(p) keep their accuracy when the window is almost
-// flat: a flat window gives var = cov = 0 up to ~1e-14 relative, far below
-// any eps.  FMA contraction is turned off inside these helpers because the
-// error terms rely on each operation being rounded on its own.
-
-// (hi, lo) += x; the rounding error of hi + x goes to lo.
-__device__ __forceinline__ void df_add(float &hi, float &lo, float x) {
-#pragma clang fp contract(off)
-    const float s = hi + x;
-    const float bb = s - hi;
-    lo += (hi - (s - bb)) + (x - bb);
-    hi = s;
-}
-
-// (hi, lo) += u*v, the product split exactly as p + e with an FMA.
-__device__ __forceinline__ void df_add_prod(float &hi, float &lo, float u, float v) {
-#pragma clang fp contract(off)
-    const float p = u * v;
-    const float e = __builtin_fmaf(u, v, -p);
-    df_add(hi, lo, p);
-    lo += e;
-}
-
-// n*A - B*C for pairs A, B, C, evaluated with the leading products exact.
-__device__ __forceinline__ float df_det(float n, float ah, float al, float bh, float bl, float ch,
-                                        float cl) {
-#pragma clang fp contract(off)
-    const float p = n * ah;
-    const float pe = __builtin_fmaf(n, ah, -p);
-    const float q = bh * ch;
-    const float qe = __builtin_fmaf(bh, ch, -q);
-    const float s = p - q;
-    const float bb = s - p;
-    const float se = (p - (s - bb)) + (-q - bb);
-    const float lo = se + pe - qe + n * al - (bh * cl + bl * ch);
-    return s + lo;
-}
-
 // ------------------------------------------------------- staging helpers
 
 // Fill an SH x SW LDS region, wave w taking rows w, w+4, ...; loads are
@@ -171,18 +128,18 @@ __device__ __forceinline__ float df_det(float n, float ah, float al, float bh, f
 // are in flight per lane.
 constexpr int kBatch = 8;
 
-template <class F>
-__device__ __forceinline__ void fill_region(float *dst, int SH, int SW, F f) {
+template <typename V, class F>
+__device__ __forceinline__ void fill_region(V *dst, int SH, int SW, F f) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ncol = (SW + 63) >> 6;
     const int nitems = ((SH + 3 - wave) >> 2) * ncol;  // rows wave, wave+4, ... times column chunks
     for (int base = 0; base < nitems; base += kBatch) {
-        float v[kBatch];
+        V v[kBatch];
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
             const int it = base + b;
             const int ry = wave + 4 * (it / ncol), rx = lane + 64 * (it % ncol);
-            v[b] = (it < nitems && rx < SW) ? f(ry, rx) : 0.f;
+            v[b] = (it < nitems && rx < SW) ? f(ry, rx) : V(0);
         }
 #pragma unroll
         for (int b = 0; b < kBatch; ++b) {
@@ -193,39 +150,128 @@ __device__ __forceinline__ void fill_region(float *dst, int SH, int SW, F f) {
     }
 }
 
-// ---------------------------------------------------------------- k_coeff
+// ------------------------------------------------------- coefficients
 //
-// One workgroup = one TH x TW tile of low-res outputs for ONE channel of p
-// (blockIdx.y).  Region: (TH + 2R) x (TW + 2R) samples of u = I' - cI and
-// v = p'_c - cP, where cI, cP are the samples at the tile's first output
-// (a per-tile mean shift).  Row pass: each thread slides a (2R+1)-wide
-// window over kRun consecutive outputs of one region row and writes the
-// compensated sums of u, u*u, v, u*v (8 floats) to LDS.  Column pass: each
-// thread owns one column and LC consecutive output rows, slides the same
-// sums down, and forms var, cov, a = cov/(var+eps), b = mean(p) - a mean(I)
-// (Eqs. 2-3), written to the coefficient planes a_c, b_c.
-template <typename T, int TH, int TW, bool STAGE>
-__global__ __launch_bounds__(kThreads) void k_coeff(const T *__restrict__ I, int64_t Irs,
-                                                    const T *__restrict__ P, int64_t Prs, int64_t Pps,
-                                                    float *__restrict__ coef, Geo g, int ntx,
-                                                    int ntiles) {
+// Statistics of a window are accumulated in FP64.  mean(I*I) - mean(I)^2 and
+// mean(I*p) - mean(I) mean(p) cancel almost completely in flat windows; FP64
+// sums (the products of FP32 samples are exact in FP64) leave ~1e-16 of
+// rounding there, far below any eps, while FP32 sums leave ~1e-8, which at
+// eps = 1e-6 moves a by percent.  On gfx950 an FP64 add or FMA issues at the
+// rate of an FP32 one (packed FP32 aside), so this costs no more than
+// compensated FP32 pairs and is more accurate.  Samples are also shifted by
+// the tile's first sample (cI, cP), which keeps the sums small.
+//
+// Final step shared by both kernels: n samples, sums Su, Suu, Sv, Suv of
+// u = I' - cI, v = p' - cP  ->  a, b of Eqs. 2-3.
+__device__ __forceinline__ void coeff_from_sums(double n, double Su, double Suu, double Sv, double Suv,
+                                                float cI, float cP, float eps, float &a, float &b) {
+    const double n2 = n * n;
+    const double var = fmax((n * Suu - Su * Su) / n2, 0.0);
+    const double cov = (n * Suv - Su * Sv) / n2;  // Eq. 2 numerator
+    const double mI = (double)cI + Su / n, mp = (double)cP + Sv / n;
+    const double ad = cov / (var + (double)eps);  // Eq. 2
+    a = (float)ad;
+    b = (float)(mp - (double)a * mI);  // Eq. 3, with the a that is stored
+}
+
+// k_coeff_slide: for small r'.  One workgroup = 4 waves over a tile of 64
+// low-res columns x 4*TH rows, for ONE channel of p (blockIdx.y).  The
+// (4TH + 2r') x (64 + 2r') region of u and v is staged in LDS; then every
+// lane owns one output column and slides the (2r'+1)^2 window down TH rows:
+// the row entering the window is added and the row leaving it subtracted,
+// tap by tap, into FP64 sums.  No row-sum buffer, one barrier.
+template <typename T, int TH>
+__global__ __launch_bounds__(kThreads) void k_coeff_slide(const T *__restrict__ I, int64_t Irs,
+                                                          const T *__restrict__ P, int64_t Prs,
+                                                          int64_t Pps, float *__restrict__ coef,
+                                                          Geo g, int ntx, int ntiles) {
     extern __shared__ float lds[];
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;  // uniform per workgroup: no barrier is skipped by part of it
-    constexpr int RUNS = TW / kRun;           // row-pass runs per region row
-    constexpr int NG = kThreads / TW;         // column-pass row groups
-    constexpr int LC = TH / NG;               // output rows per thread in the column pass
+    const int c = blockIdx.y;
+    const int R = g.R, SH = 4 * TH + 2 * R, SW = 64 + 2 * R;
+    const int ty0 = (tile / ntx) * (4 * TH), tx0 = (tile % ntx) * 64;
+    const int oy = ty0 - R, ox = tx0 - R;  // region origin in low-res coordinates
+    const T *Pc = P + (int64_t)c * Pps;
+    float *sU = lds, *sV = lds + SH * SW;
+
+    const float cI = subsample_at(I, Irs, ty0, tx0, g);
+    const float cP = subsample_at(Pc, Prs, ty0, tx0, g);
+    auto inside = [&](int ry, int rx) {
+        const int ly = oy + ry, lx = ox + rx;
+        return ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
+    };
+    fill_region(sU, SH, SW, [&](int ry, int rx) -> float {
+        return inside(ry, rx) ? subsample_at(I, Irs, oy + ry, ox + rx, g) - cI : 0.f;
+    });
+    fill_region(sV, SH, SW, [&](int ry, int rx) -> float {
+        return inside(ry, rx) ? subsample_at(Pc, Prs, oy + ry, ox + rx, g) - cP : 0.f;
+    });
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lx = tx0 + lane;
+    const int r0 = wave * TH;  // region row of the first window row of this wave's first output
+    double Su = 0.0, Suu = 0.0, Sv = 0.0, Suv = 0.0;
+    auto row = [&](int ry, double sgn) {
+        const float *pu = sU + ry * SW + lane, *pv = sV + ry * SW + lane;
+        double su = 0.0, suu = 0.0, sv = 0.0, suv = 0.0;
+        for (int k = 0; k <= 2 * R; ++k) {
+            const double u = pu[k], v = pv[k];
+            su += u;
+            suu = __builtin_fma(u, u, suu);
+            sv += v;
+            suv = __builtin_fma(u, v, suv);
+        }
+        Su = __builtin_fma(sgn, su, Su);
+        Suu = __builtin_fma(sgn, suu, Suu);
+        Sv = __builtin_fma(sgn, sv, Sv);
+        Suv = __builtin_fma(sgn, suv, Suv);
+    };
+    for (int k = 0; k <= 2 * R; ++k) row(r0 + k, 1.0);
+    const int nx = clip_len(lx, R, g.Wl);
+    float *ac = coef + (int64_t)c * g.lps;
+    float *bc = coef + (int64_t)(g.C + c) * g.lps;
+    for (int t = 0; t < TH; ++t) {
+        if (t) {
+            row(r0 + t + 2 * R, 1.0);
+            row(r0 + t - 1, -1.0);
+        }
+        const int ly = ty0 + r0 + t;
+        if (ly < g.Hl && lx < g.Wl) {
+            float a, b;
+            coeff_from_sums((double)(clip_len(ly, R, g.Hl) * nx), Su, Suu, Sv, Suv, cI, cP, g.eps, a, b);
+            ac[(int64_t)ly * g.lrs + lx] = a;
+            bc[(int64_t)ly * g.lrs + lx] = b;
+        }
+    }
+}
+
+// k_coeff_sep: any r'.  One workgroup = one TH x TW tile for ONE channel.
+// Row pass: each thread slides a (2r'+1)-wide window over kRun consecutive
+// outputs of one region row and writes the FP64 sums of u, u*u, v, u*v to
+// LDS.  Column pass: each thread owns one column and LC consecutive output
+// rows and slides the sums down.  Used when the (2r'+1)^2 taps per output of
+// k_coeff_slide would cost more than the two passes.
+template <typename T, int TH, int TW, bool STAGE>
+__global__ __launch_bounds__(kThreads) void k_coeff_sep(const T *__restrict__ I, int64_t Irs,
+                                                        const T *__restrict__ P, int64_t Prs,
+                                                        int64_t Pps, float *__restrict__ coef,
+                                                        Geo g, int ntx, int ntiles) {
+    extern __shared__ double ldsd[];
+    const int tile = xcd_tile(blockIdx.x);
+    if (tile >= ntiles) return;
+    constexpr int RUNS = TW / kRun, NG = kThreads / TW, LC = TH / NG;
     static_assert(LC * NG == TH && RUNS * kRun == TW, "tile shape");
     const int c = blockIdx.y;
     const int R = g.R, SH = TH + 2 * R, SW = TW + 2 * R;
     const int ty0 = (tile / ntx) * TH, tx0 = (tile % ntx) * TW;
-    const int oy = ty0 - R, ox = tx0 - R;  // region origin in low-res coordinates
+    const int oy = ty0 - R, ox = tx0 - R;
     const T *Pc = P + (int64_t)c * Pps;
-
-    float *rs = lds;                      // 8 row-sum planes of SH x TW
-    float *sU = rs + 8 * SH * TW;         // staged u, v (STAGE only)
-    float *sV = sU + SH * SW;
     const int plane = SH * TW;
+    double *rs = ldsd;                             // 4 row-sum planes of SH x TW
+    float *sU = (float *)(rs + 4 * plane);         // staged u, v (STAGE only)
+    float *sV = sU + SH * SW;
 
     const float cI = subsample_at(I, Irs, ty0, tx0, g);
     const float cP = subsample_at(Pc, Prs, ty0, tx0, g);
@@ -239,109 +285,130 @@ __global__ __launch_bounds__(kThreads) void k_coeff(const T *__restrict__ I, int
     auto gV = [&](int ry, int rx) -> float {
         return inside(ry, rx) ? subsample_at(Pc, Prs, oy + ry, ox + rx, g) - cP : 0.f;
     };
-    auto lU = [&](int ry, int rx) -> float { return sU[ry * SW + rx]; };
-    auto lV = [&](int ry, int rx) -> float { return sV[ry * SW + rx]; };
-
     if (STAGE) {
         fill_region(sU, SH, SW, gU);
         fill_region(sV, SH, SW, gV);
         __syncthreads();
     }
-
-    // ---- row pass
     for (int it = threadIdx.x; it < SH * RUNS; it += kThreads) {
         const int ry = it / RUNS, j0 = (it % RUNS) * kRun;
-        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        auto add = [&](float u, float v) {
-            df_add(s[0], s[1], u);
-            df_add_prod(s[2], s[3], u, u);
-            df_add(s[4], s[5], v);
-            df_add_prod(s[6], s[7], u, v);
-        };
-        auto sub = [&](float u, float v) {  // remove the sample leaving the window
-            df_add(s[0], s[1], -u);
-            df_add_prod(s[2], s[3], -u, u);
-            df_add(s[4], s[5], -v);
-            df_add_prod(s[6], s[7], -u, v);
-        };
-        auto tap = [&](int rx, float &u, float &v) {
+        auto tap = [&](int rx, double &u, double &v) {
             if (STAGE) {
-                u = lU(ry, rx);
-                v = lV(ry, rx);
+                u = sU[ry * SW + rx];
+                v = sV[ry * SW + rx];
             } else {
                 u = gU(ry, rx);
                 v = gV(ry, rx);
             }
         };
+        double su = 0.0, suu = 0.0, sv = 0.0, suv = 0.0;
         for (int k = 0; k <= 2 * R; ++k) {
-            float u, v;
+            double u, v;
             tap(j0 + k, u, v);
-            add(u, v);
+            su += u;
+            suu = __builtin_fma(u, u, suu);
+            sv += v;
+            suv = __builtin_fma(u, v, suv);
         }
-        float *o = rs + ry * TW + j0;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) o[m * plane] = s[m];
+        double *o = rs + ry * TW + j0;
+        o[0] = su;
+        o[plane] = suu;
+        o[2 * plane] = sv;
+        o[3 * plane] = suv;
 #pragma unroll
         for (int t = 1; t < kRun; ++t) {
-            float ui, vi, uo, vo;
+            double ui, vi, uo, vo;
             tap(j0 + t + 2 * R, ui, vi);
             tap(j0 + t - 1, uo, vo);
-            add(ui, vi);
-            sub(uo, vo);
-#pragma unroll
-            for (int m = 0; m < 8; ++m) o[t + m * plane] = s[m];
+            su += ui - uo;
+            suu += __builtin_fma(ui, ui, -uo * uo);
+            sv += vi - vo;
+            suv += __builtin_fma(ui, vi, -uo * vo);
+            o[t] = su;
+            o[t + plane] = suu;
+            o[t + 2 * plane] = sv;
+            o[t + 3 * plane] = suv;
         }
     }
     __syncthreads();
 
-    // ---- column pass
     const int col = threadIdx.x % TW, r0 = (threadIdx.x / TW) * LC;
     const int lx = tx0 + col;
     const int nx = clip_len(lx, R, g.Wl);
-    float S[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    auto radd = [&](int row, float sign) {
-        const float *src = rs + row * TW + col;
+    double S[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k <= 2 * R; ++k)
 #pragma unroll
-        for (int m = 0; m < 8; m += 2) {
-            df_add(S[m], S[m + 1], sign * src[m * plane]);
-            S[m + 1] += sign * src[(m + 1) * plane];
-        }
-    };
-    for (int k = 0; k <= 2 * R; ++k) radd(r0 + k, 1.f);
+        for (int m = 0; m < 4; ++m) S[m] += rs[(r0 + k) * TW + col + m * plane];
     float *ac = coef + (int64_t)c * g.lps;
     float *bc = coef + (int64_t)(g.C + c) * g.lps;
 #pragma unroll
     for (int t = 0; t < LC; ++t) {
         if (t) {
-            radd(r0 + t + 2 * R, 1.f);
-            radd(r0 + t - 1, -1.f);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                S[m] += rs[(r0 + t + 2 * R) * TW + col + m * plane] - rs[(r0 + t - 1) * TW + col + m * plane];
         }
         const int ly = ty0 + r0 + t;
         if (ly < g.Hl && lx < g.Wl) {
-            const float n = (float)(clip_len(ly, R, g.Hl) * nx);
-            const float n2 = n * n;
-            const float var = fmaxf(df_det(n, S[2], S[3], S[0], S[1], S[0], S[1]) / n2, 0.f);
-            const float cov = df_det(n, S[6], S[7], S[0], S[1], S[4], S[5]) / n2;  // Eq. 2 numerator
-            const float mI = cI + (S[0] + S[1]) / n;
-            const float mp = cP + (S[4] + S[5]) / n;
-            const float a = cov / (var + g.eps);  // Eq. 2
-            const float b = mp - a * mI;          // Eq. 3
+            float a, b;
+            coeff_from_sums((double)(clip_len(ly, R, g.Hl) * nx), S[0], S[1], S[2], S[3], cI, cP, g.eps, a, b);
             ac[(int64_t)ly * g.lrs + lx] = a;
             bc[(int64_t)ly * g.lrs + lx] = b;
         }
     }
 }
 
-// ---------------------------------------------------------------- k_box
+// ---------------------------------------------------------------- box means
 //
 // Clip-normalised box mean of one low-res FP32 plane per blockIdx.y (the
-// coefficient maps a_c, b_c: Algorithm 2 step 5).  Same row / column pass
-// structure as k_coeff with plain FP32 sums (no cancellation here).
-template <int TH, bool STAGE>
-__global__ __launch_bounds__(kThreads) void k_box(const float *__restrict__ src,
-                                                  float *__restrict__ dst, Geo g, int ntx,
-                                                  int ntiles) {
+// coefficient maps a_c, b_c: Algorithm 2 step 5).  FP64 sums.
+
+// k_box_slide: small r'; same tiling and window walk as k_coeff_slide.
+template <int TH>
+__global__ __launch_bounds__(kThreads) void k_box_slide(const float *__restrict__ src,
+                                                        float *__restrict__ dst, Geo g, int ntx,
+                                                        int ntiles) {
     extern __shared__ float lds[];
+    const int tile = xcd_tile(blockIdx.x);
+    if (tile >= ntiles) return;
+    const int R = g.R, SH = 4 * TH + 2 * R, SW = 64 + 2 * R;
+    const int ty0 = (tile / ntx) * (4 * TH), tx0 = (tile % ntx) * 64;
+    const int oy = ty0 - R, ox = tx0 - R;
+    const float *S = src + (int64_t)blockIdx.y * g.lps;
+    float *D = dst + (int64_t)blockIdx.y * g.lps;
+    float *sX = lds;
+    fill_region(sX, SH, SW, [&](int ry, int rx) -> float {
+        const int ly = oy + ry, lx = ox + rx;
+        return (ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl) ? S[(int64_t)ly * g.lrs + lx] : 0.f;
+    });
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lx = tx0 + lane, r0 = wave * TH;
+    double A = 0.0;
+    auto row = [&](int ry, double sgn) {
+        const float *px = sX + ry * SW + lane;
+        double sx = 0.0;
+        for (int k = 0; k <= 2 * R; ++k) sx += px[k];
+        A = __builtin_fma(sgn, sx, A);
+    };
+    for (int k = 0; k <= 2 * R; ++k) row(r0 + k, 1.0);
+    const int nx = clip_len(lx, R, g.Wl);
+    for (int t = 0; t < TH; ++t) {
+        if (t) {
+            row(r0 + t + 2 * R, 1.0);
+            row(r0 + t - 1, -1.0);
+        }
+        const int ly = ty0 + r0 + t;
+        if (ly < g.Hl && lx < g.Wl) D[(int64_t)ly * g.lrs + lx] = (float)(A / (double)(clip_len(ly, R, g.Hl) * nx));
+    }
+}
+
+// k_box_sep: any r'; row pass into LDS (FP64 sums), column pass in registers.
+template <int TH, bool STAGE>
+__global__ __launch_bounds__(kThreads) void k_box_sep(const float *__restrict__ src,
+                                                      float *__restrict__ dst, Geo g, int ntx,
+                                                      int ntiles) {
+    extern __shared__ double ldsd[];
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;
     constexpr int TW = kTileW, RUNS = TW / kRun, NG = kThreads / TW, LC = TH / NG;
@@ -350,9 +417,8 @@ __global__ __launch_bounds__(kThreads) void k_box(const float *__restrict__ src,
     const int oy = ty0 - R, ox = tx0 - R;
     const float *S = src + (int64_t)blockIdx.y * g.lps;
     float *D = dst + (int64_t)blockIdx.y * g.lps;
-
-    float *rA = lds;
-    float *sX = rA + SH * TW;
+    double *rA = ldsd;
+    float *sX = (float *)(rA + SH * TW);
     auto gX = [&](int ry, int rx) -> float {
         const int ly = oy + ry, lx = ox + rx;
         return (ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl) ? S[(int64_t)ly * g.lrs + lx] : 0.f;
@@ -363,10 +429,10 @@ __global__ __launch_bounds__(kThreads) void k_box(const float *__restrict__ src,
     }
     for (int it = threadIdx.x; it < SH * RUNS; it += kThreads) {
         const int ry = it / RUNS, j0 = (it % RUNS) * kRun;
-        auto x = [&](int rx) -> float { return STAGE ? sX[ry * SW + rx] : gX(ry, rx); };
-        float A = 0.f;
+        auto x = [&](int rx) -> double { return STAGE ? sX[ry * SW + rx] : gX(ry, rx); };
+        double A = 0.0;
         for (int k = 0; k <= 2 * R; ++k) A += x(j0 + k);
-        float *oa = rA + ry * TW + j0;
+        double *oa = rA + ry * TW + j0;
         oa[0] = A;
 #pragma unroll
         for (int t = 1; t < kRun; ++t) {
@@ -375,20 +441,16 @@ __global__ __launch_bounds__(kThreads) void k_box(const float *__restrict__ src,
         }
     }
     __syncthreads();
-
     const int col = threadIdx.x % TW, r0 = (threadIdx.x / TW) * LC;
     const int lx = tx0 + col;
     const int nx = clip_len(lx, R, g.Wl);
-    float A = 0.f;
+    double A = 0.0;
     for (int k = 0; k <= 2 * R; ++k) A += rA[(r0 + k) * TW + col];
 #pragma unroll
     for (int t = 0; t < LC; ++t) {
         if (t) A += rA[(r0 + t + 2 * R) * TW + col] - rA[(r0 + t - 1) * TW + col];
         const int ly = ty0 + r0 + t;
-        if (ly < g.Hl && lx < g.Wl) {
-            const int n = clip_len(ly, R, g.Hl) * nx;
-            D[(int64_t)ly * g.lrs + lx] = A / (float)n;
-        }
+        if (ly < g.Hl && lx < g.Wl) D[(int64_t)ly * g.lrs + lx] = (float)(A / (double)(clip_len(ly, R, g.Hl) * nx));
     }
 }
 
@@ -594,29 +656,44 @@ void allow_lds(K kernel, size_t bytes) {
 template <typename T>
 hipError_t coeff_t(const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
                    hipStream_t st) {
+    const T *Ip = (const T *)I.data, *Pp = (const T *)P.data;
+    const dim3 block(kThreads);
+    const size_t lds = coeff_lds_bytes(t, g.R);
+    if (t.coeff_slide) {
+        const int ntx = (g.Wl + 63) / 64, nty = (g.Hl + 4 * t.coeff_th - 1) / (4 * t.coeff_th);
+        const int ntiles = ntx * nty;
+        const dim3 grid(grid8(ntiles), g.C);
+#define GF_SLIDE(TH)                                                                             \
+    {                                                                                            \
+        allow_lds(k_coeff_slide<T, TH>, lds);                                                    \
+        hipLaunchKernelGGL((k_coeff_slide<T, TH>), grid, block, lds, st, Ip, I.rs, Pp, P.rs, P.ps, \
+                           coef, g, ntx, ntiles);                                                \
+    }
+        if (t.coeff_th == 4) GF_SLIDE(4) else if (t.coeff_th == 8) GF_SLIDE(8) else GF_SLIDE(16)
+#undef GF_SLIDE
+        return hipGetLastError();
+    }
     const int ntx = (g.Wl + t.coeff_tw - 1) / t.coeff_tw;
     const int nty = (g.Hl + t.coeff_th - 1) / t.coeff_th;
     const int ntiles = ntx * nty;
-    const size_t lds = coeff_lds_bytes(t.coeff_th, t.coeff_tw, t.coeff_stage, g.R);
-    const T *Ip = (const T *)I.data, *Pp = (const T *)P.data;
-    const dim3 grid(grid8(ntiles), g.C), block(kThreads);
-#define GF_COEFF(TH, TW, STG)                                                                     \
-    {                                                                                             \
-        allow_lds(k_coeff<T, TH, TW, STG>, lds);                                                  \
-        hipLaunchKernelGGL((k_coeff<T, TH, TW, STG>), grid, block, lds, st, Ip, I.rs, Pp, P.rs,  \
-                           P.ps, coef, g, ntx, ntiles);                                           \
+    const dim3 grid(grid8(ntiles), g.C);
+#define GF_SEP(TH, TW, STG)                                                                        \
+    {                                                                                              \
+        allow_lds(k_coeff_sep<T, TH, TW, STG>, lds);                                               \
+        hipLaunchKernelGGL((k_coeff_sep<T, TH, TW, STG>), grid, block, lds, st, Ip, I.rs, Pp, P.rs, \
+                           P.ps, coef, g, ntx, ntiles);                                            \
     }
-#define GF_COEFF_S(TH, TW) \
-    if (t.coeff_stage) GF_COEFF(TH, TW, true) else GF_COEFF(TH, TW, false)
+#define GF_SEP_S(TH, TW) \
+    if (t.coeff_stage) GF_SEP(TH, TW, true) else GF_SEP(TH, TW, false)
     if (t.coeff_th == 32) {
-        if (t.coeff_tw == 64) GF_COEFF_S(32, 64) else GF_COEFF_S(32, 32)
+        if (t.coeff_tw == 64) GF_SEP_S(32, 64) else GF_SEP_S(32, 32)
     } else if (t.coeff_th == 16) {
-        if (t.coeff_tw == 64) GF_COEFF_S(16, 64) else GF_COEFF_S(16, 32)
+        if (t.coeff_tw == 64) GF_SEP_S(16, 64) else GF_SEP_S(16, 32)
     } else {
-        if (t.coeff_tw == 64) GF_COEFF_S(8, 64) else GF_COEFF_S(8, 32)
+        if (t.coeff_tw == 64) GF_SEP_S(8, 64) else GF_SEP_S(8, 32)
     }
-#undef GF_COEFF_S
-#undef GF_COEFF
+#undef GF_SEP_S
+#undef GF_SEP
     return hipGetLastError();
 }
 
@@ -671,15 +748,29 @@ hipError_t launch_coeff(gf_dtype dt, const View &I, const View &P, float *coef, 
 }
 
 hipError_t launch_box(const float *src, float *dst, const Geo &g, const TileCfg &t, hipStream_t st) {
+    const size_t lds = box_lds_bytes(t, g.R);
+    const dim3 block(kThreads);
+    if (t.box_slide) {
+        const int ntx = (g.Wl + 63) / 64, nty = (g.Hl + 4 * t.box_th - 1) / (4 * t.box_th);
+        const int ntiles = ntx * nty;
+        const dim3 grid(grid8(ntiles), 2 * g.C);
+#define GF_BSLIDE(TH)                                                                        \
+    {                                                                                        \
+        allow_lds(k_box_slide<TH>, lds);                                                     \
+        hipLaunchKernelGGL((k_box_slide<TH>), grid, block, lds, st, src, dst, g, ntx, ntiles); \
+    }
+        if (t.box_th == 4) GF_BSLIDE(4) else if (t.box_th == 8) GF_BSLIDE(8) else GF_BSLIDE(16)
+#undef GF_BSLIDE
+        return hipGetLastError();
+    }
     const int ntx = (g.Wl + kTileW - 1) / kTileW;
     const int nty = (g.Hl + t.box_th - 1) / t.box_th;
     const int ntiles = ntx * nty;
-    const size_t lds = box_lds_bytes(t.box_th, t.box_stage, g.R);
-    const dim3 grid(grid8(ntiles), 2 * g.C), block(kThreads);
-#define GF_BOX(TH, STG)                                                                    \
-    {                                                                                      \
-        allow_lds(k_box<TH, STG>, lds);                                                    \
-        hipLaunchKernelGGL((k_box<TH, STG>), grid, block, lds, st, src, dst, g, ntx, ntiles); \
+    const dim3 grid(grid8(ntiles), 2 * g.C);
+#define GF_BOX(TH, STG)                                                                        \
+    {                                                                                          \
+        allow_lds(k_box_sep<TH, STG>, lds);                                                    \
+        hipLaunchKernelGGL((k_box_sep<TH, STG>), grid, block, lds, st, src, dst, g, ntx, ntiles); \
     }
     if (t.box_th == 32) {
         if (t.box_stage) GF_BOX(32, true) else GF_BOX(32, false)
