@@ -214,6 +214,55 @@ typedef struct {
 gf_status gf_ctx_profile(gf_ctx *ctx, int enable);
 gf_status gf_ctx_profile_read(gf_ctx *ctx, gf_kernel_time *out);
 
+/*
+ * Tile shapes of the window-sum kernels (Algorithm 2 steps 2-5).  The
+ * coefficient kernel either slides a (2r'+1)^2 window down each column
+ * (coeff_slide = 1; a tile is 64 columns x 4*coeff_th rows) or runs a row
+ * pass and a column pass (coeff_slide = 0; a tile is coeff_th x coeff_tw,
+ * coeff_stage = 1 stages the samples in LDS).  The box-mean kernel has the
+ * same two forms (box_*; separable tiles are 64 columns wide).
+ */
+typedef struct {
+    int32_t coeff_slide, coeff_th, coeff_tw, coeff_stage;
+    int32_t box_slide, box_th, box_stage;
+} gf_tiles;
+
+typedef struct {
+    int32_t kernel;   /* GF_K_COEFF or GF_K_BOX */
+    gf_tiles tiles;   /* the candidate (only that kernel's fields matter) */
+    double ms;        /* mean duration of that kernel per call */
+} gf_tune_result;
+
+/*
+ * Pin tile shapes on ctx for every call whose problem falls in the same
+ * class as (h, w, c, params, dtype): same dtype, c, s, low-res radius r' and
+ * size class (floor(log2(ceil(h/s) * ceil(w/s)))).  tiles == NULL removes
+ * the pin (the built-in choice applies again).  GF_ENOTSUP if the shapes do
+ * not fit in LDS for that radius.
+ */
+gf_status gf_ctx_set_tiles(gf_ctx *ctx, gf_dtype dtype, int32_t h, int32_t w, int32_t c,
+                           const gf_params *params, const gf_tiles *tiles);
+
+/*
+ * Autotuner: times every candidate shape of the coefficient kernel and of
+ * the box-mean kernel on this problem (HIP events on `hip_stream`, `reps`
+ * launches each after one warm-up), keeps the fastest of each for the
+ * problem's class on ctx (as gf_ctx_set_tiles would) and returns it in
+ * *best (may be NULL).  Synchronises the stream; q's contents are
+ * overwritten with a valid result.  results (may be NULL) receive up to
+ * max_results timings, *n_results their count.  Same arguments and
+ * workspace as gf_fast.
+ */
+gf_status gf_tune(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
+                  const gf_params *params, void *workspace, size_t workspace_bytes,
+                  void *hip_stream, int32_t reps, gf_tiles *best, gf_tune_result *results,
+                  int32_t max_results, int32_t *n_results);
+
+/* Write the context's tuned shapes to a JSON file / read them back (entries
+ * of the file replace those of the same class). */
+gf_status gf_ctx_save_tuning(gf_ctx *ctx, const char *path);
+gf_status gf_ctx_load_tuning(gf_ctx *ctx, const char *path);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,7 +31,8 @@ SUBSAMPLE = {"nearest": GF_SUB_NEAREST, "bilinear": GF_SUB_BILINEAR}
 # Every symbol include/gf.h declares.
 EXPORTS = ("gf_ctx_create", "gf_ctx_destroy", "gf_last_error", "gf_workspace_bytes", "gf_plain",
            "gf_fast", "gf_batched_workspace_bytes", "gf_fast_batched", "gf_submit", "gf_poll",
-           "gf_ctx_profile", "gf_ctx_profile_read")
+           "gf_ctx_profile", "gf_ctx_profile_read", "gf_ctx_set_tiles", "gf_tune",
+           "gf_ctx_save_tuning", "gf_ctx_load_tuning")
 KERNELS = ("coeff", "box", "output", "batched")
 
 
@@ -53,6 +54,20 @@ class gf_req_stats(ctypes.Structure):
 
 class gf_kernel_time(ctypes.Structure):
     _fields_ = [("total_ms", ctypes.c_double), ("launches", ctypes.c_int64)]
+
+
+class gf_tiles(ctypes.Structure):
+    _fields_ = [("coeff_slide", ctypes.c_int32), ("coeff_th", ctypes.c_int32),
+                ("coeff_tw", ctypes.c_int32), ("coeff_stage", ctypes.c_int32),
+                ("box_slide", ctypes.c_int32), ("box_th", ctypes.c_int32),
+                ("box_stage", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class gf_tune_result(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("tiles", gf_tiles), ("ms", ctypes.c_double)]
 
 
 class GfError(RuntimeError):
@@ -94,6 +109,11 @@ def lib() -> ctypes.CDLL:
             "gf_poll": (ctypes.c_int, [VP, ctypes.c_uint64, I32, P(gf_req_stats)]),
             "gf_ctx_profile": (ctypes.c_int, [VP, ctypes.c_int]),
             "gf_ctx_profile_read": (ctypes.c_int, [VP, P(gf_kernel_time)]),
+            "gf_ctx_set_tiles": (ctypes.c_int, [VP, ctypes.c_int, I32, I32, I32, par_p, P(gf_tiles)]),
+            "gf_tune": (ctypes.c_int, [VP, img_p, img_p, img_p, par_p, VP, SZ, VP, I32, P(gf_tiles),
+                                       P(gf_tune_result), I32, P(I32)]),
+            "gf_ctx_save_tuning": (ctypes.c_int, [VP, ctypes.c_char_p]),
+            "gf_ctx_load_tuning": (ctypes.c_int, [VP, ctypes.c_char_p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -279,6 +299,40 @@ class Context:
         out = (gf_kernel_time * len(KERNELS))()
         _check(lib().gf_ctx_profile_read(self._h, out), self)
         return {k: (out[i].total_ms, out[i].launches) for i, k in enumerate(KERNELS)}
+
+    def set_tiles(self, I, p, r: int, s: int, eps: float, tiles: dict | None, sub: str = "nearest"):
+        """Pin tile shapes for the class of this problem (None: unpin)."""
+        h, w = I.shape[-2:]
+        c = 1 if p.dim() == 2 else p.shape[0]
+        t = gf_tiles(**tiles) if tiles is not None else None
+        _check(lib().gf_ctx_set_tiles(self._h, _dtype_code(I), h, w, c,
+                                      ctypes.byref(params(r, s, eps, sub)),
+                                      ctypes.byref(t) if t is not None else None), self)
+
+    def tune(self, I, p, r: int, s: int, eps: float, sub: str = "nearest", q=None, reps: int = 5,
+             stream=None):
+        """Autotune the window-sum kernels for this problem's class.
+        Returns (best tiles dict, [(kernel, tiles dict, ms), ...])."""
+        q = _out_like(p, q)
+        h, w = I.shape[-2:]
+        c = 1 if p.dim() == 2 else p.shape[0]
+        pr = params(r, s, eps, sub)
+        ws = _workspace(lib().gf_workspace_bytes(h, w, c, ctypes.byref(pr)), p.device)
+        best = gf_tiles()
+        res = (gf_tune_result * 64)()
+        n = ctypes.c_int32()
+        _check(lib().gf_tune(self._h, ctypes.byref(image(I)), ctypes.byref(image(p)),
+                             ctypes.byref(image(q)), ctypes.byref(pr), ctypes.c_void_p(ws.data_ptr()),
+                             ws.numel(), _stream(stream), int(reps), ctypes.byref(best), res, 64,
+                             ctypes.byref(n)), self)
+        rows = [(KERNELS[res[i].kernel], res[i].tiles.as_dict(), res[i].ms) for i in range(n.value)]
+        return best.as_dict(), rows
+
+    def save_tuning(self, path: str):
+        _check(lib().gf_ctx_save_tuning(self._h, path.encode()), self)
+
+    def load_tuning(self, path: str):
+        _check(lib().gf_ctx_load_tuning(self._h, path.encode()), self)
 
     def gf_submit(self, I, p, q, r: int, s: int, eps: float, sub: str = "nearest") -> int:
         """Queue a request; returns its ticket.  I, p, q are kept alive here

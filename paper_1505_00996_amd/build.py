@@ -12,7 +12,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgf.so")
-SOURCES = ["gf_kernels.hip", "gf_batched.hip", "gf_api.cpp", "gf_ctx.cpp", "gf_engine.cpp"]
+SOURCES = ["gf_kernels.hip", "gf_batched.hip", "gf_api.cpp", "gf_ctx.cpp", "gf_tune.cpp",
+           "gf_engine.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for the device code on purpose.
@@ -35,9 +36,11 @@ def build(out: str = LIB, verbose: bool = False) -> str:
             continue
         obj = os.path.join(bdir, src + ".o")
         cmd = [hipcc, *HIPFLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", path, "-o", obj]
-        if src.endswith(".cpp"):
-            cmd = [hipcc, "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include"),
-                   "-I", CSRC, "-c", path, "-o", obj]
+        if src.endswith(".cpp"):  # host-only code: plain C++ against the HIP runtime API
+            cxx = os.environ.get("CXX_HOST", "/opt/rocm/llvm/bin/clang++")
+            cmd = [cxx, "-x", "c++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
+                   "-I", "/opt/rocm/include", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                   "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

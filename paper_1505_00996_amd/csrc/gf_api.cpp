@@ -2,7 +2,7 @@
 // tile heuristics and the gf_plain / gf_fast entry points of include/gf.h.
 // Validation is pure host code and runs before any HIP call, so an invalid
 // call is reported without touching a device.
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 
 #include <math.h>
 #include <stdarg.h>
@@ -195,7 +195,8 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
                    const gf_params *pr, void *ws, size_t ws_bytes, hipStream_t st,
                    const TileCfg *tiles) {
     const Geo g = make_geo(I->h, I->w, p->c, pr->r, pr->s, pr->eps, (int)pr->sub);
-    const TileCfg t = tiles ? *tiles : default_tiles(g);
+    // pinned or tuned shapes that do not fit this radius fall back to the built-in choice
+    const TileCfg t = (tiles && tiles_fit(g, *tiles)) ? *tiles : default_tiles(g);
     if (!tiles_fit(g, t)) return fail(GF_ENOTSUP, "tile shapes do not fit in LDS for r'=%d", g.R);
     const size_t need = workspace_bytes(g);
     if (!ws) return fail(GF_EINVAL, "no workspace");
@@ -272,8 +273,9 @@ gf_status gf_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q
     } else if (ctx && (st = ctx_use_device(ctx)) != GF_OK) {
         return st;
     }
-    return run_fast(ctx, I, p, q, pr, ws, ws_bytes, (hipStream_t)stream,
-                    ctx ? ctx_tiles(ctx, I, p, pr) : nullptr);
+    TileCfg tuned;
+    const bool have = ctx && ctx_tiles(ctx, I, p, pr, &tuned);
+    return run_fast(ctx, I, p, q, pr, ws, ws_bytes, (hipStream_t)stream, have ? &tuned : nullptr);
 }
 
 gf_status gf_plain(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q, int32_t r,

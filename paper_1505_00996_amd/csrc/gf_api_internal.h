@@ -56,8 +56,11 @@ struct ProfScope {
     ~ProfScope();
 };
 gf_status ctx_use_device(gf_ctx *ctx);
-const TileCfg *ctx_tiles(gf_ctx *ctx, const gf_image *I, const gf_image *p, const gf_params *pr);
-uint64_t tile_key(gf_dtype dt, int C, int s, int R);
+gf_status ctx_workspace(gf_ctx *ctx, size_t need, void **ws);
+bool ctx_tiles(gf_ctx *ctx, const gf_image *I, const gf_image *p, const gf_params *pr,
+               TileCfg *out);
+uint64_t tile_key(gf_dtype dt, int h, int w, int C, int r, int s);
+TileCfg default_tiles(const Geo &g);
 gf_status engine_start(gf_ctx *ctx, size_t arena_bytes, int max_inflight);
 void engine_stop(gf_ctx *ctx);
 

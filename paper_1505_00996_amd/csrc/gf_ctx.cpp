@@ -1,5 +1,5 @@
 // Context lifetime, device selection and per-context tile choices.
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 
 #include <new>
 
@@ -16,15 +16,23 @@ gf_status ctx_use_device(gf_ctx *ctx) {
     return GF_OK;
 }
 
-uint64_t tile_key(gf_dtype dt, int C, int s, int R) {
-    return ((uint64_t)dt << 56) | ((uint64_t)(C & 0xff) << 48) | ((uint64_t)(s & 0xffff) << 32) |
-           (uint64_t)(uint32_t)R;
+// Problem class of a tuned choice: dtype, channels, s, low-res radius and
+// the size class floor(log2(Hl * Wl)).
+uint64_t tile_key(gf_dtype dt, int h, int w, int C, int r, int s) {
+    const int R = lowres_radius(r, s);
+    const uint64_t n = (uint64_t)((h + s - 1) / s) * (uint64_t)((w + s - 1) / s);
+    int lg = 0;
+    while ((n >> (lg + 1)) != 0) ++lg;
+    return ((uint64_t)(dt & 0xf) << 60) | ((uint64_t)(C & 0xfff) << 48) |
+           ((uint64_t)(s & 0xffff) << 32) | ((uint64_t)(R & 0xffffff) << 8) | (uint64_t)(lg & 0xff);
 }
 
-const TileCfg *ctx_tiles(gf_ctx *ctx, const gf_image *I, const gf_image *p, const gf_params *pr) {
+bool ctx_tiles(gf_ctx *ctx, const gf_image *I, const gf_image *p, const gf_params *pr, TileCfg *out) {
     std::lock_guard<std::mutex> lk(ctx->tune_mu);
-    auto it = ctx->tuned.find(tile_key(I->dtype, p->c, pr->s, lowres_radius(pr->r, pr->s)));
-    return it == ctx->tuned.end() ? nullptr : &it->second;
+    auto it = ctx->tuned.find(tile_key(I->dtype, I->h, I->w, p->c, pr->r, pr->s));
+    if (it == ctx->tuned.end()) return false;
+    *out = it->second;
+    return true;
 }
 
 static hipEvent_t take_event(gf_ctx *ctx) {

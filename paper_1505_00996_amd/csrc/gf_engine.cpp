@@ -1,5 +1,5 @@
 // Batched launch and request interface (gf_fast_batched, gf_submit, gf_poll).
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 
 #include "gf_api_internal.h"
 

@@ -2,7 +2,7 @@
 // kernels (gf_kernels.hip, gf_batched.hip).  Not part of the public ABI.
 #pragma once
 
-#include <hip/hip_runtime.h>
+#include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
 #include "gf.h"

@@ -122,30 +122,51 @@ __device__ __forceinline__ float subsample_at(const T *__restrict__ img, int64_t
 }
 
 // ------------------------------------------------------- staging helpers
+//
+// Fill SH x SW row-major LDS regions: thread t takes elements t, t + 256, ...,
+// kFillPer of them at a time with every global load of the batch issued
+// before the first LDS store, so a lane has up to kFillPer (or 2 kFillPer)
+// loads in flight instead of one.
+constexpr int kFillPer = 12;
 
-// Fill an SH x SW LDS region, wave w taking rows w, w+4, ...; loads are
-// issued in batches of kBatch before any LDS store so several global loads
-// are in flight per lane.
-constexpr int kBatch = 8;
-
-template <typename V, class F>
-__device__ __forceinline__ void fill_region(V *dst, int SH, int SW, F f) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ncol = (SW + 63) >> 6;
-    const int nitems = ((SH + 3 - wave) >> 2) * ncol;  // rows wave, wave+4, ... times column chunks
-    for (int base = 0; base < nitems; base += kBatch) {
-        V v[kBatch];
+template <class F>
+__device__ __forceinline__ void fill_region(float *dst, int SH, int SW, F f) {
+    const int n = SH * SW;
+    for (int base = 0; base < n; base += kFillPer * kThreads) {
+        float v[kFillPer];
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            const int it = base + b;
-            const int ry = wave + 4 * (it / ncol), rx = lane + 64 * (it % ncol);
-            v[b] = (it < nitems && rx < SW) ? f(ry, rx) : V(0);
+        for (int b = 0; b < kFillPer; ++b) {
+            const int e = base + b * kThreads + (int)threadIdx.x;
+            const int ry = e / SW;
+            v[b] = e < n ? f(ry, e - ry * SW) : 0.f;
         }
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            const int it = base + b;
-            const int ry = wave + 4 * (it / ncol), rx = lane + 64 * (it % ncol);
-            if (it < nitems && rx < SW) dst[ry * SW + rx] = v[b];
+        for (int b = 0; b < kFillPer; ++b) {
+            const int e = base + b * kThreads + (int)threadIdx.x;
+            if (e < n) dst[e] = v[b];
+        }
+    }
+}
+
+template <class F1, class F2>
+__device__ __forceinline__ void fill_region2(float *d1, float *d2, int SH, int SW, F1 f1, F2 f2) {
+    const int n = SH * SW;
+    for (int base = 0; base < n; base += kFillPer * kThreads) {
+        float v1[kFillPer], v2[kFillPer];
+#pragma unroll
+        for (int b = 0; b < kFillPer; ++b) {
+            const int e = base + b * kThreads + (int)threadIdx.x;
+            const int ry = e / SW, rx = e - ry * SW;
+            v1[b] = e < n ? f1(ry, rx) : 0.f;
+            v2[b] = e < n ? f2(ry, rx) : 0.f;
+        }
+#pragma unroll
+        for (int b = 0; b < kFillPer; ++b) {
+            const int e = base + b * kThreads + (int)threadIdx.x;
+            if (e < n) {
+                d1[e] = v1[b];
+                d2[e] = v2[b];
+            }
         }
     }
 }
@@ -163,15 +184,18 @@ __device__ __forceinline__ void fill_region(V *dst, int SH, int SW, F f) {
 //
 // Final step shared by both kernels: n samples, sums Su, Suu, Sv, Suv of
 // u = I' - cI, v = p' - cP  ->  a, b of Eqs. 2-3.
-__device__ __forceinline__ void coeff_from_sums(double n, double Su, double Suu, double Sv, double Suv,
+__device__ __forceinline__ void coeff_from_sums(int n, double Su, double Suu, double Sv, double Suv,
                                                 float cI, float cP, float eps, float &a, float &b) {
-    const double n2 = n * n;
-    const double var = fmax((n * Suu - Su * Su) / n2, 0.0);
-    const double cov = (n * Suv - Su * Sv) / n2;  // Eq. 2 numerator
-    const double mI = (double)cI + Su / n, mp = (double)cP + Sv / n;
-    const double ad = cov / (var + (double)eps);  // Eq. 2
-    a = (float)ad;
-    b = (float)(mp - (double)a * mI);  // Eq. 3, with the a that is stored
+    // n^2 var and n^2 cov: the two cancelling differences, taken in FP64
+    const double nd = (double)n;
+    const float n2var = (float)fmax(nd * Suu - Su * Su, 0.0);
+    const float n2cov = (float)(nd * Suv - Su * Sv);
+    const float inv_n = 1.0f / (float)n;
+    const float var = n2var * inv_n * inv_n;
+    const float cov = n2cov * inv_n * inv_n;  // Eq. 2 numerator
+    const float mI = cI + (float)Su * inv_n, mp = cP + (float)Sv * inv_n;
+    a = cov / (var + eps);  // Eq. 2
+    b = mp - a * mI;        // Eq. 3
 }
 
 // k_coeff_slide: for small r'.  One workgroup = 4 waves over a tile of 64
@@ -201,12 +225,14 @@ __global__ __launch_bounds__(kThreads) void k_coeff_slide(const T *__restrict__ 
         const int ly = oy + ry, lx = ox + rx;
         return ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
     };
-    fill_region(sU, SH, SW, [&](int ry, int rx) -> float {
-        return inside(ry, rx) ? subsample_at(I, Irs, oy + ry, ox + rx, g) - cI : 0.f;
-    });
-    fill_region(sV, SH, SW, [&](int ry, int rx) -> float {
-        return inside(ry, rx) ? subsample_at(Pc, Prs, oy + ry, ox + rx, g) - cP : 0.f;
-    });
+    fill_region2(
+        sU, sV, SH, SW,
+        [&](int ry, int rx) -> float {
+            return inside(ry, rx) ? subsample_at(I, Irs, oy + ry, ox + rx, g) - cI : 0.f;
+        },
+        [&](int ry, int rx) -> float {
+            return inside(ry, rx) ? subsample_at(Pc, Prs, oy + ry, ox + rx, g) - cP : 0.f;
+        });
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -240,7 +266,7 @@ __global__ __launch_bounds__(kThreads) void k_coeff_slide(const T *__restrict__ 
         const int ly = ty0 + r0 + t;
         if (ly < g.Hl && lx < g.Wl) {
             float a, b;
-            coeff_from_sums((double)(clip_len(ly, R, g.Hl) * nx), Su, Suu, Sv, Suv, cI, cP, g.eps, a, b);
+            coeff_from_sums(clip_len(ly, R, g.Hl) * nx, Su, Suu, Sv, Suv, cI, cP, g.eps, a, b);
             ac[(int64_t)ly * g.lrs + lx] = a;
             bc[(int64_t)ly * g.lrs + lx] = b;
         }
@@ -286,8 +312,7 @@ __global__ __launch_bounds__(kThreads) void k_coeff_sep(const T *__restrict__ I,
         return inside(ry, rx) ? subsample_at(Pc, Prs, oy + ry, ox + rx, g) - cP : 0.f;
     };
     if (STAGE) {
-        fill_region(sU, SH, SW, gU);
-        fill_region(sV, SH, SW, gV);
+        fill_region2(sU, sV, SH, SW, gU, gV);
         __syncthreads();
     }
     for (int it = threadIdx.x; it < SH * RUNS; it += kThreads) {
@@ -351,7 +376,7 @@ __global__ __launch_bounds__(kThreads) void k_coeff_sep(const T *__restrict__ I,
         const int ly = ty0 + r0 + t;
         if (ly < g.Hl && lx < g.Wl) {
             float a, b;
-            coeff_from_sums((double)(clip_len(ly, R, g.Hl) * nx), S[0], S[1], S[2], S[3], cI, cP, g.eps, a, b);
+            coeff_from_sums(clip_len(ly, R, g.Hl) * nx, S[0], S[1], S[2], S[3], cI, cP, g.eps, a, b);
             ac[(int64_t)ly * g.lrs + lx] = a;
             bc[(int64_t)ly * g.lrs + lx] = b;
         }

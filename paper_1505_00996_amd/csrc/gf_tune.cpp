@@ -1,0 +1,227 @@
+// Tile-shape autotuner for the window-sum kernels, pinned shapes, and their
+// JSON cache (gf_ctx_set_tiles, gf_tune, gf_ctx_save_tuning,
+// gf_ctx_load_tuning).
+#include <hip/hip_runtime_api.h>
+
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "gf_api_internal.h"
+
+namespace gf {
+
+static TileCfg from_abi(const gf_tiles &t) {
+    TileCfg c;
+    c.coeff_slide = t.coeff_slide;
+    c.coeff_th = t.coeff_th;
+    c.coeff_tw = t.coeff_tw;
+    c.coeff_stage = t.coeff_stage;
+    c.box_slide = t.box_slide;
+    c.box_th = t.box_th;
+    c.box_stage = t.box_stage;
+    return c;
+}
+
+static gf_tiles to_abi(const TileCfg &c) {
+    gf_tiles t;
+    t.coeff_slide = c.coeff_slide;
+    t.coeff_th = c.coeff_th;
+    t.coeff_tw = c.coeff_tw;
+    t.coeff_stage = c.coeff_stage;
+    t.box_slide = c.box_slide;
+    t.box_th = c.box_th;
+    t.box_stage = c.box_stage;
+    return t;
+}
+
+// Candidates of one kernel; the other kernel's fields are taken from `base`.
+static std::vector<TileCfg> candidates(const Geo &g, const TileCfg &base, int kernel) {
+    std::vector<TileCfg> out;
+    auto push = [&](TileCfg c) {
+        if (tiles_fit(g, c)) out.push_back(c);
+    };
+    if (kernel == GF_K_COEFF) {
+        if (g.R <= 16)
+            for (int th : {4, 8, 16}) {
+                TileCfg c = base;
+                c.coeff_slide = 1;
+                c.coeff_th = th;
+                c.coeff_tw = 64;
+                c.coeff_stage = 1;
+                push(c);
+            }
+        for (int th : {8, 16, 32})
+            for (int tw : {32, 64})
+                for (int st : {1, 0}) {
+                    TileCfg c = base;
+                    c.coeff_slide = 0;
+                    c.coeff_th = th;
+                    c.coeff_tw = tw;
+                    c.coeff_stage = st;
+                    push(c);
+                }
+    } else {
+        if (g.R <= 16)
+            for (int th : {4, 8, 16}) {
+                TileCfg c = base;
+                c.box_slide = 1;
+                c.box_th = th;
+                c.box_stage = 1;
+                push(c);
+            }
+        for (int th : {8, 16, 32})
+            for (int st : {1, 0}) {
+                TileCfg c = base;
+                c.box_slide = 0;
+                c.box_th = th;
+                c.box_stage = st;
+                push(c);
+            }
+    }
+    return out;
+}
+
+}  // namespace gf
+
+using namespace gf;
+
+extern "C" {
+
+gf_status gf_ctx_set_tiles(gf_ctx *ctx, gf_dtype dtype, int32_t h, int32_t w, int32_t c,
+                           const gf_params *pr, const gf_tiles *tiles) {
+    if (!ctx || !pr) return fail(GF_EINVAL, "gf_ctx_set_tiles: null argument");
+    if (h < 1 || w < 1 || c < 1 || pr->s < 1 || pr->r < 0)
+        return fail(GF_EINVAL, "gf_ctx_set_tiles: bad problem size");
+    const uint64_t key = tile_key(dtype, h, w, c, pr->r, pr->s);
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    if (!tiles) {
+        ctx->tuned.erase(key);
+        return GF_OK;
+    }
+    const Geo g = make_geo(h, w, c, pr->r, pr->s, pr->eps, (int)pr->sub);
+    const TileCfg t = from_abi(*tiles);
+    if (!tiles_fit(g, t)) return fail(GF_ENOTSUP, "tile shapes do not fit r'=%d", g.R);
+    ctx->tuned[key] = t;
+    return GF_OK;
+}
+
+gf_status gf_tune(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
+                  const gf_params *pr, void *ws, size_t ws_bytes, void *stream, int32_t reps,
+                  gf_tiles *best, gf_tune_result *results, int32_t max_results, int32_t *n_results) {
+    if (!ctx) return fail(GF_EINVAL, "gf_tune needs a context");
+    gf_status st = validate(I, p, q, pr);
+    if (st != GF_OK) return st;
+    if ((st = ctx_use_device(ctx)) != GF_OK) return st;
+    if (reps < 1) reps = 1;
+    const Geo g = make_geo(I->h, I->w, p->c, pr->r, pr->s, pr->eps, (int)pr->sub);
+    if (!ws) {
+        ws_bytes = workspace_bytes(g);
+        if ((st = ctx_workspace(ctx, ws_bytes, &ws)) != GF_OK) return st;
+    }
+    if (ws_bytes < workspace_bytes(g)) return fail(GF_ENOMEM, "workspace too small");
+    if ((uintptr_t)ws % 256) return fail(GF_EINVAL, "workspace not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    float *coef = (float *)ws;
+    float *mean = coef + (size_t)(2 * g.C) * g.lps;
+    const View vI{I->data, I->row_stride, I->plane_stride};
+    const View vP{p->data, p->row_stride, p->plane_stride};
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(GF_EDEVICE, "hipEventCreate failed");
+    }
+    TileCfg chosen = default_tiles(g);
+    int nres = 0;
+    st = GF_OK;
+    for (int kernel : {GF_K_COEFF, GF_K_BOX}) {
+        double best_ms = 1e30;
+        TileCfg best_cfg = chosen;
+        for (const TileCfg &c : candidates(g, chosen, kernel)) {
+            auto launch = [&]() -> hipError_t {
+                return kernel == GF_K_COEFF ? launch_coeff(I->dtype, vI, vP, coef, g, c, s)
+                                            : launch_box(coef, mean, g, c, s);
+            };
+            hipError_t e = launch();  // warm-up (also leaves valid a, b for the box candidates)
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int i = 0; e == hipSuccess && i < reps; ++i) e = launch();
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                st = fail(GF_EDEVICE, "tuning launch failed: %s", hipGetErrorString(e));
+                break;
+            }
+            const double per = (double)ms / reps;
+            if (results && nres < max_results) results[nres] = gf_tune_result{kernel, to_abi(c), per};
+            ++nres;
+            if (per < best_ms) {
+                best_ms = per;
+                best_cfg = c;
+            }
+        }
+        if (st != GF_OK) break;
+        chosen = best_cfg;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (n_results) *n_results = nres < max_results ? nres : max_results;
+    if (st != GF_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(ctx->tune_mu);
+        ctx->tuned[tile_key(I->dtype, I->h, I->w, p->c, pr->r, pr->s)] = chosen;
+    }
+    if (best) *best = to_abi(chosen);
+    // leave q holding a valid result computed with the chosen shapes
+    return run_fast(ctx, I, p, q, pr, ws, ws_bytes, s, &chosen);
+}
+
+gf_status gf_ctx_save_tuning(gf_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(GF_EINVAL, "gf_ctx_save_tuning: null argument");
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(GF_EINVAL, "cannot open %s for writing", path);
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    fprintf(f, "{\"format\": \"gf-tiles-1\", \"arch\": \"gfx950\", \"entries\": [\n");
+    size_t i = 0;
+    for (const auto &kv : ctx->tuned) {
+        const TileCfg &t = kv.second;
+        fprintf(f,
+                "{\"key\": %llu, \"coeff_slide\": %d, \"coeff_th\": %d, \"coeff_tw\": %d, "
+                "\"coeff_stage\": %d, \"box_slide\": %d, \"box_th\": %d, \"box_stage\": %d}%s\n",
+                (unsigned long long)kv.first, t.coeff_slide, t.coeff_th, t.coeff_tw, t.coeff_stage,
+                t.box_slide, t.box_th, t.box_stage, ++i < ctx->tuned.size() ? "," : "");
+    }
+    fprintf(f, "]}\n");
+    const bool ok = fclose(f) == 0;
+    return ok ? GF_OK : fail(GF_EINVAL, "write to %s failed", path);
+}
+
+gf_status gf_ctx_load_tuning(gf_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(GF_EINVAL, "gf_ctx_load_tuning: null argument");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(GF_EINVAL, "cannot open %s", path);
+    char line[512];
+    gf_status st = GF_OK;
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    while (fgets(line, sizeof line, f)) {
+        if (!strstr(line, "\"key\"")) continue;
+        unsigned long long key = 0;
+        TileCfg t;
+        if (sscanf(line,
+                   " {\"key\": %llu, \"coeff_slide\": %d, \"coeff_th\": %d, \"coeff_tw\": %d, "
+                   "\"coeff_stage\": %d, \"box_slide\": %d, \"box_th\": %d, \"box_stage\": %d",
+                   &key, &t.coeff_slide, &t.coeff_th, &t.coeff_tw, &t.coeff_stage, &t.box_slide,
+                   &t.box_th, &t.box_stage) != 8) {
+            st = fail(GF_EINVAL, "malformed tuning entry in %s: %s", path, line);
+            break;
+        }
+        ctx->tuned[(uint64_t)key] = t;
+    }
+    fclose(f);
+    return st;
+}
+
+}  // extern "C"
