@@ -171,6 +171,31 @@ def main():
     ms_plain = timed(step_plain, 0, plain_steps)
     print(f"# plain: {ms_plain:.4f} ms/step", file=sys.stderr, flush=True)
 
+    # Attainable-bandwidth references measured on this GPU (context for the
+    # roofline fraction): a torch broadcast multiply with the same traffic
+    # pattern as the output kernel (read one H x W plane, write three), a
+    # torch copy and a torch fill, each on fresh 1 GiB-class buffers.
+    def bw(fn, nbytes, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return nbytes * reps / (time.perf_counter() - t0) / 1e9
+
+    src_I = sets[0][0]
+    out3 = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    big = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+    big2 = torch.empty_like(big)
+    ceilings = {
+        "read1_write3_torch_mul_GBs": round(bw(lambda: torch.mul(src_I.expand(3, H, W), 1.0, out=out3),
+                                               4 * H * W * 4), 1),
+        "copy_torch_GBs": round(bw(lambda: big2.copy_(big), 2 * big.numel() * 4), 1),
+        "fill_torch_GBs": round(bw(lambda: big.fill_(0.5), big.numel() * 4), 1),
+    }
+    del big, big2, out3
+
     mpix = H * W / 1e6
     out_ms, out_n = kt["output"]
     out_avg_ms = out_ms / max(out_n, 1)
@@ -202,6 +227,7 @@ def main():
         "speedup_vs_plain": round(ms_plain / ms_fast, 3),
         "ms_per_step_with_kernel_events": round(ms_fast_ev, 5),
         "kernels": kernels,
+        "bandwidth_references": ceilings,
         "roofline": {"kernel": "k_output (bilinear upsample + q = mean_a*I + mean_b)",
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

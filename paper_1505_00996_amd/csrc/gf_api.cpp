@@ -88,7 +88,7 @@ TileCfg default_tiles(const Geo &g) {
         t.coeff_tw = 32;
         t.coeff_stage = 1;
         if (coeff_lds_bytes(t, g.R) > kStageMax) t.coeff_stage = 0;
-        if (coeff_lds_bytes(t, g.R) > kLdsMax) t.coeff_th = 8;
+        if (coeff_lds_bytes(t, g.R) > kLdsMax) t.coeff_th = 8;  // unstaged 8 x 32
     }
     if (t.box_slide) {
         t.box_th = 8;
@@ -103,9 +103,12 @@ TileCfg default_tiles(const Geo &g) {
 }
 
 bool tiles_fit(const Geo &g, const TileCfg &t) {
+    // separable coefficient shapes built: staged 16x32, 16x64, 32x32, 32x64; unstaged 8x32, 16x32
     const bool cs = t.coeff_slide ? (t.coeff_th == 4 || t.coeff_th == 8 || t.coeff_th == 16)
-                                  : ((t.coeff_th == 8 || t.coeff_th == 16 || t.coeff_th == 32) &&
-                                     (t.coeff_tw == 32 || t.coeff_tw == 64));
+                                  : (t.coeff_stage ? ((t.coeff_th == 16 || t.coeff_th == 32) &&
+                                                      (t.coeff_tw == 32 || t.coeff_tw == 64))
+                                                   : ((t.coeff_th == 8 || t.coeff_th == 16) &&
+                                                      t.coeff_tw == 32));
     const bool bs = t.box_slide ? (t.box_th == 4 || t.box_th == 8 || t.box_th == 16)
                                 : (t.box_th == 8 || t.box_th == 16 || t.box_th == 32);
     return cs && bs && coeff_lds_bytes(t, g.R) <= kLdsMax && box_lds_bytes(t, g.R) <= kLdsMax;

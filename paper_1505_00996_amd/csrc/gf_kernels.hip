@@ -102,23 +102,44 @@ __device__ __forceinline__ int xcd_tile(int bid) {
     return (bid & 7) * per + (bid >> 3);
 }
 
-// Algorithm 2 step 1 at low-res pixel (ly, lx): nearest takes full-res
-// s*ly + floor(s/2); bilinear with even s averages the two pixels around the
-// low-res centre s*ly + (s-1)/2 on each axis; taps clamp to the image.
-template <typename T>
-__device__ __forceinline__ float subsample_at(const T *__restrict__ img, int64_t rs, int ly, int lx,
-                                              const Geo &g) {
+// Algorithm 2 step 1, the sample of the low-res map at (ly, lx), which the
+// caller keeps inside [0, Hl) x [0, Wl).  The kind is fixed per launch, so
+// the loads carry no data-dependent branch and a batch of them can be in
+// flight together:
+//   kSubId   s = 1: the image itself;
+//   kSubNear nearest: full-res s*ly + floor(s/2), clamped to the image (also
+//            bilinear with odd s, whose sample centre falls on a pixel);
+//   kSubLin  bilinear with even s: the mean of the two pixels on each side
+//            of the low-res centre s*ly + (s-1)/2, taps clamped.
+constexpr int kSubId = 0, kSubNear = 1, kSubLin = 2;
+
+template <int K, typename T>
+__device__ __forceinline__ float sample(const T *__restrict__ img, int64_t rs, int ly, int lx,
+                                        const Geo &g) {
     const int s = g.s;
-    if (s == 1) return ld(img + (int64_t)ly * rs + lx);
-    if (g.sub == GF_SUB_NEAREST || (s & 1)) {
+    if constexpr (K == kSubId) {
+        return ld(img + (int64_t)ly * rs + lx);
+    } else if constexpr (K == kSubNear) {
         const int y = min(s * ly + (s >> 1), g.H - 1), x = min(s * lx + (s >> 1), g.W - 1);
         return ld(img + (int64_t)y * rs + x);
+    } else {
+        const int y0 = min(s * ly + (s >> 1) - 1, g.H - 1), y1 = min(s * ly + (s >> 1), g.H - 1);
+        const int x0 = min(s * lx + (s >> 1) - 1, g.W - 1), x1 = min(s * lx + (s >> 1), g.W - 1);
+        const float v00 = ld(img + (int64_t)y0 * rs + x0), v01 = ld(img + (int64_t)y0 * rs + x1);
+        const float v10 = ld(img + (int64_t)y1 * rs + x0), v11 = ld(img + (int64_t)y1 * rs + x1);
+        return 0.5f * (0.5f * v00 + 0.5f * v01) + 0.5f * (0.5f * v10 + 0.5f * v11);
     }
-    const int y0 = min(s * ly + (s >> 1) - 1, g.H - 1), y1 = min(s * ly + (s >> 1), g.H - 1);
-    const int x0 = min(s * lx + (s >> 1) - 1, g.W - 1), x1 = min(s * lx + (s >> 1), g.W - 1);
-    const float v00 = ld(img + (int64_t)y0 * rs + x0), v01 = ld(img + (int64_t)y0 * rs + x1);
-    const float v10 = ld(img + (int64_t)y1 * rs + x0), v11 = ld(img + (int64_t)y1 * rs + x1);
-    return 0.5f * (0.5f * v00 + 0.5f * v01) + 0.5f * (0.5f * v10 + 0.5f * v11);
+}
+
+// Sample at region position (ly, lx) shifted by c, or 0 outside the
+// low-res map: the load always reads a clamped, valid address and the
+// outside case is a select, not a branch.
+template <int K, typename T>
+__device__ __forceinline__ float sample_shifted(const T *__restrict__ img, int64_t rs, int ly, int lx,
+                                                float c, const Geo &g) {
+    const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
+    const float v = sample<K>(img, rs, clampi(ly, 0, g.Hl - 1), clampi(lx, 0, g.Wl - 1), g);
+    return in ? v - c : 0.f;
 }
 
 // ------------------------------------------------------- staging helpers
@@ -135,10 +156,10 @@ __device__ __forceinline__ void fill_region(float *dst, int SH, int SW, F f) {
     for (int base = 0; base < n; base += kFillPer * kThreads) {
         float v[kFillPer];
 #pragma unroll
-        for (int b = 0; b < kFillPer; ++b) {
-            const int e = base + b * kThreads + (int)threadIdx.x;
+        for (int b = 0; b < kFillPer; ++b) {  // clamped index: every load is unconditional
+            const int e = min(base + b * kThreads + (int)threadIdx.x, n - 1);
             const int ry = e / SW;
-            v[b] = e < n ? f(ry, e - ry * SW) : 0.f;
+            v[b] = f(ry, e - ry * SW);
         }
 #pragma unroll
         for (int b = 0; b < kFillPer; ++b) {
@@ -154,11 +175,11 @@ __device__ __forceinline__ void fill_region2(float *d1, float *d2, int SH, int S
     for (int base = 0; base < n; base += kFillPer * kThreads) {
         float v1[kFillPer], v2[kFillPer];
 #pragma unroll
-        for (int b = 0; b < kFillPer; ++b) {
-            const int e = base + b * kThreads + (int)threadIdx.x;
+        for (int b = 0; b < kFillPer; ++b) {  // clamped index: every load is unconditional
+            const int e = min(base + b * kThreads + (int)threadIdx.x, n - 1);
             const int ry = e / SW, rx = e - ry * SW;
-            v1[b] = e < n ? f1(ry, rx) : 0.f;
-            v2[b] = e < n ? f2(ry, rx) : 0.f;
+            v1[b] = f1(ry, rx);
+            v2[b] = f2(ry, rx);
         }
 #pragma unroll
         for (int b = 0; b < kFillPer; ++b) {
@@ -204,7 +225,7 @@ __device__ __forceinline__ void coeff_from_sums(int n, double Su, double Suu, do
 // lane owns one output column and slides the (2r'+1)^2 window down TH rows:
 // the row entering the window is added and the row leaving it subtracted,
 // tap by tap, into FP64 sums.  No row-sum buffer, one barrier.
-template <typename T, int TH>
+template <typename T, int K, int TH>
 __global__ __launch_bounds__(kThreads) void k_coeff_slide(const T *__restrict__ I, int64_t Irs,
                                                           const T *__restrict__ P, int64_t Prs,
                                                           int64_t Pps, float *__restrict__ coef,
@@ -219,20 +240,12 @@ __global__ __launch_bounds__(kThreads) void k_coeff_slide(const T *__restrict__ 
     const T *Pc = P + (int64_t)c * Pps;
     float *sU = lds, *sV = lds + SH * SW;
 
-    const float cI = subsample_at(I, Irs, ty0, tx0, g);
-    const float cP = subsample_at(Pc, Prs, ty0, tx0, g);
-    auto inside = [&](int ry, int rx) {
-        const int ly = oy + ry, lx = ox + rx;
-        return ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
-    };
+    const float cI = sample<K>(I, Irs, ty0, tx0, g);
+    const float cP = sample<K>(Pc, Prs, ty0, tx0, g);
     fill_region2(
         sU, sV, SH, SW,
-        [&](int ry, int rx) -> float {
-            return inside(ry, rx) ? subsample_at(I, Irs, oy + ry, ox + rx, g) - cI : 0.f;
-        },
-        [&](int ry, int rx) -> float {
-            return inside(ry, rx) ? subsample_at(Pc, Prs, oy + ry, ox + rx, g) - cP : 0.f;
-        });
+        [&](int ry, int rx) { return sample_shifted<K>(I, Irs, oy + ry, ox + rx, cI, g); },
+        [&](int ry, int rx) { return sample_shifted<K>(Pc, Prs, oy + ry, ox + rx, cP, g); });
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -279,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void k_coeff_slide(const T *__restrict__ 
 // LDS.  Column pass: each thread owns one column and LC consecutive output
 // rows and slides the sums down.  Used when the (2r'+1)^2 taps per output of
 // k_coeff_slide would cost more than the two passes.
-template <typename T, int TH, int TW, bool STAGE>
+template <typename T, int K, int TH, int TW, bool STAGE>
 __global__ __launch_bounds__(kThreads) void k_coeff_sep(const T *__restrict__ I, int64_t Irs,
                                                         const T *__restrict__ P, int64_t Prs,
                                                         int64_t Pps, float *__restrict__ coef,
@@ -299,18 +312,10 @@ __global__ __launch_bounds__(kThreads) void k_coeff_sep(const T *__restrict__ I,
     float *sU = (float *)(rs + 4 * plane);         // staged u, v (STAGE only)
     float *sV = sU + SH * SW;
 
-    const float cI = subsample_at(I, Irs, ty0, tx0, g);
-    const float cP = subsample_at(Pc, Prs, ty0, tx0, g);
-    auto inside = [&](int ry, int rx) {
-        const int ly = oy + ry, lx = ox + rx;
-        return ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
-    };
-    auto gU = [&](int ry, int rx) -> float {
-        return inside(ry, rx) ? subsample_at(I, Irs, oy + ry, ox + rx, g) - cI : 0.f;
-    };
-    auto gV = [&](int ry, int rx) -> float {
-        return inside(ry, rx) ? subsample_at(Pc, Prs, oy + ry, ox + rx, g) - cP : 0.f;
-    };
+    const float cI = sample<K>(I, Irs, ty0, tx0, g);
+    const float cP = sample<K>(Pc, Prs, ty0, tx0, g);
+    auto gU = [&](int ry, int rx) { return sample_shifted<K>(I, Irs, oy + ry, ox + rx, cI, g); };
+    auto gV = [&](int ry, int rx) { return sample_shifted<K>(Pc, Prs, oy + ry, ox + rx, cP, g); };
     if (STAGE) {
         fill_region2(sU, sV, SH, SW, gU, gV);
         __syncthreads();
@@ -404,7 +409,9 @@ __global__ __launch_bounds__(kThreads) void k_box_slide(const float *__restrict_
     float *sX = lds;
     fill_region(sX, SH, SW, [&](int ry, int rx) -> float {
         const int ly = oy + ry, lx = ox + rx;
-        return (ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl) ? S[(int64_t)ly * g.lrs + lx] : 0.f;
+        const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
+        const float v = S[(int64_t)clampi(ly, 0, g.Hl - 1) * g.lrs + clampi(lx, 0, g.Wl - 1)];
+        return in ? v : 0.f;
     });
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -446,7 +453,9 @@ __global__ __launch_bounds__(kThreads) void k_box_sep(const float *__restrict__ 
     float *sX = (float *)(rA + SH * TW);
     auto gX = [&](int ry, int rx) -> float {
         const int ly = oy + ry, lx = ox + rx;
-        return (ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl) ? S[(int64_t)ly * g.lrs + lx] : 0.f;
+        const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
+        const float v = S[(int64_t)clampi(ly, 0, g.Hl - 1) * g.lrs + clampi(lx, 0, g.Wl - 1)];
+        return in ? v : 0.f;
     };
     if (STAGE) {
         fill_region(sX, SH, SW, gX);
@@ -678,9 +687,9 @@ void allow_lds(K kernel, size_t bytes) {
                                   (int)bytes);
 }
 
-template <typename T>
-hipError_t coeff_t(const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
-                   hipStream_t st) {
+template <typename T, int K>
+hipError_t coeff_tk(const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
+                    hipStream_t st) {
     const T *Ip = (const T *)I.data, *Pp = (const T *)P.data;
     const dim3 block(kThreads);
     const size_t lds = coeff_lds_bytes(t, g.R);
@@ -688,11 +697,11 @@ hipError_t coeff_t(const View &I, const View &P, float *coef, const Geo &g, cons
         const int ntx = (g.Wl + 63) / 64, nty = (g.Hl + 4 * t.coeff_th - 1) / (4 * t.coeff_th);
         const int ntiles = ntx * nty;
         const dim3 grid(grid8(ntiles), g.C);
-#define GF_SLIDE(TH)                                                                             \
-    {                                                                                            \
-        allow_lds(k_coeff_slide<T, TH>, lds);                                                    \
-        hipLaunchKernelGGL((k_coeff_slide<T, TH>), grid, block, lds, st, Ip, I.rs, Pp, P.rs, P.ps, \
-                           coef, g, ntx, ntiles);                                                \
+#define GF_SLIDE(TH)                                                                               \
+    {                                                                                              \
+        allow_lds(k_coeff_slide<T, K, TH>, lds);                                                   \
+        hipLaunchKernelGGL((k_coeff_slide<T, K, TH>), grid, block, lds, st, Ip, I.rs, Pp, P.rs, P.ps, \
+                           coef, g, ntx, ntiles);                                                  \
     }
         if (t.coeff_th == 4) GF_SLIDE(4) else if (t.coeff_th == 8) GF_SLIDE(8) else GF_SLIDE(16)
 #undef GF_SLIDE
@@ -702,24 +711,29 @@ hipError_t coeff_t(const View &I, const View &P, float *coef, const Geo &g, cons
     const int nty = (g.Hl + t.coeff_th - 1) / t.coeff_th;
     const int ntiles = ntx * nty;
     const dim3 grid(grid8(ntiles), g.C);
-#define GF_SEP(TH, TW, STG)                                                                        \
-    {                                                                                              \
-        allow_lds(k_coeff_sep<T, TH, TW, STG>, lds);                                               \
-        hipLaunchKernelGGL((k_coeff_sep<T, TH, TW, STG>), grid, block, lds, st, Ip, I.rs, Pp, P.rs, \
-                           P.ps, coef, g, ntx, ntiles);                                            \
+#define GF_SEP(TH, TW, STG)                                                                           \
+    {                                                                                                 \
+        allow_lds(k_coeff_sep<T, K, TH, TW, STG>, lds);                                               \
+        hipLaunchKernelGGL((k_coeff_sep<T, K, TH, TW, STG>), grid, block, lds, st, Ip, I.rs, Pp, P.rs, \
+                           P.ps, coef, g, ntx, ntiles);                                               \
     }
-#define GF_SEP_S(TH, TW) \
-    if (t.coeff_stage) GF_SEP(TH, TW, true) else GF_SEP(TH, TW, false)
-    if (t.coeff_th == 32) {
-        if (t.coeff_tw == 64) GF_SEP_S(32, 64) else GF_SEP_S(32, 32)
-    } else if (t.coeff_th == 16) {
-        if (t.coeff_tw == 64) GF_SEP_S(16, 64) else GF_SEP_S(16, 32)
+    if (!t.coeff_stage) {
+        if (t.coeff_th == 8) GF_SEP(8, 32, false) else GF_SEP(16, 32, false)
+    } else if (t.coeff_th == 32) {
+        if (t.coeff_tw == 64) GF_SEP(32, 64, true) else GF_SEP(32, 32, true)
     } else {
-        if (t.coeff_tw == 64) GF_SEP_S(8, 64) else GF_SEP_S(8, 32)
+        if (t.coeff_tw == 64) GF_SEP(16, 64, true) else GF_SEP(16, 32, true)
     }
-#undef GF_SEP_S
 #undef GF_SEP
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t coeff_t(const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
+                   hipStream_t st) {
+    if (g.s == 1) return coeff_tk<T, kSubId>(I, P, coef, g, t, st);
+    if (g.sub == GF_SUB_NEAREST || (g.s & 1)) return coeff_tk<T, kSubNear>(I, P, coef, g, t, st);
+    return coeff_tk<T, kSubLin>(I, P, coef, g, t, st);
 }
 
 template <typename T, int CC>

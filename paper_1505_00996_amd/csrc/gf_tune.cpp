@@ -60,7 +60,7 @@ static std::vector<TileCfg> candidates(const Geo &g, const TileCfg &base, int ke
                     c.coeff_th = th;
                     c.coeff_tw = tw;
                     c.coeff_stage = st;
-                    push(c);
+                    push(c);  // shapes that are not built fail tiles_fit and are skipped
                 }
     } else {
         if (g.R <= 16)

@@ -17,8 +17,10 @@ gfp = gpuutil.ensure_built()
 def coeff_shapes():
     for th in (4, 8, 16):
         yield dict(coeff_slide=1, coeff_th=th, coeff_tw=64, coeff_stage=1)
-    for th, tw, st in itertools.product((8, 16, 32), (32, 64), (0, 1)):
-        yield dict(coeff_slide=0, coeff_th=th, coeff_tw=tw, coeff_stage=st)
+    for th, tw in itertools.product((16, 32), (32, 64)):
+        yield dict(coeff_slide=0, coeff_th=th, coeff_tw=tw, coeff_stage=1)
+    for th in (8, 16):
+        yield dict(coeff_slide=0, coeff_th=th, coeff_tw=32, coeff_stage=0)
 
 
 def box_shapes():
