@@ -215,16 +215,14 @@ gf_status gf_ctx_profile(gf_ctx *ctx, int enable);
 gf_status gf_ctx_profile_read(gf_ctx *ctx, gf_kernel_time *out);
 
 /*
- * Tile shapes of the window-sum kernels (Algorithm 2 steps 2-5).  The
- * coefficient kernel either slides a (2r'+1)^2 window down each column
- * (coeff_slide = 1; a tile is 64 columns x 4*coeff_th rows) or runs a row
- * pass and a column pass (coeff_slide = 0; a tile is coeff_th x coeff_tw,
- * coeff_stage = 1 stages the samples in LDS).  The box-mean kernel has the
- * same two forms (box_*; separable tiles are 64 columns wide).
+ * Tile shapes of the window-sum kernels (Algorithm 2 steps 2-5).  Both the
+ * coefficient kernel and the box-mean kernel work on tiles of 64 low-res
+ * columns by *_th rows (8, 16, 24 or 32) plus an r' halo staged in LDS.
+ * Tall tiles amortise the halo; short ones need less LDS per workgroup.
  */
 typedef struct {
-    int32_t coeff_slide, coeff_th, coeff_tw, coeff_stage;
-    int32_t box_slide, box_th, box_stage;
+    int32_t coeff_th;
+    int32_t box_th;
 } gf_tiles;
 
 typedef struct {

@@ -57,10 +57,7 @@ class gf_kernel_time(ctypes.Structure):
 
 
 class gf_tiles(ctypes.Structure):
-    _fields_ = [("coeff_slide", ctypes.c_int32), ("coeff_th", ctypes.c_int32),
-                ("coeff_tw", ctypes.c_int32), ("coeff_stage", ctypes.c_int32),
-                ("box_slide", ctypes.c_int32), ("box_th", ctypes.c_int32),
-                ("box_stage", ctypes.c_int32)]
+    _fields_ = [("coeff_th", ctypes.c_int32), ("box_th", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -52,66 +52,36 @@ Geo make_geo(int H, int W, int C, int r, int s, double eps, int sub) {
     return g;
 }
 
-size_t coeff_lds_bytes(const TileCfg &t, int R) {
-    if (t.coeff_slide) {  // staged u, v for 64 + 2R columns and 4*th + 2R rows
-        const size_t SH = 4 * t.coeff_th + 2 * R, SW = 64 + 2 * R;
-        return sizeof(float) * 2 * SH * SW;
-    }
-    // 4 planes of FP64 row sums, plus the staged u and v samples
-    const size_t SH = t.coeff_th + 2 * R, SW = t.coeff_tw + 2 * R;
-    return sizeof(double) * 4 * SH * t.coeff_tw + (t.coeff_stage ? sizeof(float) * 2 * SH * SW : 0);
-}
-
-size_t box_lds_bytes(const TileCfg &t, int R) {
-    if (t.box_slide) {
-        const size_t SH = 4 * t.box_th + 2 * R, SW = 64 + 2 * R;
-        return sizeof(float) * SH * SW;
-    }
-    const size_t SH = t.box_th + 2 * R, SW = kTileW + 2 * R;
-    return sizeof(double) * SH * kTileW + (t.box_stage ? sizeof(float) * SH * SW : 0);
-}
-
 static const size_t kLdsMax = 160 * 1024;
-static const size_t kStageMax = 100 * 1024;
-static const int kSlideMaxR = 8;  // above this the separable passes do fewer operations
+
+static bool th_ok(int th) { return th == 8 || th == 16 || th == 24 || th == 32; }
+
+// Tile height: tall tiles amortise the 2r' halo rows, short ones keep the
+// LDS footprint (FP64 row sums) low enough for several workgroups per CU.
+static int pick_th(int R, size_t (*lds)(const TileCfg &, int), bool coeff) {
+    int best = 8;
+    for (int th : {32, 24, 16, 8}) {
+        TileCfg t{th, th};
+        const size_t b = lds(t, R);
+        (void)coeff;
+        if (b <= 64 * 1024 || th == 8) {
+            best = th;
+            break;
+        }
+    }
+    return best;
+}
 
 TileCfg default_tiles(const Geo &g) {
     TileCfg t;
-    t.coeff_slide = g.R <= kSlideMaxR;
-    t.box_slide = g.R <= kSlideMaxR;
-    if (t.coeff_slide) {
-        t.coeff_th = 8;
-        t.coeff_tw = 64;
-        t.coeff_stage = 1;
-    } else {
-        t.coeff_th = 16;
-        t.coeff_tw = 32;
-        t.coeff_stage = 1;
-        if (coeff_lds_bytes(t, g.R) > kStageMax) t.coeff_stage = 0;
-        if (coeff_lds_bytes(t, g.R) > kLdsMax) t.coeff_th = 8;  // unstaged 8 x 32
-    }
-    if (t.box_slide) {
-        t.box_th = 8;
-        t.box_stage = 1;
-    } else {
-        t.box_th = 16;
-        t.box_stage = 1;
-        if (box_lds_bytes(t, g.R) > kStageMax) t.box_stage = 0;
-        if (box_lds_bytes(t, g.R) > kLdsMax) t.box_th = 8;
-    }
+    t.coeff_th = pick_th(g.R, coeff_lds_bytes, true);
+    t.box_th = pick_th(g.R, box_lds_bytes, false);
     return t;
 }
 
 bool tiles_fit(const Geo &g, const TileCfg &t) {
-    // separable coefficient shapes built: staged 16x32, 16x64, 32x32, 32x64; unstaged 8x32, 16x32
-    const bool cs = t.coeff_slide ? (t.coeff_th == 4 || t.coeff_th == 8 || t.coeff_th == 16)
-                                  : (t.coeff_stage ? ((t.coeff_th == 16 || t.coeff_th == 32) &&
-                                                      (t.coeff_tw == 32 || t.coeff_tw == 64))
-                                                   : ((t.coeff_th == 8 || t.coeff_th == 16) &&
-                                                      t.coeff_tw == 32));
-    const bool bs = t.box_slide ? (t.box_th == 4 || t.box_th == 8 || t.box_th == 16)
-                                : (t.box_th == 8 || t.box_th == 16 || t.box_th == 32);
-    return cs && bs && coeff_lds_bytes(t, g.R) <= kLdsMax && box_lds_bytes(t, g.R) <= kLdsMax;
+    return th_ok(t.coeff_th) && th_ok(t.box_th) && coeff_lds_bytes(t, g.R) <= kLdsMax &&
+           box_lds_bytes(t, g.R) <= kLdsMax;
 }
 
 size_t workspace_bytes(const Geo &g) {

@@ -1,0 +1,574 @@
+// Device code of the (fast) guided filter for gfx950 (CDNA4, wave64): the
+// per-tile work of Algorithm 2 of He & Sun, "Fast Guided Filter", written as
+// device functions so that the per-image kernels (gf_kernels.hip) and the
+// persistent batched kernel (gf_batched.hip) run the same code.
+//
+//   coeff_tile  : subsample I and p (step 1) while staging a low-res tile and
+//                 its r' halo in LDS; window sums of I', I'^2, p', I'p'
+//                 (step 2); var, cov (step 3) and a, b of Eqs. 2-3 (step 4).
+//   box_tile    : clip-normalised box mean of one coefficient map (step 5).
+//   output_tile : bilinear upsampling of mean_a, mean_b fused with
+//                 q = mean_a * I + mean_b against the full-resolution I
+//                 (steps 6-7); the HBM-bound pass.
+//
+// Every tile function is called by a whole 256-thread workgroup (4 waves);
+// coeff_tile and box_tile use __syncthreads and LDS passed in by the caller.
+//
+// Window sums: a row pass (each thread slides a (2r'+1)-wide window over
+// kRun consecutive outputs of one region row) writes row sums to LDS; a
+// column pass (each thread owns one column and TH/4 consecutive output rows)
+// slides over them.  The statistics of step 2 are summed in FP64: in a flat
+// window mean(I*I) - mean(I)^2 and mean(I*p) - mean(I) mean(p) cancel almost
+// completely, FP64 leaves ~1e-16 of rounding there (FP32 would leave ~1e-8,
+// which moves a by percent at eps = 1e-6), and products of FP32 samples are
+// exact in FP64.  On gfx950 an FP64 add or FMA issues at the rate of a
+// non-packed FP32 one.  Samples are also shifted by the tile's first sample,
+// which keeps the sums small.  The box means of a and b have no cancellation
+// and are summed in FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "gf_internal.h"
+
+namespace gf {
+namespace dev {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
+struct bf16 {
+    unsigned short bits;
+};
+
+// ---------------------------------------------------------------- storage
+
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ float to_f32(_Float16 v) { return (float)v; }
+__device__ __forceinline__ float to_f32(bf16 v) { return __uint_as_float((unsigned)v.bits << 16); }
+
+// float -> bfloat16, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ unsigned short f32_to_bf16_bits(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+template <typename T> __device__ __forceinline__ T from_f32(float v);
+template <> __device__ __forceinline__ float from_f32<float>(float v) { return v; }
+template <> __device__ __forceinline__ _Float16 from_f32<_Float16>(float v) { return (_Float16)v; }
+template <> __device__ __forceinline__ bf16 from_f32<bf16>(float v) { return bf16{f32_to_bf16_bits(v)}; }
+
+template <typename T> __device__ __forceinline__ float ld(const T *p) { return to_f32(*p); }
+
+// Four consecutive elements, 16 bytes (fp32) or 8 bytes (16-bit), aligned.
+__device__ __forceinline__ f32x4 ld4(const float *p) { return *(const f32x4 *)p; }
+__device__ __forceinline__ f32x4 ld4(const _Float16 *p) {
+    f16x4 h = *(const f16x4 *)p;
+    return f32x4{(float)h.x, (float)h.y, (float)h.z, (float)h.w};
+}
+__device__ __forceinline__ f32x4 ld4(const bf16 *p) {
+    u16x4 b = *(const u16x4 *)p;
+    return f32x4{__uint_as_float((unsigned)b.x << 16), __uint_as_float((unsigned)b.y << 16),
+                 __uint_as_float((unsigned)b.z << 16), __uint_as_float((unsigned)b.w << 16)};
+}
+
+// Streaming (non-temporal) stores of four outputs.
+__device__ __forceinline__ void st4(float *p, f32x4 v) { __builtin_nontemporal_store(v, (f32x4 *)p); }
+__device__ __forceinline__ void st4(_Float16 *p, f32x4 v) {
+    f16x4 h = {(_Float16)v.x, (_Float16)v.y, (_Float16)v.z, (_Float16)v.w};
+    __builtin_nontemporal_store(h, (f16x4 *)p);
+}
+__device__ __forceinline__ void st4(bf16 *p, f32x4 v) {
+    u16x4 b = {f32_to_bf16_bits(v.x), f32_to_bf16_bits(v.y), f32_to_bf16_bits(v.z),
+               f32_to_bf16_bits(v.w)};
+    __builtin_nontemporal_store(b, (u16x4 *)p);
+}
+template <typename T> __device__ __forceinline__ void st1(T *p, float v) { *p = from_f32<T>(v); }
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int floordiv(int a, int b) {  // b > 0
+    int q = a / b;
+    return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Number of in-image positions of a radius-R window centred at i on an n-axis.
+__device__ __forceinline__ int clip_len(int i, int R, int n) {
+    return min(n - 1, i + R) - max(0, i - R) + 1;
+}
+
+// Wave index as a scalar, so values derived from it stay in SGPRs.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6); }
+
+// Approximate reciprocal (1 ulp): the results it feeds tolerate 1e-7.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// ---------------------------------------------------------------- sampling
+//
+// Algorithm 2 step 1, the low-res sample at (ly, lx) inside [0,Hl) x [0,Wl).
+// The kind is fixed per launch, so the loads carry no data-dependent branch:
+//   kSubId   s = 1: the image itself;
+//   kSubNear nearest: full-res s*ly + floor(s/2), clamped to the image (also
+//            bilinear with odd s, whose sample centre falls on a pixel);
+//   kSubLin  bilinear with even s: the mean of the two pixels on each side
+//            of the low-res centre s*ly + (s-1)/2, taps clamped.
+// A sample is split into a row part (uniform across a wave in the fills, so
+// the row address stays scalar) and a column part (per lane).
+constexpr int kSubId = 0, kSubNear = 1, kSubLin = 2;
+
+struct Taps {
+    int a, b;  // full-res indices (b only used by kSubLin)
+};
+
+template <int K>
+__device__ __forceinline__ Taps taps(int l, int s, int n) {
+    if constexpr (K == kSubId) {
+        return Taps{l, l};
+    } else if constexpr (K == kSubNear) {
+        return Taps{min(s * l + (s >> 1), n - 1), 0};
+    } else {
+        return Taps{min(s * l + (s >> 1) - 1, n - 1), min(s * l + (s >> 1), n - 1)};
+    }
+}
+
+template <int K, typename T>
+__device__ __forceinline__ float sample_rc(const T *__restrict__ img, int64_t rs, Taps ry, Taps cx) {
+    const T *r0 = img + (int64_t)ry.a * rs;
+    if constexpr (K != kSubLin) {
+        return ld(r0 + cx.a);
+    } else {
+        const T *r1 = img + (int64_t)ry.b * rs;
+        const float v00 = ld(r0 + cx.a), v01 = ld(r0 + cx.b);
+        const float v10 = ld(r1 + cx.a), v11 = ld(r1 + cx.b);
+        return 0.5f * (0.5f * v00 + 0.5f * v01) + 0.5f * (0.5f * v10 + 0.5f * v11);
+    }
+}
+
+template <int K, typename T>
+__device__ __forceinline__ float sample(const T *__restrict__ img, int64_t rs, int ly, int lx,
+                                        const Geo &g) {
+    return sample_rc<K>(img, rs, taps<K>(ly, g.s, g.H), taps<K>(lx, g.s, g.W));
+}
+
+// ---------------------------------------------------------------- window sums
+
+constexpr int kFillRows = 8;   // region rows per wave per fill batch
+constexpr int kRowW = 65;      // padded row stride (elements) of the row-sum planes
+
+// LDS bytes of coeff_tile / box_tile for a tile of TH rows at radius R.
+__host__ __device__ constexpr int region_stride(int R) { return (kTileW + 2 * R) | 1; }
+__host__ __device__ constexpr size_t coeff_tile_lds(int TH, int R) {
+    return (size_t)2 * (TH + 2 * R) * kRowW * sizeof(double) +
+           (size_t)2 * (TH + 2 * R) * region_stride(R) * sizeof(float);
+}
+__host__ __device__ constexpr size_t box_tile_lds(int TH, int R) {
+    return (size_t)(TH + 2 * R) * kRowW * sizeof(float) +
+           (size_t)(TH + 2 * R) * region_stride(R) * sizeof(float);
+}
+
+// Stage an SH x SW region whose element (ry, rx) is f(ry, rx, c_ry, c_rx):
+// wave w takes rows w, w+4, ...; lanes take columns lane and lane + 64 (and
+// further chunks for wide regions); kFillRows rows x 2 chunks of loads are
+// issued before the first LDS store.  Out-of-range rows/columns are clamped
+// so every load is unconditional; f decides the value kept.
+template <class F>
+__device__ __forceinline__ void fill_tile(float *dst, int SH, int SW, int SWp, F f) {
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    for (int c0 = 0; c0 < SW; c0 += 128) {
+        const int rx0 = c0 + lane, rx1 = c0 + 64 + lane;
+        for (int r0 = wave; r0 < SH; r0 += 4 * kFillRows) {
+            float v0[kFillRows], v1[kFillRows];
+#pragma unroll
+            for (int b = 0; b < kFillRows; ++b) {
+                const int ry = min(r0 + 4 * b, SH - 1);
+                v0[b] = f(ry, min(rx0, SW - 1));
+                v1[b] = f(ry, min(rx1, SW - 1));
+            }
+#pragma unroll
+            for (int b = 0; b < kFillRows; ++b) {
+                const int ry = r0 + 4 * b;
+                if (ry < SH) {
+                    if (rx0 < SW) dst[ry * SWp + rx0] = v0[b];
+                    if (rx1 < SW) dst[ry * SWp + rx1] = v1[b];
+                }
+            }
+        }
+    }
+}
+
+// n^2 var and n^2 cov are the two cancelling differences; they are taken
+// in FP64, everything after them in FP32.  Eqs. 2-3.
+__device__ __forceinline__ void coeff_from_sums(int n, double Su, double Suu, double Sv, double Suv,
+                                                float cI, float cP, float eps, float &a, float &b) {
+    const double nd = (double)n;
+    const float n2var = (float)fmax(nd * Suu - Su * Su, 0.0);
+    const float n2cov = (float)(nd * Suv - Su * Sv);
+    const float rn = rcp((float)n);
+    const float var = n2var * rn * rn;
+    const float cov = n2cov * rn * rn;  // Eq. 2 numerator
+    const float mI = cI + (float)Su * rn, mp = cP + (float)Sv * rn;
+    a = cov * rcp(var + eps);  // Eq. 2
+    b = mp - a * mI;           // Eq. 3
+}
+
+// One TH x 64 tile of a, b (low-res) at tile origin (ty0, tx0), for one
+// channel of p.  The statistics are formed in two phases (I alone, then I
+// with p) so that LDS holds two FP64 row-sum planes instead of four.
+template <typename T, int K, int TH>
+__device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
+                                           const T *__restrict__ Pc, int64_t Prs,
+                                           float *__restrict__ ac, float *__restrict__ bc,
+                                           const Geo &g, int ty0, int tx0, void *lds) {
+    constexpr int LC = TH / 4;  // output rows per thread in the column pass
+    const int R = g.R, SH = TH + 2 * R, SW = kTileW + 2 * R, SWp = region_stride(R);
+    const int plane = SH * kRowW;
+    double *rA = (double *)lds, *rB = rA + plane;
+    float *sU = (float *)(rB + plane), *sV = sU + SH * SWp;
+    const int oy = ty0 - R, ox = tx0 - R;
+    const int lane = threadIdx.x & 63, wave = wave_id();
+
+    const float cI = sample<K>(I, Irs, ty0, tx0, g);
+    const float cP = sample<K>(Pc, Prs, ty0, tx0, g);
+    // u = I' - cI and v = p' - cP over the region, 0 outside the low-res map.
+    // The outside case multiplies by 0 rather than selecting: a select on a
+    // loaded value lets the compiler turn the load into a branch that waits
+    // for it, one load at a time.  The sample read there is an in-image one
+    // (clamped address), so the product is an exact 0 for finite images.
+    auto fill = [&](float *dst, const T *img, int64_t rs, float c) {
+        fill_tile(dst, SH, SW, SWp, [&](int ry, int rx) -> float {
+            const int ly = oy + ry, lx = ox + rx;
+            const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
+            const float v = sample_rc<K>(img, rs, taps<K>(clampi(ly, 0, g.Hl - 1), g.s, g.H),
+                                         taps<K>(clampi(lx, 0, g.Wl - 1), g.s, g.W));
+            return (v - c) * (in ? 1.f : 0.f);
+        });
+    };
+    fill(sU, I, Irs, cI);
+    fill(sV, Pc, Prs, cP);
+    __syncthreads();
+
+    const int col = lane, r0 = wave * LC;
+    const int lx = tx0 + col;
+    const int nx = clip_len(lx, R, g.Wl);
+    double Su[LC], Suu[LC];
+
+    // PAIR = false: rA = sum u, rB = sum u*u.  PAIR = true: rA = sum v, rB = sum u*v.
+    auto row_pass = [&](auto pair) {
+        constexpr bool PAIR = decltype(pair)::value;
+        for (int it = threadIdx.x; it < SH * (kTileW / kRun); it += kThreads) {
+            const int ry = it >> 3, j0 = (it & 7) * kRun;
+            const float *pu = sU + ry * SWp + j0, *pv = sV + ry * SWp + j0;
+            double A = 0.0, B = 0.0;
+            for (int k = 0; k <= 2 * R; ++k) {
+                const double u = pu[k];
+                const double x = PAIR ? (double)pv[k] : u;
+                A += x;
+                B = __builtin_fma(u, x, B);
+            }
+            double *oa = rA + ry * kRowW + j0, *ob = rB + ry * kRowW + j0;
+            oa[0] = A;
+            ob[0] = B;
+#pragma unroll
+            for (int t = 1; t < kRun; ++t) {
+                const double ui = pu[t + 2 * R], uo = pu[t - 1];
+                const double xi = PAIR ? (double)pv[t + 2 * R] : ui, xo = PAIR ? (double)pv[t - 1] : uo;
+                A += xi - xo;
+                B += __builtin_fma(ui, xi, -uo * xo);
+                oa[t] = A;
+                ob[t] = B;
+            }
+        }
+    };
+
+    // phase 1: sums of u and u*u
+    row_pass(std::false_type{});
+    __syncthreads();
+    {
+        double A = 0.0, B = 0.0;
+        for (int k = 0; k <= 2 * R; ++k) {
+            A += rA[(r0 + k) * kRowW + col];
+            B += rB[(r0 + k) * kRowW + col];
+        }
+#pragma unroll
+        for (int t = 0; t < LC; ++t) {
+            if (t) {
+                A += rA[(r0 + t + 2 * R) * kRowW + col] - rA[(r0 + t - 1) * kRowW + col];
+                B += rB[(r0 + t + 2 * R) * kRowW + col] - rB[(r0 + t - 1) * kRowW + col];
+            }
+            Su[t] = A;
+            Suu[t] = B;
+        }
+    }
+    __syncthreads();
+    // phase 2: sums of v and u*v, then a and b
+    row_pass(std::true_type{});
+    __syncthreads();
+    double A = 0.0, B = 0.0;
+    for (int k = 0; k <= 2 * R; ++k) {
+        A += rA[(r0 + k) * kRowW + col];
+        B += rB[(r0 + k) * kRowW + col];
+    }
+#pragma unroll
+    for (int t = 0; t < LC; ++t) {
+        if (t) {
+            A += rA[(r0 + t + 2 * R) * kRowW + col] - rA[(r0 + t - 1) * kRowW + col];
+            B += rB[(r0 + t + 2 * R) * kRowW + col] - rB[(r0 + t - 1) * kRowW + col];
+        }
+        const int ly = ty0 + r0 + t;
+        if (ly < g.Hl && lx < g.Wl) {
+            float a, b;
+            coeff_from_sums(clip_len(ly, R, g.Hl) * nx, Su[t], Suu[t], A, B, cI, cP, g.eps, a, b);
+            ac[(int64_t)ly * g.lrs + lx] = a;
+            bc[(int64_t)ly * g.lrs + lx] = b;
+        }
+    }
+}
+
+// One TH x 64 tile of the clip-normalised box mean of a low-res FP32 plane.
+template <int TH>
+__device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__restrict__ D,
+                                         const Geo &g, int ty0, int tx0, void *lds) {
+    constexpr int LC = TH / 4;
+    const int R = g.R, SH = TH + 2 * R, SW = kTileW + 2 * R, SWp = region_stride(R);
+    float *rA = (float *)lds;
+    float *sX = rA + SH * kRowW;
+    const int oy = ty0 - R, ox = tx0 - R;
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    fill_tile(sX, SH, SW, SWp, [&](int ry, int rx) -> float {
+        const int ly = oy + ry, lx = ox + rx;
+        const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
+        const float v = S[(int64_t)clampi(ly, 0, g.Hl - 1) * g.lrs + clampi(lx, 0, g.Wl - 1)];
+        return v * (in ? 1.f : 0.f);  // product, not select: see coeff_tile
+    });
+    __syncthreads();
+    for (int it = threadIdx.x; it < SH * (kTileW / kRun); it += kThreads) {
+        const int ry = it >> 3, j0 = (it & 7) * kRun;
+        const float *px = sX + ry * SWp + j0;
+        float A = 0.f;
+        for (int k = 0; k <= 2 * R; ++k) A += px[k];
+        float *oa = rA + ry * kRowW + j0;
+        oa[0] = A;
+#pragma unroll
+        for (int t = 1; t < kRun; ++t) {
+            A += px[t + 2 * R] - px[t - 1];
+            oa[t] = A;
+        }
+    }
+    __syncthreads();
+    const int col = lane, r0 = wave * LC;
+    const int lx = tx0 + col;
+    const int nx = clip_len(lx, R, g.Wl);
+    float A = 0.f;
+    for (int k = 0; k <= 2 * R; ++k) A += rA[(r0 + k) * kRowW + col];
+#pragma unroll
+    for (int t = 0; t < LC; ++t) {
+        if (t) A += rA[(r0 + t + 2 * R) * kRowW + col] - rA[(r0 + t - 1) * kRowW + col];
+        const int ly = ty0 + r0 + t;
+        if (ly < g.Hl && lx < g.Wl) D[(int64_t)ly * g.lrs + lx] = A * rcp((float)(clip_len(ly, R, g.Hl) * nx));
+    }
+}
+
+// ---------------------------------------------------------------- output
+//
+// A wave covers 256 full-res columns (4 per lane) and kOutRows = 8 rows
+// starting at a multiple of 8.  A lane first loads its 8 x 4 guide pixels
+// (all loads in flight together); then, channel by channel, it loads the
+// low-res rows and columns of mean_a, mean_b its pixels interpolate from,
+// interpolates them horizontally once, and for every row finishes the
+// bilinear weights and writes q = a*I + b with non-temporal stores.
+//
+// Upsampling geometry (half-pixel centres): full-res x maps to low-res
+// u = (x + 0.5)/s - 0.5 = (2x + 1 - s) / (2s), taps floor(u), floor(u) + 1
+// clamped to the map.  For s in {2, 4, 8} lanes start at x0 = 0 mod 4 and
+// waves at y = 0 mod 8, so which low-res rows/columns each pixel uses,
+// relative to the first one, is known at compile time.
+
+constexpr int kOutRows = 8;
+
+// floor((2x + 1 - s) / (2s)) and its fractional part, for compile-time use
+constexpr int cfloor_u(int x, int s) {
+    return (2 * x + 1 - s) >= 0 ? (2 * x + 1 - s) / (2 * s) : -((2 * s - 1 - (2 * x + 1 - s)) / (2 * s));
+}
+constexpr float cfrac_u(int x, int s) {
+    return (float)((2 * x + 1 - s) - 2 * s * cfloor_u(x, s)) / (float)(2 * s);
+}
+
+// q for CC channels (planes Q + c*Qps) of the wave's 8 x 256 block at
+// (yb, xw); mean_a_c = M + (c0+c)*lps, mean_b_c = M + (C+c0+c)*lps.
+// S: compile-time ratio, 0 = read g.s at run time.
+template <typename T, int CC, int S>
+__device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs, T *__restrict__ Q,
+                                            int64_t Qrs, int64_t Qps, const float *__restrict__ M,
+                                            const Geo &g, int c0, int yb, int xw, bool vec) {
+    constexpr int ROWS = kOutRows;
+    const int lane = threadIdx.x & 63;
+    const int x0 = xw + lane * kOutPx;
+    const int nrows = min(ROWS, g.H - yb);
+    if (x0 >= g.W || nrows <= 0) return;  // no barriers below
+    const bool full = vec && (x0 + 3 < g.W);
+
+    f32x4 iv[ROWS];
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+        iv[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if (i < nrows) {
+            const T *row = I + (int64_t)(yb + i) * Irs + x0;
+            if (full) {
+                iv[i] = ld4(row);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (x0 + j < g.W) iv[i][j] = ld(row + j);
+            }
+        }
+    }
+    auto store_q = [&](T *plane, int y, f32x4 v) {
+        T *row = plane + (int64_t)y * Qrs + x0;
+        if (full) {
+            st4(row, v);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (x0 + j < g.W) st1(row + j, v[j]);
+        }
+    };
+
+    if constexpr (S == 1) {
+        // Algorithm 1: the maps are full resolution; rows are padded to a
+        // multiple of 16 floats, so the 16-byte read at x0 stays in the row.
+#pragma unroll 1
+        for (int c = 0; c < CC; ++c) {
+            const float *Ma = M + (int64_t)(c0 + c) * g.lps;
+            const float *Mb = M + (int64_t)(g.C + c0 + c) * g.lps;
+            T *Qc = Q + (int64_t)c * Qps;
+#pragma unroll
+            for (int i = 0; i < ROWS; ++i) {
+                if (i < nrows) {
+                    const int y = yb + i;
+                    const f32x4 a = ld4(Ma + (int64_t)y * g.lrs + x0);
+                    const f32x4 b = ld4(Mb + (int64_t)y * g.lrs + x0);
+                    store_q(Qc, y, a * iv[i] + b);
+                }
+            }
+        }
+    } else if constexpr (S == 2 || S == 4 || S == 8) {
+        // low-res rows base_y .. base_y + NL - 1 and columns base_x .. base_x + NC - 1
+        constexpr int NL = cfloor_u(ROWS - 1, S) - cfloor_u(0, S) + 2;
+        constexpr int NC = cfloor_u(3, S) - cfloor_u(0, S) + 2;
+        const int base_y = floordiv(2 * yb + 1 - S, 2 * S);
+        const int base_x = floordiv(2 * x0 + 1 - S, 2 * S);
+        int ry[NL], cx[NC];
+#pragma unroll
+        for (int m = 0; m < NL; ++m) ry[m] = clampi(base_y + m, 0, g.Hl - 1);
+#pragma unroll
+        for (int m = 0; m < NC; ++m) cx[m] = clampi(base_x + m, 0, g.Wl - 1);
+        // horizontal weights: compile time when s divides 4; for s = 8 they
+        // depend on whether the lane starts at 0 or 4 mod 8
+        float wx[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            wx[j] = (S == 8) ? (float)((2 * ((x0 & 7) + j) + 1 - 8) & 15) * (1.0f / 16.0f)
+                             : cfrac_u(j, S);
+#pragma unroll 1
+        for (int c = 0; c < CC; ++c) {
+            const float *Ma = M + (int64_t)(c0 + c) * g.lps;
+            const float *Mb = M + (int64_t)(g.C + c0 + c) * g.lps;
+            T *Qc = Q + (int64_t)c * Qps;
+            float ha[NL][4], hb[NL][4];
+#pragma unroll
+            for (int m = 0; m < NL; ++m) {
+                const float *ra = Ma + (int64_t)ry[m] * g.lrs;
+                const float *rb = Mb + (int64_t)ry[m] * g.lrs;
+                float va[NC], vb[NC];
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    va[k] = ra[cx[k]];
+                    vb[k] = rb[cx[k]];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int k0 = cfloor_u(j, S) - cfloor_u(0, S);  // 0 for s = 8 as well
+                    ha[m][j] = va[k0] + wx[j] * (va[k0 + 1] - va[k0]);
+                    hb[m][j] = vb[k0] + wx[j] * (vb[k0 + 1] - vb[k0]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < ROWS; ++i) {
+                if (i < nrows) {
+                    const int m0 = cfloor_u(i, S) - cfloor_u(0, S);
+                    const float wy = cfrac_u(i, S);
+                    f32x4 out;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float a = ha[m0][j] + wy * (ha[m0 + 1][j] - ha[m0][j]);
+                        const float b = hb[m0][j] + wy * (hb[m0 + 1][j] - hb[m0][j]);
+                        out[j] = a * iv[i][j] + b;
+                    }
+                    store_q(Qc, yb + i, out);
+                }
+            }
+        }
+    } else {
+        // any other ratio: taps computed per pixel and per row at run time
+        const int s = g.s, s2 = 2 * s;
+        const float inv2s = 1.0f / (float)s2;
+        int xa[4], xb[4];
+        float wx[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int num = 2 * (x0 + j) + 1 - s;
+            const int l = floordiv(num, s2);
+            wx[j] = (float)(num - s2 * l) * inv2s;
+            xa[j] = clampi(l, 0, g.Wl - 1);
+            xb[j] = clampi(l + 1, 0, g.Wl - 1);
+        }
+#pragma unroll 1
+        for (int c = 0; c < CC; ++c) {
+            const float *Ma = M + (int64_t)(c0 + c) * g.lps;
+            const float *Mb = M + (int64_t)(g.C + c0 + c) * g.lps;
+            T *Qc = Q + (int64_t)c * Qps;
+#pragma unroll 1
+            for (int i = 0; i < nrows; ++i) {
+                const int y = yb + i;
+                const int num = 2 * y + 1 - s;
+                const int l = floordiv(num, s2);
+                const float wy = (float)(num - s2 * l) * inv2s;
+                const int k0 = clampi(l, 0, g.Hl - 1), k1 = clampi(l + 1, 0, g.Hl - 1);
+                const float *ra0 = Ma + (int64_t)k0 * g.lrs, *ra1 = Ma + (int64_t)k1 * g.lrs;
+                const float *rb0 = Mb + (int64_t)k0 * g.lrs, *rb1 = Mb + (int64_t)k1 * g.lrs;
+                f32x4 iy = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int r = 0; r < ROWS; ++r)
+                    if (r == i) iy = iv[r];
+                f32x4 out;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float a0 = ra0[xa[j]] + wx[j] * (ra0[xb[j]] - ra0[xa[j]]);
+                    const float a1 = ra1[xa[j]] + wx[j] * (ra1[xb[j]] - ra1[xa[j]]);
+                    const float b0 = rb0[xa[j]] + wx[j] * (rb0[xb[j]] - rb0[xa[j]]);
+                    const float b1 = rb1[xa[j]] + wx[j] * (rb1[xb[j]] - rb1[xa[j]]);
+                    out[j] = (a0 + wy * (a1 - a0)) * iy[j] + (b0 + wy * (b1 - b0));
+                }
+                store_q(Qc, y, out);
+            }
+        }
+    }
+}
+
+// Workgroups are handed to the 8 XCDs round robin (id mod 8).  Launches use
+// a grid that is a multiple of 8 and this map gives XCD k the k-th
+// contiguous range of logical tiles (row-major), so tiles that share halo
+// rows of the low-res maps share an L2.
+__device__ __forceinline__ int xcd_tile(int bid) {
+    const int per = (int)gridDim.x >> 3;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+}  // namespace dev
+}  // namespace gf

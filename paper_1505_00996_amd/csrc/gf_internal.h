@@ -30,13 +30,8 @@ struct View {
 
 // Tile shapes for one call (picked by the host heuristic or the tuner).
 struct TileCfg {
-    int coeff_slide;  // 1: sliding-window kernel (tile 64 x 4*coeff_th), 0: separable passes
-    int coeff_th;     // slide: rows per wave (4, 8, 16); separable: tile rows (8, 16, 32)
-    int coeff_tw;     // separable: tile columns (32 or 64)
-    int coeff_stage;  // separable: 1 = stage the samples in LDS, 0 = read through the caches
-    int box_slide;    // same choices for the box-mean kernel (tile width 64)
-    int box_th;
-    int box_stage;
+    int coeff_th;  // rows of a coefficient tile (8, 16, 24 or 32); tiles are 64 columns wide
+    int box_th;    // rows of a box-mean tile (8, 16, 24 or 32)
 };
 
 constexpr int kThreads = 256;   // threads per workgroup for every kernel
@@ -44,7 +39,7 @@ constexpr int kTileW = 64;      // low-res tile width of the window-sum kernels
 constexpr int kRun = 8;         // consecutive outputs per thread in a row pass
 constexpr int kOutPx = 4;       // full-res pixels per lane in the output kernel
 constexpr int kOutTileW = 64 * kOutPx;  // full-res columns per output tile
-constexpr int kMaxRadius = 64;  // largest low-res radius the LDS row buffers hold
+constexpr int kMaxRadius = 64;  // largest low-res radius the LDS tile buffers hold
 
 Geo make_geo(int H, int W, int C, int r, int s, double eps, int sub);
 size_t coeff_lds_bytes(const TileCfg &t, int R);

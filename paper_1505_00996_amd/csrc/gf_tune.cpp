@@ -12,73 +12,17 @@
 
 namespace gf {
 
-static TileCfg from_abi(const gf_tiles &t) {
-    TileCfg c;
-    c.coeff_slide = t.coeff_slide;
-    c.coeff_th = t.coeff_th;
-    c.coeff_tw = t.coeff_tw;
-    c.coeff_stage = t.coeff_stage;
-    c.box_slide = t.box_slide;
-    c.box_th = t.box_th;
-    c.box_stage = t.box_stage;
-    return c;
-}
+static TileCfg from_abi(const gf_tiles &t) { return TileCfg{t.coeff_th, t.box_th}; }
 
-static gf_tiles to_abi(const TileCfg &c) {
-    gf_tiles t;
-    t.coeff_slide = c.coeff_slide;
-    t.coeff_th = c.coeff_th;
-    t.coeff_tw = c.coeff_tw;
-    t.coeff_stage = c.coeff_stage;
-    t.box_slide = c.box_slide;
-    t.box_th = c.box_th;
-    t.box_stage = c.box_stage;
-    return t;
-}
+static gf_tiles to_abi(const TileCfg &c) { return gf_tiles{c.coeff_th, c.box_th}; }
 
-// Candidates of one kernel; the other kernel's fields are taken from `base`.
+// Candidates of one kernel; the other kernel's field is taken from `base`.
 static std::vector<TileCfg> candidates(const Geo &g, const TileCfg &base, int kernel) {
     std::vector<TileCfg> out;
-    auto push = [&](TileCfg c) {
+    for (int th : {8, 16, 24, 32}) {
+        TileCfg c = base;
+        (kernel == GF_K_COEFF ? c.coeff_th : c.box_th) = th;
         if (tiles_fit(g, c)) out.push_back(c);
-    };
-    if (kernel == GF_K_COEFF) {
-        if (g.R <= 16)
-            for (int th : {4, 8, 16}) {
-                TileCfg c = base;
-                c.coeff_slide = 1;
-                c.coeff_th = th;
-                c.coeff_tw = 64;
-                c.coeff_stage = 1;
-                push(c);
-            }
-        for (int th : {8, 16, 32})
-            for (int tw : {32, 64})
-                for (int st : {1, 0}) {
-                    TileCfg c = base;
-                    c.coeff_slide = 0;
-                    c.coeff_th = th;
-                    c.coeff_tw = tw;
-                    c.coeff_stage = st;
-                    push(c);  // shapes that are not built fail tiles_fit and are skipped
-                }
-    } else {
-        if (g.R <= 16)
-            for (int th : {4, 8, 16}) {
-                TileCfg c = base;
-                c.box_slide = 1;
-                c.box_th = th;
-                c.box_stage = 1;
-                push(c);
-            }
-        for (int th : {8, 16, 32})
-            for (int st : {1, 0}) {
-                TileCfg c = base;
-                c.box_slide = 0;
-                c.box_th = th;
-                c.box_stage = st;
-                push(c);
-            }
     }
     return out;
 }
@@ -188,11 +132,8 @@ gf_status gf_ctx_save_tuning(gf_ctx *ctx, const char *path) {
     size_t i = 0;
     for (const auto &kv : ctx->tuned) {
         const TileCfg &t = kv.second;
-        fprintf(f,
-                "{\"key\": %llu, \"coeff_slide\": %d, \"coeff_th\": %d, \"coeff_tw\": %d, "
-                "\"coeff_stage\": %d, \"box_slide\": %d, \"box_th\": %d, \"box_stage\": %d}%s\n",
-                (unsigned long long)kv.first, t.coeff_slide, t.coeff_th, t.coeff_tw, t.coeff_stage,
-                t.box_slide, t.box_th, t.box_stage, ++i < ctx->tuned.size() ? "," : "");
+        fprintf(f, "{\"key\": %llu, \"coeff_th\": %d, \"box_th\": %d}%s\n",
+                (unsigned long long)kv.first, t.coeff_th, t.box_th, ++i < ctx->tuned.size() ? "," : "");
     }
     fprintf(f, "]}\n");
     const bool ok = fclose(f) == 0;
@@ -210,11 +151,8 @@ gf_status gf_ctx_load_tuning(gf_ctx *ctx, const char *path) {
         if (!strstr(line, "\"key\"")) continue;
         unsigned long long key = 0;
         TileCfg t;
-        if (sscanf(line,
-                   " {\"key\": %llu, \"coeff_slide\": %d, \"coeff_th\": %d, \"coeff_tw\": %d, "
-                   "\"coeff_stage\": %d, \"box_slide\": %d, \"box_th\": %d, \"box_stage\": %d",
-                   &key, &t.coeff_slide, &t.coeff_th, &t.coeff_tw, &t.coeff_stage, &t.box_slide,
-                   &t.box_th, &t.box_stage) != 8) {
+        if (sscanf(line, " {\"key\": %llu, \"coeff_th\": %d, \"box_th\": %d", &key, &t.coeff_th,
+                   &t.box_th) != 3) {
             st = fail(GF_EINVAL, "malformed tuning entry in %s: %s", path, line);
             break;
         }
