@@ -52,30 +52,29 @@ Geo make_geo(int H, int W, int C, int r, int s, double eps, int sub) {
     return g;
 }
 
-static const size_t kLdsMax = 160 * 1024;
+static const size_t kLdsMax = kLdsLimit;
 
 static bool th_ok(int th) { return th == 8 || th == 16 || th == 24 || th == 32; }
 
-// Tile height: tall tiles amortise the 2r' halo rows, short ones keep the
-// LDS footprint (FP64 row sums) low enough for several workgroups per CU.
-static int pick_th(int R, size_t (*lds)(const TileCfg &, int), bool coeff) {
-    int best = 8;
-    for (int th : {32, 24, 16, 8}) {
-        TileCfg t{th, th};
-        const size_t b = lds(t, R);
-        (void)coeff;
-        if (b <= 64 * 1024 || th == 8) {
-            best = th;
-            break;
-        }
-    }
-    return best;
+// Tile height: tall tiles amortise the 2r' halo rows.  Prefer 24 rows when
+// the footprint leaves room for two workgroups per CU (measured best at
+// r' <= 8); at larger radii the halo dominates, so take the tallest tile
+// that fits at all.
+static int pick_th(int R, bool coeff) {
+    auto bytes = [&](int th) {
+        const TileCfg t{th, th};
+        return coeff ? coeff_lds_bytes(t, R) : box_lds_bytes(t, R);
+    };
+    if (bytes(24) <= 64 * 1024) return 24;
+    for (int th : {32, 24, 16})
+        if (bytes(th) <= kLdsMax) return th;
+    return 8;
 }
 
 TileCfg default_tiles(const Geo &g) {
     TileCfg t;
-    t.coeff_th = pick_th(g.R, coeff_lds_bytes, true);
-    t.box_th = pick_th(g.R, box_lds_bytes, false);
+    t.coeff_th = pick_th(g.R, true);
+    t.box_th = pick_th(g.R, false);
     return t;
 }
 

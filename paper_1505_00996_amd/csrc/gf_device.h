@@ -163,9 +163,9 @@ constexpr int kRowW = 65;      // padded row stride (elements) of the row-sum pl
 
 // LDS bytes of coeff_tile / box_tile for a tile of TH rows at radius R.
 __host__ __device__ constexpr int region_stride(int R) { return (kTileW + 2 * R) | 1; }
-__host__ __device__ constexpr size_t coeff_tile_lds(int TH, int R) {
+__host__ __device__ constexpr size_t coeff_tile_lds(int TH, int R, bool stage) {
     return (size_t)2 * (TH + 2 * R) * kRowW * sizeof(double) +
-           (size_t)2 * (TH + 2 * R) * region_stride(R) * sizeof(float);
+           (stage ? (size_t)2 * (TH + 2 * R) * region_stride(R) * sizeof(float) : 0);
 }
 __host__ __device__ constexpr size_t box_tile_lds(int TH, int R) {
     return (size_t)(TH + 2 * R) * kRowW * sizeof(float) +
@@ -202,6 +202,41 @@ __device__ __forceinline__ void fill_tile(float *dst, int SH, int SW, int SWp, F
     }
 }
 
+// Two regions of the same shape in one batch (twice the loads in flight).
+template <class F1, class F2>
+__device__ __forceinline__ void fill_tile2(float *d1, float *d2, int SH, int SW, int SWp, F1 f1, F2 f2) {
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    for (int c0 = 0; c0 < SW; c0 += 128) {
+        const int rx0 = c0 + lane, rx1 = c0 + 64 + lane;
+        const int cx0 = min(rx0, SW - 1), cx1 = min(rx1, SW - 1);
+        for (int r0 = wave; r0 < SH; r0 += 4 * kFillRows) {
+            float a0[kFillRows], a1[kFillRows], b0[kFillRows], b1[kFillRows];
+#pragma unroll
+            for (int b = 0; b < kFillRows; ++b) {
+                const int ry = min(r0 + 4 * b, SH - 1);
+                a0[b] = f1(ry, cx0);
+                a1[b] = f1(ry, cx1);
+                b0[b] = f2(ry, cx0);
+                b1[b] = f2(ry, cx1);
+            }
+#pragma unroll
+            for (int b = 0; b < kFillRows; ++b) {
+                const int ry = r0 + 4 * b;
+                if (ry < SH) {
+                    if (rx0 < SW) {
+                        d1[ry * SWp + rx0] = a0[b];
+                        d2[ry * SWp + rx0] = b0[b];
+                    }
+                    if (rx1 < SW) {
+                        d1[ry * SWp + rx1] = a1[b];
+                        d2[ry * SWp + rx1] = b1[b];
+                    }
+                }
+            }
+        }
+    }
+}
+
 // n^2 var and n^2 cov are the two cancelling differences; they are taken
 // in FP64, everything after them in FP32.  Eqs. 2-3.
 __device__ __forceinline__ void coeff_from_sums(int n, double Su, double Suu, double Sv, double Suv,
@@ -219,8 +254,11 @@ __device__ __forceinline__ void coeff_from_sums(int n, double Su, double Suu, do
 
 // One TH x 64 tile of a, b (low-res) at tile origin (ty0, tx0), for one
 // channel of p.  The statistics are formed in two phases (I alone, then I
-// with p) so that LDS holds two FP64 row-sum planes instead of four.
-template <typename T, int K, int TH>
+// with p) so that LDS holds two FP64 row-sum planes instead of four.  With
+// STAGE the samples of the region are staged in LDS first; without it (large
+// r', where the staged region would not fit) the row pass reads them through
+// the caches.
+template <typename T, int K, int TH, bool STAGE>
 __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
                                            const T *__restrict__ Pc, int64_t Prs,
                                            float *__restrict__ ac, float *__restrict__ bc,
@@ -240,18 +278,19 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
     // loaded value lets the compiler turn the load into a branch that waits
     // for it, one load at a time.  The sample read there is an in-image one
     // (clamped address), so the product is an exact 0 for finite images.
-    auto fill = [&](float *dst, const T *img, int64_t rs, float c) {
-        fill_tile(dst, SH, SW, SWp, [&](int ry, int rx) -> float {
-            const int ly = oy + ry, lx = ox + rx;
-            const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
-            const float v = sample_rc<K>(img, rs, taps<K>(clampi(ly, 0, g.Hl - 1), g.s, g.H),
-                                         taps<K>(clampi(lx, 0, g.Wl - 1), g.s, g.W));
-            return (v - c) * (in ? 1.f : 0.f);
-        });
+    auto gsample = [&](const T *img, int64_t rs, float c, int ry, int rx) -> float {
+        const int ly = oy + ry, lx = ox + rx;
+        const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
+        const float v = sample_rc<K>(img, rs, taps<K>(clampi(ly, 0, g.Hl - 1), g.s, g.H),
+                                     taps<K>(clampi(lx, 0, g.Wl - 1), g.s, g.W));
+        return (v - c) * (in ? 1.f : 0.f);
     };
-    fill(sU, I, Irs, cI);
-    fill(sV, Pc, Prs, cP);
-    __syncthreads();
+    auto gU = [&](int ry, int rx) { return gsample(I, Irs, cI, ry, rx); };
+    auto gV = [&](int ry, int rx) { return gsample(Pc, Prs, cP, ry, rx); };
+    if (STAGE) {
+        fill_tile2(sU, sV, SH, SW, SWp, gU, gV);
+        __syncthreads();
+    }
 
     const int col = lane, r0 = wave * LC;
     const int lx = tx0 + col;
@@ -264,10 +303,12 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
         for (int it = threadIdx.x; it < SH * (kTileW / kRun); it += kThreads) {
             const int ry = it >> 3, j0 = (it & 7) * kRun;
             const float *pu = sU + ry * SWp + j0, *pv = sV + ry * SWp + j0;
+            auto U = [&](int k) -> double { return STAGE ? pu[k] : gU(ry, j0 + k); };
+            auto V = [&](int k) -> double { return STAGE ? pv[k] : gV(ry, j0 + k); };
             double A = 0.0, B = 0.0;
             for (int k = 0; k <= 2 * R; ++k) {
-                const double u = pu[k];
-                const double x = PAIR ? (double)pv[k] : u;
+                const double u = U(k);
+                const double x = PAIR ? V(k) : u;
                 A += x;
                 B = __builtin_fma(u, x, B);
             }
@@ -276,8 +317,8 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
             ob[0] = B;
 #pragma unroll
             for (int t = 1; t < kRun; ++t) {
-                const double ui = pu[t + 2 * R], uo = pu[t - 1];
-                const double xi = PAIR ? (double)pv[t + 2 * R] : ui, xo = PAIR ? (double)pv[t - 1] : uo;
+                const double ui = U(t + 2 * R), uo = U(t - 1);
+                const double xi = PAIR ? V(t + 2 * R) : ui, xo = PAIR ? V(t - 1) : uo;
                 A += xi - xo;
                 B += __builtin_fma(ui, xi, -uo * xo);
                 oa[t] = A;

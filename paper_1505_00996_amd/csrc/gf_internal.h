@@ -42,6 +42,8 @@ constexpr int kOutTileW = 64 * kOutPx;  // full-res columns per output tile
 constexpr int kMaxRadius = 64;  // largest low-res radius the LDS tile buffers hold
 
 Geo make_geo(int H, int W, int C, int r, int s, double eps, int sub);
+constexpr size_t kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
+bool coeff_staged(const TileCfg &t, int R);
 size_t coeff_lds_bytes(const TileCfg &t, int R);
 size_t box_lds_bytes(const TileCfg &t, int R);
 TileCfg default_tiles(const Geo &g);

@@ -16,7 +16,7 @@ namespace {
 
 using namespace dev;
 
-template <typename T, int K, int TH>
+template <typename T, int K, int TH, bool STAGE>
 __global__ __launch_bounds__(kThreads) void k_coeff(const T *__restrict__ I, int64_t Irs,
                                                     const T *__restrict__ P, int64_t Prs, int64_t Pps,
                                                     float *__restrict__ coef, Geo g, int ntx, int ntiles) {
@@ -24,7 +24,7 @@ __global__ __launch_bounds__(kThreads) void k_coeff(const T *__restrict__ I, int
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;  // uniform per workgroup: no barrier is skipped by part of it
     const int c = blockIdx.y;
-    coeff_tile<T, K, TH>(I, Irs, P + (int64_t)c * Pps, Prs, coef + (int64_t)c * g.lps,
+    coeff_tile<T, K, TH, STAGE>(I, Irs, P + (int64_t)c * Pps, Prs, coef + (int64_t)c * g.lps,
                          coef + (int64_t)(g.C + c) * g.lps, g, (tile / ntx) * TH, (tile % ntx) * kTileW,
                          lds_d);
 }
@@ -70,17 +70,21 @@ hipError_t coeff_tk(const View &I, const View &P, float *coef, const Geo &g, con
     const int ntiles = ntx * nty;
     const size_t lds = coeff_lds_bytes(t, g.R);
     const dim3 grid(grid8(ntiles), g.C), block(kThreads);
-#define GF_COEFF(TH)                                                                                   \
-    {                                                                                                  \
-        allow_lds(k_coeff<T, K, TH>, lds);                                                             \
-        hipLaunchKernelGGL((k_coeff<T, K, TH>), grid, block, lds, st, Ip, I.rs, Pp, P.rs, P.ps, coef, g, \
-                           ntx, ntiles);                                                               \
+#define GF_COEFF(TH, STG)                                                                              \
+    {                                                                                                   \
+        allow_lds(k_coeff<T, K, TH, STG>, lds);                                                         \
+        hipLaunchKernelGGL((k_coeff<T, K, TH, STG>), grid, block, lds, st, Ip, I.rs, Pp, P.rs, P.ps, coef, \
+                           g, ntx, ntiles);                                                             \
     }
-    switch (t.coeff_th) {
-        case 8: GF_COEFF(8) break;
-        case 16: GF_COEFF(16) break;
-        case 24: GF_COEFF(24) break;
-        default: GF_COEFF(32) break;
+    if (!coeff_staged(t, g.R)) {
+        GF_COEFF(8, false)  // large r': only the row sums live in LDS
+    } else {
+        switch (t.coeff_th) {
+            case 8: GF_COEFF(8, true) break;
+            case 16: GF_COEFF(16, true) break;
+            case 24: GF_COEFF(24, true) break;
+            default: GF_COEFF(32, true) break;
+        }
     }
 #undef GF_COEFF
     return hipGetLastError();
@@ -132,7 +136,11 @@ hipError_t output_t(const View &I, const View &Q, const float *mean, const Geo &
 
 }  // namespace
 
-size_t coeff_lds_bytes(const TileCfg &t, int R) { return dev::coeff_tile_lds(t.coeff_th, R); }
+// Staged coefficient tiles when they fit; otherwise unstaged 8-row tiles.
+bool coeff_staged(const TileCfg &t, int R) { return dev::coeff_tile_lds(t.coeff_th, R, true) <= kLdsLimit; }
+size_t coeff_lds_bytes(const TileCfg &t, int R) {
+    return coeff_staged(t, R) ? dev::coeff_tile_lds(t.coeff_th, R, true) : dev::coeff_tile_lds(8, R, false);
+}
 size_t box_lds_bytes(const TileCfg &t, int R) { return dev::box_tile_lds(t.box_th, R); }
 
 hipError_t launch_coeff(gf_dtype dt, const View &I, const View &P, float *coef, const Geo &g,
