@@ -65,10 +65,10 @@ static int pick_th(int R, bool coeff) {
         const TileCfg t{th, th};
         return coeff ? coeff_lds_bytes(t, R) : box_lds_bytes(t, R);
     };
-    if (bytes(24) <= 64 * 1024) return 24;
+    if (bytes(24) <= 64 * 1024 && (!coeff || coeff_staged(TileCfg{24, 24}, R))) return 24;
     for (int th : {32, 24, 16})
-        if (bytes(th) <= kLdsMax) return th;
-    return 8;
+        if (bytes(th) <= kLdsMax && (!coeff || coeff_staged(TileCfg{th, th}, R))) return th;
+    return 8;  // coefficient tiles fall back to unstaged 8-row tiles
 }
 
 TileCfg default_tiles(const Geo &g) {

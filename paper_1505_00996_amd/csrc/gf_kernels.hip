@@ -66,7 +66,9 @@ template <typename T, int K>
 hipError_t coeff_tk(const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
                     hipStream_t st) {
     const T *Ip = (const T *)I.data, *Pp = (const T *)P.data;
-    const int ntx = (g.Wl + kTileW - 1) / kTileW, nty = (g.Hl + t.coeff_th - 1) / t.coeff_th;
+    const bool staged = coeff_staged(t, g.R);
+    const int th = staged ? t.coeff_th : 8;  // the unstaged kernel works on 8-row tiles
+    const int ntx = (g.Wl + kTileW - 1) / kTileW, nty = (g.Hl + th - 1) / th;
     const int ntiles = ntx * nty;
     const size_t lds = coeff_lds_bytes(t, g.R);
     const dim3 grid(grid8(ntiles), g.C), block(kThreads);
@@ -76,7 +78,7 @@ hipError_t coeff_tk(const View &I, const View &P, float *coef, const Geo &g, con
         hipLaunchKernelGGL((k_coeff<T, K, TH, STG>), grid, block, lds, st, Ip, I.rs, Pp, P.rs, P.ps, coef, \
                            g, ntx, ntiles);                                                             \
     }
-    if (!coeff_staged(t, g.R)) {
+    if (!staged) {
         GF_COEFF(8, false)  // large r': only the row sums live in LDS
     } else {
         switch (t.coeff_th) {
