@@ -33,7 +33,8 @@ H, W, C = 3000, 4000, 3
 R_FULL, S, EPS = 16, 4, 1e-3
 HBM_PEAK_GBS = 8000.0
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_output_12mp_fp32_counters.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_1505_00996_amd", "csrc", "gf_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1505_00996_amd", "csrc", f)
+               for f in ("gf_device.h", "gf_kernels.hip")]
 
 
 def parse():
@@ -61,7 +62,11 @@ def output_kernel_bytes(h, w, c, s, elem=4):
 
 
 def source_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the sources the output kernel is built from."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic():
