@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgf.so")
 SOURCES = ["gf_kernels.hip", "gf_batched.hip", "gf_api.cpp", "gf_ctx.cpp", "gf_tune.cpp",
-           "gf_engine.cpp"]
+           "gf_batch_host.cpp", "gf_engine.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for the device code on purpose.
@@ -27,7 +27,7 @@ HIPFLAGS = [
 def build(out: str = LIB, verbose: bool = False) -> str:
     """Compile every source and link libgf.so (always recompiles)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
+    objs, procs = [], []
     bdir = os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
@@ -43,8 +43,11 @@ def build(out: str = LIB, verbose: bool = False) -> str:
                    "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        procs.append((src, subprocess.Popen(cmd)))  # translation units compile in parallel
         objs.append(obj)
+    failed = [src for src, pr in procs if pr.wait() != 0]
+    if failed:
+        raise RuntimeError(f"compilation failed: {failed}")
     tmp = out + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     if verbose:

@@ -31,6 +31,11 @@ struct gf_ctx {
     std::mutex prof_mu;
     std::vector<Mark> marks;
     std::vector<hipEvent_t> event_pool;
+    // pinned staging of batched-launch descriptor tables
+    std::mutex pin_mu;
+    void *pin = nullptr;
+    size_t pin_bytes = 0;
+    hipEvent_t pin_ev = nullptr;  // completes when the last upload from `pin` is done
 };
 
 namespace gf {

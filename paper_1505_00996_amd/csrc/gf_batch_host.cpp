@@ -1,0 +1,191 @@
+// Host side of the persistent batched launch: planning (task queue layout,
+// workspace layout, tile height) and gf_fast_batched / gf_batched_workspace_bytes.
+#include <hip/hip_runtime_api.h>
+
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "gf_api_internal.h"
+#include "gf_batch_host.h"
+
+namespace gf {
+
+static size_t round256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Tile height shared by every image of the launch: 16 rows when the
+// staged tiles fit at the batch's largest radius, else 8, else none (the
+// batch then runs as per-image launches).  The choice depends only on the
+// largest radius, so an image gives the same bits alone and in any batch
+// whose radii stay under the same bound, and the same bits as gf_fast with
+// tiles {16, 16} (or {8, 8}).
+static int batch_th(int maxR, size_t *lds) {
+    for (int th : {16, 8}) {
+        const TileCfg t{th, th};
+        if (!coeff_staged(t, maxR)) continue;
+        const size_t b = std::max(coeff_lds_bytes(t, maxR), box_lds_bytes(t, maxR));
+        if (b <= kLdsLimit) {
+            *lds = b;
+            return th;
+        }
+    }
+    return 0;
+}
+
+gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image *q,
+                     const gf_params *pr, char *ws_base, BatchPlan *plan) {
+    if (n < 1) return fail(GF_EINVAL, "batch of %d images", n);
+    if (!I || !p || !q || !pr) return fail(GF_EINVAL, "batch: null array");
+    gf_status st;
+    int maxR = 0;
+    for (int i = 0; i < n; ++i) {
+        if ((st = validate(&I[i], &p[i], &q[i], &pr[i])) != GF_OK)
+            return fail(st, "image %d: %s", i, last_error());
+        if (I[i].dtype != I[0].dtype) return fail(GF_EINVAL, "image %d: dtype differs from image 0", i);
+        maxR = std::max(maxR, lowres_radius(pr[i].r, pr[i].s));
+    }
+    plan->n = n;
+    plan->dtype = I[0].dtype;
+    plan->th = batch_th(maxR, &plan->lds);
+    plan->desc.assign(n, BDesc{});
+    // workspace: control words, descriptor table, then each image's 4C planes
+    size_t off = round256(sizeof(unsigned) * batch_ctl_words(n));
+    plan->desc_off = off;
+    off += round256(sizeof(BDesc) * n);
+    unsigned base[3] = {0, 0, 0};
+    std::vector<unsigned> cnt[3];
+    for (int i = 0; i < n; ++i) {
+        BDesc &d = plan->desc[i];
+        const Geo g = make_geo(I[i].h, I[i].w, p[i].c, pr[i].r, pr[i].s, pr[i].eps, (int)pr[i].sub);
+        d.I = I[i].data;
+        d.P = p[i].data;
+        d.Q = q[i].data;
+        d.Irs = I[i].row_stride;
+        d.Prs = p[i].row_stride;
+        d.Pps = p[i].plane_stride;
+        d.Qrs = q[i].row_stride;
+        d.Qps = q[i].plane_stride;
+        d.g = g;
+        d.kind = g.s == 1 ? 0 : ((g.sub == GF_SUB_NEAREST || (g.s & 1)) ? 1 : 2);
+        d.vec = vector_ok(&I[i], &q[i]) ? 1 : 0;
+        const int th = plan->th ? plan->th : 8;
+        d.ntx_l = (g.Wl + kTileW - 1) / kTileW;
+        d.nty_l = (g.Hl + th - 1) / th;
+        d.ntx_o = (g.W + kOutTileW - 1) / kOutTileW;
+        d.nty_o = (g.H + 4 * 8 - 1) / (4 * 8);
+        d.ntiles[0] = (unsigned)(d.ntx_l * d.nty_l * g.C);
+        d.ntiles[1] = (unsigned)(d.ntx_l * d.nty_l * 2 * g.C);
+        d.ntiles[2] = (unsigned)(d.ntx_o * d.nty_o * ((g.C + 2) / 3));
+        const size_t planes = sizeof(float) * (size_t)g.lps * 2 * g.C;
+        d.coef = (float *)(ws_base + off);
+        off += round256(planes);
+        d.mean = (float *)(ws_base + off);
+        off += round256(planes);
+        for (int ph = 0; ph < 3; ++ph) {
+            d.base[ph] = base[ph];
+            base[ph] += d.ntiles[ph];
+        }
+    }
+    // phases follow each other in the queue
+    for (int i = 0; i < n; ++i) {
+        plan->desc[i].base[1] += base[0];
+        plan->desc[i].base[2] += base[0] + base[1];
+    }
+    plan->p1 = base[0];
+    plan->p2 = base[0] + base[1];
+    plan->total = base[0] + base[1] + base[2];
+    plan->ws_bytes = off;
+    return GF_OK;
+}
+
+gf_status launch_plan(gf_ctx *ctx, BatchPlan &plan, void *ws, hipStream_t st) {
+    char *base = (char *)ws;
+    const size_t dbytes = sizeof(BDesc) * plan.n;
+    // The descriptor table goes through pinned host memory owned by the
+    // context (reused once the previous upload from it has completed), or,
+    // without a context, through a temporary buffer and a stream sync.
+    hipError_t e;
+    if (ctx) {
+        std::lock_guard<std::mutex> lk(ctx->pin_mu);
+        if (ctx->pin_ev) (void)hipEventSynchronize(ctx->pin_ev);
+        if (ctx->pin_bytes < dbytes) {
+            if (ctx->pin) (void)hipHostFree(ctx->pin);
+            ctx->pin = nullptr;
+            ctx->pin_bytes = 0;
+            if ((e = hipHostMalloc(&ctx->pin, dbytes, hipHostMallocDefault)) != hipSuccess)
+                return fail(GF_ENOMEM, "hipHostMalloc(%zu): %s", dbytes, hipGetErrorString(e));
+            ctx->pin_bytes = dbytes;
+        }
+        if (!ctx->pin_ev && (e = hipEventCreateWithFlags(&ctx->pin_ev, hipEventDisableTiming)) != hipSuccess)
+            return fail(GF_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+        memcpy(ctx->pin, plan.desc.data(), dbytes);
+        e = hipMemcpyAsync(base + plan.desc_off, ctx->pin, dbytes, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipEventRecord(ctx->pin_ev, st);
+    } else {
+        e = hipMemcpyAsync(base + plan.desc_off, plan.desc.data(), dbytes, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (e != hipSuccess) return fail(GF_EDEVICE, "descriptor upload: %s", hipGetErrorString(e));
+
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        ncu = 256;
+    const int occ = batched_occupancy(plan.dtype, plan.th, plan.lds);
+    const int grid = (int)std::min<unsigned>(plan.total, (unsigned)(occ * ncu));
+    ProfScope ps(ctx, GF_K_BATCHED, st);
+    e = launch_batched(plan.dtype, plan.th, (const BDesc *)(base + plan.desc_off), plan.n,
+                       (unsigned *)base, plan.total, plan.p1, plan.p2, plan.lds, grid, st);
+    if (e != hipSuccess) return fail(GF_EDEVICE, "batched launch: %s", hipGetErrorString(e));
+    return GF_OK;
+}
+
+}  // namespace gf
+
+using namespace gf;
+
+extern "C" {
+
+size_t gf_batched_workspace_bytes(int32_t n, const gf_image *I, const gf_image *p,
+                                  const gf_params *pr) {
+    if (n < 1 || !I || !p || !pr) return 0;
+    size_t planes = 0;
+    for (int i = 0; i < n; ++i) {
+        if (I[i].h < 1 || I[i].w < 1 || p[i].c < 1 || pr[i].s < 1 || pr[i].r < 0) return 0;
+        const Geo g = make_geo(I[i].h, I[i].w, p[i].c, pr[i].r, pr[i].s, pr[i].eps, (int)pr[i].sub);
+        planes += 2 * round256(sizeof(float) * (size_t)g.lps * 2 * g.C);
+    }
+    return round256(sizeof(unsigned) * batch_ctl_words(n)) + round256(sizeof(BDesc) * n) + planes;
+}
+
+gf_status gf_fast_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_image *p, gf_image *q,
+                          const gf_params *pr, void *ws, size_t ws_bytes, void *stream) {
+    gf_status st;
+    BatchPlan plan;
+    if ((st = plan_batch(n, I, p, q, pr, (char *)ws, &plan)) != GF_OK) return st;
+    if (ctx && (st = ctx_use_device(ctx)) != GF_OK) return st;
+    if (!ws) {
+        if (!ctx) return fail(GF_EINVAL, "workspace is NULL and there is no context");
+        if ((st = ctx_workspace(ctx, plan.ws_bytes, &ws)) != GF_OK) return st;
+        if ((st = plan_batch(n, I, p, q, pr, (char *)ws, &plan)) != GF_OK) return st;
+    } else if (ws_bytes < plan.ws_bytes) {
+        return fail(GF_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, plan.ws_bytes);
+    }
+    if ((uintptr_t)ws % 256) return fail(GF_EINVAL, "workspace not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    if (plan.th == 0) {
+        // radius too large for the persistent kernel's staged tiles: one
+        // gf_fast per image on the same stream (same results)
+        for (int i = 0; i < n; ++i) {
+            const BDesc &d = plan.desc[i];
+            if ((st = run_fast(ctx, &I[i], &p[i], &q[i], &pr[i], d.coef,
+                               sizeof(float) * (size_t)d.g.lps * 4 * d.g.C, s, nullptr)) != GF_OK)
+                return st;
+        }
+        return GF_OK;
+    }
+    return launch_plan(ctx, plan, ws, s);
+}
+
+}  // extern "C"

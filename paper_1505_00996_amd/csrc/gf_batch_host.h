@@ -1,0 +1,31 @@
+// Host planning of the persistent batched launch (shared by gf_fast_batched
+// and the request engine).  Not public ABI.
+#pragma once
+
+#include <vector>
+
+#include "gf.h"
+#include "gf_batched.h"
+
+namespace gf {
+
+struct BatchPlan {
+    int n = 0;
+    gf_dtype dtype = GF_F32;
+    int th = 0;               // tile height of the window-sum tiles (0: use per-image launches)
+    size_t lds = 0;           // dynamic LDS of the persistent kernel
+    size_t desc_off = 0;      // byte offset of the descriptor table in the workspace
+    size_t ws_bytes = 0;      // workspace bytes the plan needs
+    unsigned p1 = 0, p2 = 0, total = 0;  // queue: [0,p1) coefficients, [p1,p2) box means, [p2,total) output
+    std::vector<BDesc> desc;
+};
+
+// Validate the n problems and lay out the queue and the workspace (whose
+// device base address is ws_base; may be null when only sizes are wanted).
+gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image *q,
+                     const gf_params *pr, char *ws_base, BatchPlan *plan);
+
+// Upload the descriptor table and enqueue the persistent kernel on st.
+gf_status launch_plan(gf_ctx *ctx, BatchPlan &plan, void *ws, hipStream_t st);
+
+}  // namespace gf

@@ -1,0 +1,36 @@
+// Shared host/device layout of the persistent batched launch.  Not public ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include "gf_internal.h"
+
+namespace gf {
+
+// One image of a batch, as the persistent kernel reads it (device memory).
+struct BDesc {
+    const void *I, *P;
+    void *Q;
+    float *coef, *mean;  // 2C planes each, in the workspace
+    int64_t Irs, Prs, Pps, Qrs, Qps;
+    Geo g;
+    int kind;                // subsampling kind (0 identity, 1 nearest, 2 two-tap mean)
+    int vec;                 // 16-byte (or 8-byte) output accesses allowed
+    int ntx_l, nty_l;        // low-res tiles: 64 columns x TH rows
+    int ntx_o, nty_o;        // output blocks: 256 columns x 32 rows
+    unsigned base[3];        // queue index of the image's first task in each phase
+    unsigned ntiles[3];      // tasks of each phase: C*tiles, 2C*tiles, groups*blocks
+};
+
+// The control words live at the start of the batch workspace: [0] queue
+// head, [1] error flag, then 2 per image: coefficient tiles done, box tiles
+// done.
+inline int batch_ctl_words(int n) { return 2 + 2 * n; }
+
+constexpr unsigned kBatchSpinLimit = 1u << 26;  // ~3 s of polling before a wait is declared stuck
+
+hipError_t launch_batched(gf_dtype dt, int th, const BDesc *D, int n, unsigned *ctl, unsigned total,
+                          unsigned p1, unsigned p2, size_t lds, int grid, hipStream_t st);
+int batched_occupancy(gf_dtype dt, int th, size_t lds);
+
+}  // namespace gf

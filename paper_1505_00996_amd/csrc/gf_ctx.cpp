@@ -146,10 +146,10 @@ void gf_ctx_destroy(gf_ctx *ctx) {
         for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
         ctx->event_pool.clear();
     }
-    if (ctx->ws) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(ctx->ws);
-    }
+    if (ctx->ws || ctx->pin) (void)hipDeviceSynchronize();
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->pin) (void)hipHostFree(ctx->pin);
+    if (ctx->pin_ev) (void)hipEventDestroy(ctx->pin_ev);
     delete ctx;
 }
 
