@@ -25,7 +25,7 @@ static int batch_th(int maxR, size_t *lds) {
         const TileCfg t{th, th};
         if (!coeff_staged(t, maxR)) continue;
         const size_t b = std::max(coeff_lds_bytes(t, maxR), box_lds_bytes(t, maxR));
-        if (b <= kLdsLimit) {
+        if (b + 256 <= kLdsLimit) {  // the kernel also holds a few static LDS words
             *lds = b;
             return th;
         }
