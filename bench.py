@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--sets", type=int, default=4, help="rotated input sets (cache control)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (parity and CPU baseline)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and served measurements")
     ap.add_argument("--profile-pass", action="store_true",
                     help="a short run for counter collection: a few fast steps and a copy kernel "
                          "of known size, no oracle")
@@ -81,6 +82,131 @@ def read_traffic():
     if not m_sha or not m_b or m_sha.group(1) != source_sha():
         return None
     return float(m_b.group(1))
+
+
+def measure_batched(gfp, torch, dev, n=256, reps=5, seed=6):
+    """One persistent launch over a batch of n images drawn like the
+    256-image workload: H~U{256..1536}, W~U{256..2048} (swapped with prob.
+    1/2), s in {2,4,8}, C in {1,3}, r = round(0.01 max(H,W)), eps = 1e-3,
+    fp16 storage.  Pixel values are seeded uniform noise made on the GPU (the
+    kernels have no data-dependent branches, so content does not change the
+    time)."""
+    import synth
+    specs = synth.batch_specs(n, seed=seed)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    Is, ps, qs, prs = [], [], [], []
+    for sp in specs:
+        Is.append(torch.rand((sp.h, sp.w), generator=g, device=dev, dtype=torch.float32).half())
+        ps.append(torch.rand((sp.c, sp.h, sp.w), generator=g, device=dev, dtype=torch.float32).half())
+        qs.append(torch.empty_like(ps[-1]))
+        prs.append(gfp.params(sp.r, sp.s, sp.eps))
+    ctx = gfp.Context(0)
+    ws = torch.empty(gfp.batched_workspace_bytes(Is, ps, prs), dtype=torch.uint8, device=dev)
+    gfp.gf_fast_batched(Is, ps, prs, qs=qs, ctx=ctx, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        gfp.gf_fast_batched(Is, ps, prs, qs=qs, ctx=ctx, workspace=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    # the same batch prepared once and captured into a HIP graph
+    b = gfp.Batch(Is, ps, prs, qs=qs, workspace=ws)
+    b.launch()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.launch()
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / reps
+    del graph
+    b.close()
+    mpix = sum(sp.h * sp.w for sp in specs) / 1e6
+    ctx.close()
+    return {"images": n, "mpix_per_batch": round(mpix, 1), "ms_per_batch": round(ms, 3),
+            "ms_per_batch_graph": round(ms_graph, 3),
+            "value": round(mpix / (ms * 1e-3), 1), "unit": "MPix/s", "dtype": "f16",
+            "workload": "256 images, H 256-1536 x W 256-2048 (either orientation), s in {2,4,8}, "
+                        "C in {1,3}, r = round(0.01 max(H,W)), eps=1e-3, one persistent launch"}
+
+
+def measure_served(gfp, torch, dev, pool=48, seed=7, seconds=1.5):
+    """Requests through gf_submit / gf_poll: log-uniform 0.25-24 MP, aspect
+    1:1/4:3/3:2/16:9 either way, gray or RGB input 50/50, s = 4,
+    r = round(0.01 max(H,W)), eps in {1e-2, 1e-3}, fp16, inputs resident on
+    the device.  First the saturation rate (all requests submitted at once),
+    then Poisson arrivals at 50% and 80% of it; latency = completion seen by
+    the library minus submission."""
+    import numpy as np
+    import synth
+    reqs = synth.request_mix(pool, qps=1.0, seed=seed)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    bufs = []
+    for rq in reqs:
+        sp = rq.spec
+        I = torch.rand((sp.h, sp.w), generator=g, device=dev, dtype=torch.float32).half()
+        p = torch.rand((sp.c, sp.h, sp.w), generator=g, device=dev, dtype=torch.float32).half()
+        bufs.append((sp, I, p, torch.empty_like(p)))
+    mean_mp = sum(sp.h * sp.w for sp, *_ in bufs) / len(bufs) / 1e6
+    ctx = gfp.Context(0, arena_bytes=4 << 30, max_inflight=4 * pool)
+
+    def run(arrivals):
+        """arrivals: list of (t_offset_s, pool index).  Returns latencies (s)."""
+        busy = {}
+        lat, pending = [], []
+        t_start = time.perf_counter()
+        k = 0
+        while k < len(arrivals) or pending:
+            now = time.perf_counter() - t_start
+            if k < len(arrivals) and arrivals[k][0] <= now and len(busy) < len(bufs):
+                idx = arrivals[k][1]
+                while idx in busy:  # a buffer still in flight: take the next free one
+                    idx = (idx + 1) % len(bufs)
+                sp, I, p, q = bufs[idx]
+                t = ctx.gf_submit(I, p, q, sp.r, sp.s, sp.eps)
+                busy[idx] = t
+                pending.append((t, idx))
+                k += 1
+                continue
+            still = []
+            for t, idx in pending:
+                st, stt = ctx.gf_poll(t, wait_ms=0)
+                if st == gfp.GF_OK:
+                    lat.append(stt.t_done - stt.t_submit)
+                    del busy[idx]
+                else:
+                    still.append((t, idx))
+            pending = still
+        return lat, time.perf_counter() - t_start
+
+    # warm-up and saturation: every pool entry submitted at once, twice
+    run([(0.0, i) for i in range(len(bufs))])
+    lat, el = run([(0.0, i % len(bufs)) for i in range(2 * len(bufs))])
+    sat_mpix = 2 * len(bufs) * mean_mp / el
+    out = {"mean_request_mpix": round(mean_mp, 2), "saturation_mpix_s": round(sat_mpix, 1),
+           "dtype": "f16", "workload": "log-uniform 0.25-24 MP requests, gray/RGB 50/50, s=4, "
+                                        "eps 1e-2/1e-3, device-resident inputs, Poisson arrivals"}
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for frac in (0.5, 0.8):
+        qps = frac * sat_mpix / mean_mp
+        n = max(20, int(qps * seconds))
+        t, arr = 0.0, []
+        for i in range(n):
+            t += rng.exponential(1.0 / qps)
+            arr.append((t, int(rng.integers(0, len(bufs)))))
+        lat, el = run(arr)
+        lat = np.array(lat) * 1e3
+        out[f"at_{int(frac * 100)}pct"] = {"qps": round(qps, 1), "requests": n,
+                                            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                                            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                                            "mpix_s": round(n * mean_mp / el, 1)}
+    ctx.close()
+    return out
 
 
 def main():
@@ -201,6 +327,13 @@ def main():
     }
     del big, big2, out3
 
+    batched = served = None
+    if not args.no_extra:
+        batched = measure_batched(gfp, torch, dev)
+        print(f"# batched: {batched['ms_per_batch']} ms per batch", file=sys.stderr, flush=True)
+        served = measure_served(gfp, torch, dev)
+        print(f"# served: {served}", file=sys.stderr, flush=True)
+
     mpix = H * W / 1e6
     out_ms, out_n = kt["output"]
     out_avg_ms = out_ms / max(out_n, 1)
@@ -232,6 +365,8 @@ def main():
         "speedup_vs_plain": round(ms_plain / ms_fast, 3),
         "ms_per_step_with_kernel_events": round(ms_fast_ev, 5),
         "kernels": kernels,
+        "batched": batched,
+        "served": served,
         "bandwidth_references": ceilings,
         "roofline": {"kernel": "k_output (bilinear upsample + q = mean_a*I + mean_b)",
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

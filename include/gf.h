@@ -163,11 +163,47 @@ size_t gf_batched_workspace_bytes(int32_t n, const gf_image *I, const gf_image *
  * ONE persistent launch over a queue of tiles.  Each q[k] equals what gf_fast
  * writes for image k.  Descriptor arrays are host memory, read during the
  * call.  workspace: at least gf_batched_workspace_bytes(...) of device memory,
- * or NULL for the context's.
+ * or NULL for the context's.  Its first two uint32 words are the queue head
+ * and an error word: once the launch has completed, a nonzero error word
+ * means some tile stopped waiting for the previous phase of its image after
+ * a bounded spin (about three seconds) and that image's q is incomplete.
  */
 gf_status gf_fast_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_image *p,
                           gf_image *q, const gf_params *params,
                           void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/*
+ * A prepared batch: the same work as gf_fast_batched, planned once so that
+ * the launch itself can be captured into a HIP graph and replayed.
+ *
+ * gf_batch_create validates the n problems, lays out the tile queue and the
+ * workspace, copies the descriptor table into the workspace and waits for
+ * that copy on `hip_stream` (so it must not run under stream capture).  It
+ * does not launch the filter.  `workspace` is device memory of at least
+ * gf_batched_workspace_bytes(...) bytes owned by the caller (NULL is
+ * refused: the batch keeps pointing at it).  The batch records the device
+ * addresses in I, p, q and the workspace; those buffers must outlive it.
+ * Returns GF_OK with *out set, or the errors of gf_fast_batched.
+ *
+ * gf_batch_launch enqueues the whole batch on `hip_stream`: a small kernel
+ * that clears the queue's control words, then the persistent kernel (or,
+ * for radii past the persistent kernel's tile limit, the per-image
+ * kernels).  It copies nothing from the host, allocates nothing and never
+ * synchronises, so it may be called under stream capture; every launch or
+ * replay reads the current contents of I and p and rewrites q.  Launches of
+ * one batch on different streams must not overlap (they share the
+ * workspace).  ctx profiling does not apply to it.
+ *
+ * gf_batch_destroy frees the host-side plan (not the workspace, not any
+ * graph holding its launch: destroy those first).
+ */
+typedef struct gf_batch gf_batch;
+
+gf_status gf_batch_create(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_image *p,
+                          gf_image *q, const gf_params *params, void *workspace,
+                          size_t workspace_bytes, void *hip_stream, gf_batch **out);
+gf_status gf_batch_launch(const gf_batch *batch, void *hip_stream);
+void gf_batch_destroy(gf_batch *batch);
 
 /*
  * Asynchronous request: filter (I, p) into q like gf_fast.  The request is

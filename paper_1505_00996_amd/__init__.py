@@ -32,7 +32,8 @@ SUBSAMPLE = {"nearest": GF_SUB_NEAREST, "bilinear": GF_SUB_BILINEAR}
 EXPORTS = ("gf_ctx_create", "gf_ctx_destroy", "gf_last_error", "gf_workspace_bytes", "gf_plain",
            "gf_fast", "gf_batched_workspace_bytes", "gf_fast_batched", "gf_submit", "gf_poll",
            "gf_ctx_profile", "gf_ctx_profile_read", "gf_ctx_set_tiles", "gf_tune",
-           "gf_ctx_save_tuning", "gf_ctx_load_tuning")
+           "gf_ctx_save_tuning", "gf_ctx_load_tuning", "gf_batch_create", "gf_batch_launch",
+           "gf_batch_destroy")
 KERNELS = ("coeff", "box", "output", "batched")
 
 
@@ -111,6 +112,9 @@ def lib() -> ctypes.CDLL:
                                        P(gf_tune_result), I32, P(I32)]),
             "gf_ctx_save_tuning": (ctypes.c_int, [VP, ctypes.c_char_p]),
             "gf_ctx_load_tuning": (ctypes.c_int, [VP, ctypes.c_char_p]),
+            "gf_batch_create": (ctypes.c_int, [VP, I32, img_p, img_p, img_p, par_p, VP, SZ, VP, P(VP)]),
+            "gf_batch_launch": (ctypes.c_int, [VP, VP]),
+            "gf_batch_destroy": (None, [VP]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -250,6 +254,50 @@ def gf_fast_batched(Is, ps, prs, qs=None, ctx=None, workspace=None, stream=None)
                                  ctypes.c_void_p(workspace.data_ptr()),
                                  workspace.numel() * workspace.element_size(), _stream(stream)), ctx)
     return qs
+
+
+def batched_wait_abandoned(workspace) -> bool:
+    """After a batched launch has completed: True if some tile gave up
+    waiting for the previous phase of its image (its outputs are then
+    incomplete).  Reads word 1 of the batch workspace."""
+    import torch
+    return bool(workspace[4:8].cpu().view(torch.int32).item())
+
+
+class Batch:
+    """gf_batch: a planned batch whose launch() only enqueues kernels, so it
+    can be captured into a HIP graph (torch.cuda.graph) and replayed.  Keeps
+    I, p, q and the workspace alive; each launch reads the current I, p."""
+
+    def __init__(self, Is, ps, prs, qs=None, ctx=None, workspace=None, stream=None):
+        if qs is None:
+            qs = [_out_like(p, None) for p in ps]
+        n = len(Is)
+        aI, ap, aq, apr = _arrays(Is, ps, qs, prs)
+        if workspace is None:
+            workspace = _workspace(lib().gf_batched_workspace_bytes(n, aI, ap, apr), ps[0].device)
+        h = ctypes.c_void_p()
+        _check(lib().gf_batch_create(ctx._h if ctx else None, n, aI, ap, aq, apr,
+                                     ctypes.c_void_p(workspace.data_ptr()),
+                                     workspace.numel() * workspace.element_size(), _stream(stream),
+                                     ctypes.byref(h)), ctx)
+        self._h = h
+        self.Is, self.ps, self.qs, self.workspace = list(Is), list(ps), qs, workspace
+
+    def launch(self, stream=None):
+        _check(lib().gf_batch_launch(self._h, _stream(stream)))
+        return self.qs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 @dataclass

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <new>
 #include <vector>
 
 #include "gf_api_internal.h"
@@ -24,7 +25,7 @@ static int batch_th(int maxR, size_t *lds) {
     for (int th : {16, 8}) {
         const TileCfg t{th, th};
         if (!coeff_staged(t, maxR)) continue;
-        const size_t b = std::max(coeff_lds_bytes(t, maxR), box_lds_bytes(t, maxR));
+        const size_t b = std::max({coeff_lds_bytes(t, maxR), box_lds_bytes(t, maxR), kOutPatchLds});
         if (b + 256 <= kLdsLimit) {  // the kernel also holds a few static LDS words
             *lds = b;
             return th;
@@ -99,6 +100,28 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
     return GF_OK;
 }
 
+// Workgroups of the persistent launch: as many as can be resident at once,
+// never more than there are tasks.
+static int plan_grid(const BatchPlan &plan) {
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        ncu = 256;
+    const int occ = batched_occupancy(plan.dtype, plan.th, plan.lds);
+    return (int)std::min<unsigned>(plan.total, (unsigned)(occ * ncu));
+}
+
+static gf_status enqueue_plan(gf_ctx *ctx, const BatchPlan &plan, void *ws, int grid, bool set_lds,
+                              hipStream_t st) {
+    char *base = (char *)ws;
+    ProfScope ps(ctx, GF_K_BATCHED, st);
+    const hipError_t e = launch_batched(plan.dtype, plan.th, (const BDesc *)(base + plan.desc_off), plan.n,
+                                        (unsigned *)base, plan.total, plan.p1, plan.p2, plan.lds, grid,
+                                        set_lds, st);
+    if (e != hipSuccess) return fail(GF_EDEVICE, "batched launch: %s", hipGetErrorString(e));
+    return GF_OK;
+}
+
 gf_status launch_plan(gf_ctx *ctx, BatchPlan &plan, void *ws, hipStream_t st) {
     char *base = (char *)ws;
     const size_t dbytes = sizeof(BDesc) * plan.n;
@@ -127,23 +150,23 @@ gf_status launch_plan(gf_ctx *ctx, BatchPlan &plan, void *ws, hipStream_t st) {
         if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
     if (e != hipSuccess) return fail(GF_EDEVICE, "descriptor upload: %s", hipGetErrorString(e));
-
-    int dev = 0, ncu = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
-        ncu = 256;
-    const int occ = batched_occupancy(plan.dtype, plan.th, plan.lds);
-    const int grid = (int)std::min<unsigned>(plan.total, (unsigned)(occ * ncu));
-    ProfScope ps(ctx, GF_K_BATCHED, st);
-    e = launch_batched(plan.dtype, plan.th, (const BDesc *)(base + plan.desc_off), plan.n,
-                       (unsigned *)base, plan.total, plan.p1, plan.p2, plan.lds, grid, st);
-    if (e != hipSuccess) return fail(GF_EDEVICE, "batched launch: %s", hipGetErrorString(e));
-    return GF_OK;
+    return enqueue_plan(ctx, plan, ws, plan_grid(plan), true, st);
 }
 
 }  // namespace gf
 
 using namespace gf;
+
+// A planned batch whose launch needs no host work beyond kernel enqueues.
+struct gf_batch {
+    int device = 0;
+    BatchPlan plan;
+    void *ws = nullptr;
+    int grid = 0;
+    // per-image launches (plan.th == 0): the problems as given
+    std::vector<gf_image> I, p, q;
+    std::vector<gf_params> pr;
+};
 
 extern "C" {
 
@@ -187,5 +210,70 @@ gf_status gf_fast_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_im
     }
     return launch_plan(ctx, plan, ws, s);
 }
+
+gf_status gf_batch_create(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_image *p, gf_image *q,
+                          const gf_params *pr, void *ws, size_t ws_bytes, void *stream, gf_batch **out) {
+    if (!out) return fail(GF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ws) return fail(GF_EINVAL, "a prepared batch needs a caller-owned workspace");
+    if ((uintptr_t)ws % 256) return fail(GF_EINVAL, "workspace not 256-byte aligned");
+    gf_status st;
+    if (ctx && (st = ctx_use_device(ctx)) != GF_OK) return st;
+    gf_batch *b = new (std::nothrow) gf_batch;
+    if (!b) return fail(GF_ENOMEM, "host allocation");
+    if ((st = plan_batch(n, I, p, q, pr, (char *)ws, &b->plan)) != GF_OK) {
+        delete b;
+        return st;
+    }
+    if (ws_bytes < b->plan.ws_bytes) {
+        const size_t need = b->plan.ws_bytes;
+        delete b;
+        return fail(GF_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
+    }
+    (void)hipGetDevice(&b->device);
+    b->ws = ws;
+    hipStream_t s = (hipStream_t)stream;
+    if (b->plan.th == 0) {
+        b->I.assign(I, I + n);
+        b->p.assign(p, p + n);
+        b->q.assign(q, q + n);
+        b->pr.assign(pr, pr + n);
+    } else {
+        hipError_t e = hipMemcpyAsync((char *)ws + b->plan.desc_off, b->plan.desc.data(),
+                                      sizeof(BDesc) * n, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = batched_allow_lds(b->plan.dtype, b->plan.th, b->plan.lds);
+        if (e != hipSuccess) {
+            delete b;
+            return fail(GF_EDEVICE, "descriptor upload: %s", hipGetErrorString(e));
+        }
+        b->grid = plan_grid(b->plan);
+    }
+    *out = b;
+    return GF_OK;
+}
+
+gf_status gf_batch_launch(const gf_batch *b, void *stream) {
+    if (!b) return fail(GF_EINVAL, "batch is NULL");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != b->device) {
+        const hipError_t e = hipSetDevice(b->device);
+        if (e != hipSuccess) return fail(GF_EDEVICE, "hipSetDevice(%d): %s", b->device, hipGetErrorString(e));
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (b->plan.th == 0) {
+        gf_status st;
+        for (int i = 0; i < b->plan.n; ++i) {
+            const BDesc &d = b->plan.desc[i];
+            if ((st = run_fast(nullptr, &b->I[i], &b->p[i], const_cast<gf_image *>(&b->q[i]), &b->pr[i],
+                               d.coef, sizeof(float) * (size_t)d.g.lps * 4 * d.g.C, s, nullptr)) != GF_OK)
+                return st;
+        }
+        return GF_OK;
+    }
+    return enqueue_plan(nullptr, b->plan, b->ws, b->grid, false, s);
+}
+
+void gf_batch_destroy(gf_batch *b) { delete b; }
 
 }  // extern "C"

@@ -27,10 +27,19 @@ struct BDesc {
 // done.
 inline int batch_ctl_words(int n) { return 2 + 2 * n; }
 
+// Low-res patch under one output block (32 x 256 pixels) at s >= 2: rows
+// span at most ceil(31/s) + 2 <= 18 and columns ceil(255/s) + 2 <= 130.
+constexpr int kPatchRows = 18, kPatchCols = 130, kPatchStride = kPatchCols + 1;
+constexpr size_t kOutPatchLds = 2 * kPatchRows * kPatchStride * sizeof(float);
+
 constexpr unsigned kBatchSpinLimit = 1u << 26;  // ~3 s of polling before a wait is declared stuck
 
+// Clears the control words, then launches the persistent kernel.  With
+// set_lds the kernel's dynamic-LDS limit is raised first (otherwise
+// batched_allow_lds must have been called for this dtype, th and size).
 hipError_t launch_batched(gf_dtype dt, int th, const BDesc *D, int n, unsigned *ctl, unsigned total,
-                          unsigned p1, unsigned p2, size_t lds, int grid, hipStream_t st);
+                          unsigned p1, unsigned p2, size_t lds, int grid, bool set_lds, hipStream_t st);
+hipError_t batched_allow_lds(gf_dtype dt, int th, size_t lds);
 int batched_occupancy(gf_dtype dt, int th, size_t lds);
 
 }  // namespace gf

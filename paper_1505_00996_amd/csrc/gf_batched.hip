@@ -11,12 +11,16 @@
 // after a spin limit the workgroup flags an error, skips the task and goes
 // on, so every wave reaches the end of the kernel.
 //
-// Memory ordering between workgroups (possibly on different XCDs, whose L2s
-// are not coherent with each other): a producer's threads fence at agent
-// scope after their stores (release: stores reach memory, L2 written back),
-// then one thread bumps the image's phase counter; the consumer polls the
-// counter and fences at agent scope (acquire: stale L1/L2 lines dropped)
-// before reading.
+// Hand-over between workgroups (possibly on different XCDs, whose L2s are
+// not coherent with each other): every store of a coefficient or box-mean
+// plane and every load of one is a device-coherent access (ldp / stp with
+// COH), so no cache-wide writeback or invalidate is needed.  A producer's
+// threads wait until their stores have completed, the workgroup meets at a
+// barrier and one thread bumps the image's phase counter; a consumer polls
+// the counter and only then issues its loads, which are served from the
+// coherence point.  (An agent-scope fence per task would write back and
+// invalidate the whole L2 of the XCD each time, which costs several times
+// the work of a tile.)
 #include <hip/hip_runtime.h>
 
 #include "gf_batched.h"
@@ -48,9 +52,9 @@ __device__ __forceinline__ void run_coeff(const BDesc &d, unsigned local, void *
     const T *Pc = (const T *)d.P + (int64_t)c * d.Pps;
     float *ac = d.coef + (int64_t)c * d.g.lps, *bc = d.coef + (int64_t)(d.g.C + c) * d.g.lps;
     switch (d.kind) {
-        case kSubId: coeff_tile<T, kSubId, TH, true>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
-        case kSubNear: coeff_tile<T, kSubNear, TH, true>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
-        default: coeff_tile<T, kSubLin, TH, true>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
+        case kSubId: coeff_tile<T, kSubId, TH, true, true>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
+        case kSubNear: coeff_tile<T, kSubNear, TH, true, true>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
+        default: coeff_tile<T, kSubLin, TH, true, true>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
     }
 }
 
@@ -58,25 +62,135 @@ template <int TH>
 __device__ __forceinline__ void run_box(const BDesc &d, unsigned local, void *lds) {
     const unsigned per = (unsigned)(d.ntx_l * d.nty_l);
     const int m = (int)(local / per), r = (int)(local % per);
-    box_tile<TH>(d.coef + (int64_t)m * d.g.lps, d.mean + (int64_t)m * d.g.lps, d.g, (r / d.ntx_l) * TH,
-                 (r % d.ntx_l) * kTileW, lds);
+    box_tile<TH, true>(d.coef + (int64_t)m * d.g.lps, d.mean + (int64_t)m * d.g.lps, d.g, (r / d.ntx_l) * TH,
+                       (r % d.ntx_l) * kTileW, lds);
 }
 
-// Output blocks use the run-time-ratio form of output_rows: one code path
-// for every s keeps the persistent kernel's register budget (and so its
-// occupancy during the HBM-bound phase) at that of a single variant.
+// One output block (32 rows x 256 columns, up to three channels).  The
+// workgroup first copies the low-res patch of mean_a and mean_b under the
+// block into LDS with coherent loads (each value once), then every lane
+// interpolates its 8 x 4 pixels from LDS.  The arithmetic is that of
+// output_rows, term for term, so the bits equal those of the per-image
+// kernel.  At s = 1 the maps are full resolution and are read directly.
 template <typename T>
-__device__ __forceinline__ void run_output(const BDesc &d, unsigned local) {
+__device__ __forceinline__ void run_output(const BDesc &d, unsigned local, float *lds) {
+    const Geo &g = d.g;
     const unsigned per = (unsigned)(d.ntx_o * d.nty_o);
     const int grp = (int)(local / per), r = (int)(local % per);
-    const int c0 = 3 * grp, cc = min(3, d.g.C - c0);
-    const int yb = (r / d.ntx_o) * (4 * kOutRows) + wave_id() * kOutRows, xw = (r % d.ntx_o) * kOutTileW;
+    const int c0 = 3 * grp, cc = min(3, g.C - c0);
+    const int y0 = (r / d.ntx_o) * (4 * kOutRows), xw = (r % d.ntx_o) * kOutTileW;
+    const int lane = threadIdx.x & 63;
+    const int yb = y0 + wave_id() * kOutRows, x0 = xw + lane * kOutPx;
+    const int nrows = max(0, min(kOutRows, g.H - yb));
+    const bool act = x0 < g.W && nrows > 0;
+    const bool full = d.vec != 0 && x0 + 3 < g.W;
     const T *I = (const T *)d.I;
     T *Q = (T *)d.Q + (int64_t)c0 * d.Qps;
-    const bool vec = d.vec != 0;
-    if (cc == 3) output_rows<T, 3, 0>(I, d.Irs, Q, d.Qrs, d.Qps, d.mean, d.g, c0, yb, xw, vec);
-    else if (cc == 2) output_rows<T, 2, 0>(I, d.Irs, Q, d.Qrs, d.Qps, d.mean, d.g, c0, yb, xw, vec);
-    else output_rows<T, 1, 0>(I, d.Irs, Q, d.Qrs, d.Qps, d.mean, d.g, c0, yb, xw, vec);
+
+    typedef typename Raw4<T>::type raw4;
+    raw4 iv[kOutRows];
+#pragma unroll
+    for (int i = 0; i < kOutRows; ++i) {
+        iv[i] = raw4{0, 0, 0, 0};
+        if (act && i < nrows) {
+            const T *row = I + (int64_t)(yb + i) * d.Irs + x0;
+            if (full) {
+                iv[i] = ldraw4(row);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (x0 + j < g.W) iv[i][j] = raw1(row + j);
+            }
+        }
+    }
+    auto store_q = [&](T *plane, int y, f32x4 v) {
+        T *row = plane + (int64_t)y * d.Qrs + x0;
+        if (full) {
+            st4(row, v);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (x0 + j < g.W) st1(row + j, v[j]);
+        }
+    };
+
+    const int s = g.s;
+    if (s == 1) {  // uniform over the workgroup: no barriers on this path
+        if (!act) return;
+        for (int c = 0; c < cc; ++c) {
+            const float *Ma = d.mean + (int64_t)(c0 + c) * g.lps;
+            const float *Mb = d.mean + (int64_t)(g.C + c0 + c) * g.lps;
+            T *Qc = Q + (int64_t)c * d.Qps;
+#pragma unroll
+            for (int i = 0; i < kOutRows; ++i) {
+                if (i < nrows) {
+                    const int64_t o = (int64_t)(yb + i) * g.lrs + x0;
+                    f32x4 out;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int jj = x0 + j < g.W ? j : 0;  // stays inside the row
+                        out[j] = ldp<true>(Ma + o + jj) * widen(iv[i], j) + ldp<true>(Mb + o + jj);
+                    }
+                    store_q(Qc, yb + i, out);
+                }
+            }
+        }
+        return;
+    }
+
+    const int s2 = 2 * s;
+    const float inv2s = 1.0f / (float)s2;
+    const int yl = min(y0 + 4 * kOutRows - 1, g.H - 1), xl = min(xw + kOutTileW - 1, g.W - 1);
+    const int py0 = clampi(floordiv(2 * y0 + 1 - s, s2), 0, g.Hl - 1);
+    const int py1 = clampi(floordiv(2 * yl + 1 - s, s2) + 1, 0, g.Hl - 1);
+    const int px0 = clampi(floordiv(2 * xw + 1 - s, s2), 0, g.Wl - 1);
+    const int px1 = clampi(floordiv(2 * xl + 1 - s, s2) + 1, 0, g.Wl - 1);
+    const int nr = py1 - py0 + 1, nc = px1 - px0 + 1;  // <= kPatchRows, kPatchCols for s >= 2
+    float *pa = lds, *pb = lds + kPatchRows * kPatchStride;
+    int xa[4], xb[4];
+    float wx[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int num = 2 * min(x0 + j, xl) + 1 - s;
+        const int l = floordiv(num, s2);
+        wx[j] = (float)(num - s2 * l) * inv2s;
+        xa[j] = clampi(l, 0, g.Wl - 1) - px0;
+        xb[j] = clampi(l + 1, 0, g.Wl - 1) - px0;
+    }
+    for (int c = 0; c < cc; ++c) {
+        const float *Ma = d.mean + (int64_t)(c0 + c) * g.lps + (int64_t)py0 * g.lrs + px0;
+        const float *Mb = d.mean + (int64_t)(g.C + c0 + c) * g.lps + (int64_t)py0 * g.lrs + px0;
+        __syncthreads();  // the previous channel's patch has been read
+        for (int k = threadIdx.x; k < nr * nc; k += kThreads) {
+            const int ry = k / nc, rx = k - ry * nc;
+            pa[ry * kPatchStride + rx] = ldp<true>(Ma + (int64_t)ry * g.lrs + rx);
+            pb[ry * kPatchStride + rx] = ldp<true>(Mb + (int64_t)ry * g.lrs + rx);
+        }
+        __syncthreads();
+        if (act) {
+            T *Qc = Q + (int64_t)c * d.Qps;
+#pragma unroll
+            for (int i = 0; i < kOutRows; ++i) {
+                if (i < nrows) {
+                    const int num = 2 * (yb + i) + 1 - s;
+                    const int l = floordiv(num, s2);
+                    const float wy = (float)(num - s2 * l) * inv2s;
+                    const int r0 = (clampi(l, 0, g.Hl - 1) - py0) * kPatchStride;
+                    const int r1 = (clampi(l + 1, 0, g.Hl - 1) - py0) * kPatchStride;
+                    f32x4 out;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float a0 = pa[r0 + xa[j]] + wx[j] * (pa[r0 + xb[j]] - pa[r0 + xa[j]]);
+                        const float a1 = pa[r1 + xa[j]] + wx[j] * (pa[r1 + xb[j]] - pa[r1 + xa[j]]);
+                        const float b0 = pb[r0 + xa[j]] + wx[j] * (pb[r0 + xb[j]] - pb[r0 + xa[j]]);
+                        const float b1 = pb[r1 + xa[j]] + wx[j] * (pb[r1 + xb[j]] - pb[r1 + xa[j]]);
+                        out[j] = (a0 + wy * (a1 - a0)) * widen(iv[i], j) + (b0 + wy * (b1 - b0));
+                    }
+                    store_q(Qc, yb + i, out);
+                }
+            }
+        }
+    }
 }
 
 template <typename T, int TH>
@@ -86,48 +200,57 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BDesc *__restrict__ 
     extern __shared__ double lds_d[];
     __shared__ unsigned s_task;
     __shared__ int s_skip;
+    unsigned next = 0;  // thread 0: the ticket taken one task ahead
+    if (threadIdx.x == 0) s_task = atomicAdd(&ctl[0], 1u);
+    __syncthreads();
     for (;;) {
-        if (threadIdx.x == 0) s_task = atomicAdd(&ctl[0], 1u);
-        __syncthreads();
         const unsigned t = s_task;
         if (t >= total) break;  // uniform: every thread read the same s_task
+        // Take the next ticket now, so that its round trip overlaps this task.
+        // The task it names waits for nothing this one does not, and only
+        // ever on tasks before it in the queue, so holding it cannot stall.
+        if (threadIdx.x == 0) next = atomicAdd(&ctl[0], 1u);
         const int ph = t < p1 ? 0 : (t < p2 ? 1 : 2);
         const int i = find_image(D, n, ph, t);
         const BDesc &d = D[i];
         const unsigned local = t - (ph == 0 ? d.base[0] : ph == 1 ? d.base[1] : d.base[2]);
+        int skip = 0;
         if (ph > 0) {
             // wait until every tile of the previous phase of this image is done
             const unsigned need = ph == 1 ? d.ntiles[0] : d.ntiles[1];
             if (threadIdx.x == 0) {
                 unsigned spins = 0;
-                int skip = 0;
+                int sk = 0;
                 while (__hip_atomic_load(&ctl[2 + 2 * i + ph - 1], __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT) < need) {
                     __builtin_amdgcn_s_sleep(2);
                     if (++spins > spin_limit) {
                         atomicOr(&ctl[1], 1u);
-                        skip = 1;
+                        sk = 1;
                         break;
                     }
                 }
-                s_skip = skip;
+                s_skip = sk;
             }
             __syncthreads();
-            __threadfence();  // acquire: drop stale cached lines before reading the previous phase
-            if (s_skip) {
-                __syncthreads();
-                continue;
+            skip = s_skip;
+        }
+        if (!skip) {
+            if (ph == 0) run_coeff<T, TH>(d, local, lds_d);
+            else if (ph == 1) run_box<TH>(d, local, lds_d);
+            else run_output<T>(d, local, (float *)lds_d);
+            if (ph < 2) {
+                // this thread's coherent plane stores have completed ...
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __builtin_amdgcn_s_waitcnt(0);
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __syncthreads();  // ... and so have every other thread's
+                if (threadIdx.x == 0) atomicAdd(&ctl[2 + 2 * i + ph], 1u);
             }
         }
-        if (ph == 0) run_coeff<T, TH>(d, local, lds_d);
-        else if (ph == 1) run_box<TH>(d, local, lds_d);
-        else run_output<T>(d, local);
-        if (ph < 2) {
-            __threadfence();  // release: this thread's stores reach memory before the count
-            __syncthreads();
-            if (threadIdx.x == 0) atomicAdd(&ctl[2 + 2 * i + ph], 1u);
-        }
-        __syncthreads();  // s_task / s_skip are rewritten by the next iteration
+        __syncthreads();  // every thread has read s_task and s_skip
+        if (threadIdx.x == 0) s_task = next;
+        __syncthreads();
     }
 }
 
@@ -139,11 +262,16 @@ __global__ void k_zero(unsigned *p, int n) {
 }
 
 template <typename T, int TH>
+hipError_t allow_t(size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void *)k_batched<T, TH>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+template <typename T, int TH>
 hipError_t launch_t(const BDesc *D, int n, unsigned *ctl, unsigned total, unsigned p1, unsigned p2,
-                    size_t lds, int grid, hipStream_t st) {
-    if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)k_batched<T, TH>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                    size_t lds, int grid, bool set_lds, hipStream_t st) {
+    if (set_lds) (void)allow_t<T, TH>(lds);
     hipLaunchKernelGGL((k_batched<T, TH>), dim3(grid), dim3(kThreads), lds, st, D, n, ctl, total, p1, p2,
                        kBatchSpinLimit);
     return hipGetLastError();
@@ -160,21 +288,32 @@ int occupancy_t(size_t lds) {
 }  // namespace
 
 hipError_t launch_batched(gf_dtype dt, int th, const BDesc *D, int n, unsigned *ctl, unsigned total,
-                          unsigned p1, unsigned p2, size_t lds, int grid, hipStream_t st) {
+                          unsigned p1, unsigned p2, size_t lds, int grid, bool set_lds, hipStream_t st) {
     const int nctl = batch_ctl_words(n);
     hipLaunchKernelGGL(k_zero, dim3((nctl + 255) / 256), dim3(256), 0, st, ctl, nctl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
 #define GF_B(TT)                                                                           \
-    return th == 8 ? launch_t<TT, 8>(D, n, ctl, total, p1, p2, lds, grid, st)              \
-         : th == 16 ? launch_t<TT, 16>(D, n, ctl, total, p1, p2, lds, grid, st)            \
-                    : launch_t<TT, 24>(D, n, ctl, total, p1, p2, lds, grid, st)
+    return th == 8 ? launch_t<TT, 8>(D, n, ctl, total, p1, p2, lds, grid, set_lds, st)     \
+         : th == 16 ? launch_t<TT, 16>(D, n, ctl, total, p1, p2, lds, grid, set_lds, st)   \
+                    : launch_t<TT, 24>(D, n, ctl, total, p1, p2, lds, grid, set_lds, st)
     switch (dt) {
         case GF_F32: GF_B(float);
         case GF_F16: GF_B(_Float16);
         case GF_BF16: GF_B(dev::bf16);
     }
 #undef GF_B
+    return hipErrorInvalidValue;
+}
+
+hipError_t batched_allow_lds(gf_dtype dt, int th, size_t lds) {
+#define GF_A(TT) return th == 8 ? allow_t<TT, 8>(lds) : th == 16 ? allow_t<TT, 16>(lds) : allow_t<TT, 24>(lds)
+    switch (dt) {
+        case GF_F32: GF_A(float);
+        case GF_F16: GF_A(_Float16);
+        case GF_BF16: GF_A(dev::bf16);
+    }
+#undef GF_A
     return hipErrorInvalidValue;
 }
 

@@ -60,7 +60,16 @@ __device__ __forceinline__ unsigned short f32_to_bf16_bits(float f) {
 
 template <typename T> __device__ __forceinline__ T from_f32(float v);
 template <> __device__ __forceinline__ float from_f32<float>(float v) { return v; }
-template <> __device__ __forceinline__ _Float16 from_f32<_Float16>(float v) { return (_Float16)v; }
+// q is an FP32 result rounded once more, to nearest even, for 16-bit
+// storage.  The empty asm pins the FP32 value: without it the compiler may
+// fuse the last multiply-add with the narrowing (v_fma_mixlo_f16, one
+// rounding straight to fp16), and whether it does differs between kernels,
+// so the same pixel could get different bits in different launches.
+__device__ __forceinline__ float pin_f32(float v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+template <> __device__ __forceinline__ _Float16 from_f32<_Float16>(float v) { return (_Float16)pin_f32(v); }
 template <> __device__ __forceinline__ bf16 from_f32<bf16>(float v) { return bf16{f32_to_bf16_bits(v)}; }
 
 template <typename T> __device__ __forceinline__ float ld(const T *p) { return to_f32(*p); }
@@ -80,7 +89,8 @@ __device__ __forceinline__ f32x4 ld4(const bf16 *p) {
 // Streaming (non-temporal) stores of four outputs.
 __device__ __forceinline__ void st4(float *p, f32x4 v) { __builtin_nontemporal_store(v, (f32x4 *)p); }
 __device__ __forceinline__ void st4(_Float16 *p, f32x4 v) {
-    f16x4 h = {(_Float16)v.x, (_Float16)v.y, (_Float16)v.z, (_Float16)v.w};
+    f16x4 h = {from_f32<_Float16>(v.x), from_f32<_Float16>(v.y), from_f32<_Float16>(v.z),
+               from_f32<_Float16>(v.w)};
     __builtin_nontemporal_store(h, (f16x4 *)p);
 }
 __device__ __forceinline__ void st4(bf16 *p, f32x4 v) {
@@ -89,6 +99,41 @@ __device__ __forceinline__ void st4(bf16 *p, f32x4 v) {
     __builtin_nontemporal_store(b, (u16x4 *)p);
 }
 template <typename T> __device__ __forceinline__ void st1(T *p, float v) { *p = from_f32<T>(v); }
+
+// Four samples held in their storage width (half the registers for 16-bit
+// types) and widened when used; widening is exact.
+template <typename T> struct Raw4;
+template <> struct Raw4<float> { typedef f32x4 type; };
+template <> struct Raw4<_Float16> { typedef f16x4 type; };
+template <> struct Raw4<bf16> { typedef u16x4 type; };
+__device__ __forceinline__ f32x4 ldraw4(const float *p) { return *(const f32x4 *)p; }
+__device__ __forceinline__ f16x4 ldraw4(const _Float16 *p) { return *(const f16x4 *)p; }
+__device__ __forceinline__ u16x4 ldraw4(const bf16 *p) { return *(const u16x4 *)p; }
+__device__ __forceinline__ float raw1(const float *p) { return *p; }
+__device__ __forceinline__ _Float16 raw1(const _Float16 *p) { return *p; }
+__device__ __forceinline__ unsigned short raw1(const bf16 *p) { return p->bits; }
+__device__ __forceinline__ float widen(f32x4 v, int j) { return v[j]; }
+__device__ __forceinline__ float widen(f16x4 v, int j) { return (float)v[j]; }
+__device__ __forceinline__ float widen(u16x4 v, int j) { return __uint_as_float((unsigned)v[j] << 16); }
+
+// Accesses to the low-resolution planes that workgroups of one launch hand
+// to each other (the batched kernel).  With COH they are relaxed atomics at
+// agent scope, which the compiler emits as device-coherent loads and stores
+// (sc1): a store is written through the XCD's L2 and is complete when its
+// vmcnt retires, and a load is served from the coherence point, not from a
+// line another XCD's write has made stale.  Handing planes over this way
+// needs no cache-wide writeback or invalidate (an agent-scope fence does
+// both), only a wait for the producer's stores before it signals.
+typedef __attribute__((address_space(1))) float gfloat;  // global memory, not generic
+template <bool COH> __device__ __forceinline__ float ldp(const float *p) {
+    if constexpr (COH)
+        return __hip_atomic_load((gfloat *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+template <bool COH> __device__ __forceinline__ void stp(float *p, float v) {
+    if constexpr (COH) __hip_atomic_store((gfloat *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
 
 // ---------------------------------------------------------------- helpers
 
@@ -258,7 +303,7 @@ __device__ __forceinline__ void coeff_from_sums(int n, double Su, double Suu, do
 // STAGE the samples of the region are staged in LDS first; without it (large
 // r', where the staged region would not fit) the row pass reads them through
 // the caches.
-template <typename T, int K, int TH, bool STAGE>
+template <typename T, int K, int TH, bool STAGE, bool COH = false>
 __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
                                            const T *__restrict__ Pc, int64_t Prs,
                                            float *__restrict__ ac, float *__restrict__ bc,
@@ -365,14 +410,14 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
         if (ly < g.Hl && lx < g.Wl) {
             float a, b;
             coeff_from_sums(clip_len(ly, R, g.Hl) * nx, Su[t], Suu[t], A, B, cI, cP, g.eps, a, b);
-            ac[(int64_t)ly * g.lrs + lx] = a;
-            bc[(int64_t)ly * g.lrs + lx] = b;
+            stp<COH>(ac + (int64_t)ly * g.lrs + lx, a);
+            stp<COH>(bc + (int64_t)ly * g.lrs + lx, b);
         }
     }
 }
 
 // One TH x 64 tile of the clip-normalised box mean of a low-res FP32 plane.
-template <int TH>
+template <int TH, bool COH = false>
 __device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__restrict__ D,
                                          const Geo &g, int ty0, int tx0, void *lds) {
     constexpr int LC = TH / 4;
@@ -384,7 +429,7 @@ __device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__r
     fill_tile(sX, SH, SW, SWp, [&](int ry, int rx) -> float {
         const int ly = oy + ry, lx = ox + rx;
         const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
-        const float v = S[(int64_t)clampi(ly, 0, g.Hl - 1) * g.lrs + clampi(lx, 0, g.Wl - 1)];
+        const float v = ldp<COH>(S + (int64_t)clampi(ly, 0, g.Hl - 1) * g.lrs + clampi(lx, 0, g.Wl - 1));
         return v * (in ? 1.f : 0.f);  // product, not select: see coeff_tile
     });
     __syncthreads();
@@ -411,7 +456,8 @@ __device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__r
     for (int t = 0; t < LC; ++t) {
         if (t) A += rA[(r0 + t + 2 * R) * kRowW + col] - rA[(r0 + t - 1) * kRowW + col];
         const int ly = ty0 + r0 + t;
-        if (ly < g.Hl && lx < g.Wl) D[(int64_t)ly * g.lrs + lx] = A * rcp((float)(clip_len(ly, R, g.Hl) * nx));
+        if (ly < g.Hl && lx < g.Wl)
+            stp<COH>(D + (int64_t)ly * g.lrs + lx, A * rcp((float)(clip_len(ly, R, g.Hl) * nx)));
     }
 }
 

@@ -155,3 +155,25 @@ def test_workspace_bytes():
     assert L.gf_workspace_bytes(0, 4000, 3, ctypes.byref(pr)) == 0
     pr1 = gfp.params(16, 1, 1e-3)
     assert L.gf_workspace_bytes(10, 10, 1, ctypes.byref(pr1)) == 4 * 1 * 192 * 4
+
+
+def test_prepared_batch_rejected_on_host():
+    I, p, q, pr = good()
+    n = 1
+    aI, ap, aq, apr = ((gfp.gf_image * 1)(I), (gfp.gf_image * 1)(p), (gfp.gf_image * 1)(q),
+                       (gfp.gf_params * 1)(pr))
+    h = ctypes.c_void_p()
+
+    def create(ws=0x40000000, ws_bytes=1 << 40, out=True, prs=apr):
+        return L.gf_batch_create(None, n, aI, ap, aq, prs, ctypes.c_void_p(ws), ws_bytes, None,
+                                 ctypes.byref(h) if out else None)
+
+    assert create(out=False) == gfp.GF_EINVAL
+    assert create(ws=0) == gfp.GF_EINVAL and "workspace" in gfp.last_error()
+    assert create(ws=0x40000010) == gfp.GF_EINVAL
+    assert create(ws_bytes=4096) == gfp.GF_ENOMEM and h.value is None
+    bad = (gfp.gf_params * 1)(gfp.params(8, 4, 1e-2))
+    bad[0].eps = 0.0
+    assert create(prs=bad) == gfp.GF_EINVAL and h.value is None
+    assert L.gf_batch_launch(None, None) == gfp.GF_EINVAL
+    L.gf_batch_destroy(None)
