@@ -160,8 +160,9 @@ size_t gf_batched_workspace_bytes(int32_t n, const gf_image *I, const gf_image *
 /*
  * Algorithm 2 for n independent images (arrays of n descriptors and n
  * parameter sets; sizes, c, r, s and eps may differ, the dtype may not) in
- * ONE persistent launch over a queue of tiles.  Each q[k] equals what gf_fast
- * writes for image k.  Descriptor arrays are host memory, read during the
+ * one batched launch with the context's batch configuration (see
+ * gf_batch_cfg; without a context the default).  Each q[k] equals what
+ * gf_fast writes for image k with tiles {tile_h, tile_h}.  Descriptor arrays are host memory, read during the
  * call.  workspace: at least gf_batched_workspace_bytes(...) of device memory,
  * or NULL for the context's.  Its first two uint32 words are the queue head
  * and an error word: once the launch has completed, a nonzero error word
@@ -171,6 +172,48 @@ size_t gf_batched_workspace_bytes(int32_t n, const gf_image *I, const gf_image *
 gf_status gf_fast_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_image *p,
                           gf_image *q, const gf_params *params,
                           void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/*
+ * Schedules of a batched launch.  Both give every image the bits gf_fast
+ * gives it with tiles {tile_h, tile_h}.
+ *   GF_BATCH_PHASES: one grid per phase (coefficient tiles, box-mean tiles,
+ *     output blocks) over the tiles of all images: three kernel launches per
+ *     batch, each at its own occupancy.
+ *   GF_BATCH_QUEUE: one persistent kernel; workgroups take tiles from a
+ *     queue ordered phase by phase and wait on per-image phase counters, so
+ *     the phases of different images overlap.
+ * tile_h: rows of the low-res window-sum tiles (8, 16 or 24); 0 picks the
+ * tallest of 24, 16, 8 whose tiles fit in LDS at the batch's largest r'.
+ */
+typedef enum { GF_BATCH_PHASES = 0, GF_BATCH_QUEUE = 1 } gf_batch_schedule;
+
+typedef struct {
+    int32_t schedule; /* gf_batch_schedule */
+    int32_t tile_h;
+} gf_batch_cfg;
+
+/* Schedule and tile height of the context's batched launches (gf_fast_batched,
+ * gf_batch_create, gf_submit); NULL restores the default {GF_BATCH_PHASES, 0}.
+ * GF_EINVAL for an unknown schedule or tile height. */
+gf_status gf_ctx_set_batch_cfg(gf_ctx *ctx, const gf_batch_cfg *cfg);
+
+typedef struct {
+    gf_batch_cfg cfg;
+    double ms; /* mean time of one launch of the whole batch */
+} gf_batch_tune_result;
+
+/*
+ * Autotuner for batches: times gf_fast_batched on this batch for every
+ * schedule and tile height that fits (`reps` launches each, after one
+ * warm-up, HIP events on `hip_stream`), sets the fastest as the context's
+ * batch configuration and writes it to *best.  Up to max_results timings go
+ * to results (count in *n_results).  Arguments as gf_fast_batched; q holds
+ * the batch's output when it returns.  Synchronises `hip_stream`.
+ */
+gf_status gf_tune_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_image *p, gf_image *q,
+                          const gf_params *params, void *workspace, size_t workspace_bytes,
+                          void *hip_stream, int32_t reps, gf_batch_cfg *best,
+                          gf_batch_tune_result *results, int32_t max_results, int32_t *n_results);
 
 /*
  * A prepared batch: the same work as gf_fast_batched, planned once so that

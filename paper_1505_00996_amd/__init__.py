@@ -33,7 +33,7 @@ EXPORTS = ("gf_ctx_create", "gf_ctx_destroy", "gf_last_error", "gf_workspace_byt
            "gf_fast", "gf_batched_workspace_bytes", "gf_fast_batched", "gf_submit", "gf_poll",
            "gf_ctx_profile", "gf_ctx_profile_read", "gf_ctx_set_tiles", "gf_tune",
            "gf_ctx_save_tuning", "gf_ctx_load_tuning", "gf_batch_create", "gf_batch_launch",
-           "gf_batch_destroy")
+           "gf_batch_destroy", "gf_ctx_set_batch_cfg", "gf_tune_batched")
 KERNELS = ("coeff", "box", "output", "batched")
 
 
@@ -66,6 +66,21 @@ class gf_tiles(ctypes.Structure):
 
 class gf_tune_result(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("tiles", gf_tiles), ("ms", ctypes.c_double)]
+
+
+GF_BATCH_PHASES, GF_BATCH_QUEUE = 0, 1
+SCHEDULES = {"phases": GF_BATCH_PHASES, "queue": GF_BATCH_QUEUE}
+
+
+class gf_batch_cfg(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("tile_h", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"schedule": {v: k for k, v in SCHEDULES.items()}[self.schedule], "tile_h": self.tile_h}
+
+
+class gf_batch_tune_result(ctypes.Structure):
+    _fields_ = [("cfg", gf_batch_cfg), ("ms", ctypes.c_double)]
 
 
 class GfError(RuntimeError):
@@ -115,6 +130,9 @@ def lib() -> ctypes.CDLL:
             "gf_batch_create": (ctypes.c_int, [VP, I32, img_p, img_p, img_p, par_p, VP, SZ, VP, P(VP)]),
             "gf_batch_launch": (ctypes.c_int, [VP, VP]),
             "gf_batch_destroy": (None, [VP]),
+            "gf_ctx_set_batch_cfg": (ctypes.c_int, [VP, P(gf_batch_cfg)]),
+            "gf_tune_batched": (ctypes.c_int, [VP, I32, img_p, img_p, img_p, par_p, VP, SZ, VP, I32,
+                                               P(gf_batch_cfg), P(gf_batch_tune_result), I32, P(I32)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -378,6 +396,32 @@ class Context:
 
     def load_tuning(self, path: str):
         _check(lib().gf_ctx_load_tuning(self._h, path.encode()), self)
+
+    def set_batch_cfg(self, schedule: str | None = "phases", tile_h: int = 0):
+        """Schedule ("phases" or "queue") and tile height of this context's
+        batched launches; None restores the default."""
+        if schedule is None:
+            _check(lib().gf_ctx_set_batch_cfg(self._h, None), self)
+        else:
+            c = gf_batch_cfg(SCHEDULES[schedule], int(tile_h))
+            _check(lib().gf_ctx_set_batch_cfg(self._h, ctypes.byref(c)), self)
+
+    def tune_batched(self, Is, ps, prs, qs=None, workspace=None, reps: int = 3, stream=None):
+        """Time every batch schedule and tile height on this batch, keep the
+        fastest for the context.  Returns (best dict, [(dict, ms), ...])."""
+        if qs is None:
+            qs = [_out_like(p, None) for p in ps]
+        n = len(Is)
+        aI, ap, aq, apr = _arrays(Is, ps, qs, prs)
+        if workspace is None:
+            workspace = _workspace(lib().gf_batched_workspace_bytes(n, aI, ap, apr), ps[0].device)
+        best = gf_batch_cfg()
+        res = (gf_batch_tune_result * 16)()
+        cnt = ctypes.c_int32()
+        _check(lib().gf_tune_batched(self._h, n, aI, ap, aq, apr, ctypes.c_void_p(workspace.data_ptr()),
+                                     workspace.numel() * workspace.element_size(), _stream(stream),
+                                     int(reps), ctypes.byref(best), res, 16, ctypes.byref(cnt)), self)
+        return best.as_dict(), [(res[i].cfg.as_dict(), res[i].ms) for i in range(cnt.value)]
 
     def gf_submit(self, I, p, q, r: int, s: int, eps: float, sub: str = "nearest") -> int:
         """Queue a request; returns its ticket.  I, p, q are kept alive here

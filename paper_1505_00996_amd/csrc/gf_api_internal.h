@@ -22,6 +22,7 @@ struct gf_ctx {
     std::mutex tune_mu;      // guards `tuned`
     std::unordered_map<uint64_t, gf::TileCfg> tuned;  // tile shapes picked by gf_tune
     gf::Engine *engine = nullptr;  // request interface (gf_submit / gf_poll)
+    gf_batch_cfg batch_cfg{GF_BATCH_PHASES, 0};  // batched launches (gf_ctx_set_batch_cfg / gf_tune_batched)
     // kernel timing (gf_ctx_profile)
     bool profiling = false;
     struct Mark {

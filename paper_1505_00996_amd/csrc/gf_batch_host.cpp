@@ -15,28 +15,55 @@ namespace gf {
 
 static size_t round256(size_t v) { return (v + 255) / 256 * 256; }
 
-// Tile height shared by every image of the launch: 16 rows when the
-// staged tiles fit at the batch's largest radius, else 8, else none (the
-// batch then runs as per-image launches).  The choice depends only on the
-// largest radius, so an image gives the same bits alone and in any batch
-// whose radii stay under the same bound, and the same bits as gf_fast with
-// tiles {16, 16} (or {8, 8}).
-static int batch_th(int maxR, size_t *lds) {
-    for (int th : {16, 8}) {
+// Tile height shared by every image of the launch: the requested one, else
+// 24, falling back to smaller heights until the staged tiles of the batch's
+// largest r' fit in LDS (the queue kernel also holds the output patch and a
+// few static words); 0 when none fits (the batch then runs as per-image
+// launches).  The choice depends only on the configuration and the largest
+// radius, so an image gives the same bits alone and in any batch, and the
+// same bits as gf_fast with tiles {th, th}.
+static int batch_th(int sched, int want, int maxR, BatchPlan *plan) {
+    for (int th : {24, 16, 8}) {
+        if (want && th > want) continue;
         const TileCfg t{th, th};
         if (!coeff_staged(t, maxR)) continue;
-        const size_t b = std::max({coeff_lds_bytes(t, maxR), box_lds_bytes(t, maxR), kOutPatchLds});
-        if (b + 256 <= kLdsLimit) {  // the kernel also holds a few static LDS words
-            *lds = b;
-            return th;
+        const size_t c = coeff_lds_bytes(t, maxR), b = box_lds_bytes(t, maxR);
+        if (sched == GF_BATCH_QUEUE) {
+            const size_t all = std::max({c, b, kOutPatchLds});
+            if (all + 256 > kLdsLimit) continue;
+            plan->lds = all;
+        } else if (c > kLdsLimit || b > kLdsLimit) {
+            continue;
         }
+        plan->lds_coeff = c;
+        plan->lds_box = b;
+        return th;
     }
     return 0;
 }
 
+int batch_tile_h(const gf_batch_cfg &cfg, int maxR) {
+    BatchPlan scratch;
+    return batch_th(cfg.schedule, cfg.tile_h, maxR, &scratch);
+}
+
+static bool cfg_ok(const gf_batch_cfg &c) {
+    return (c.schedule == GF_BATCH_PHASES || c.schedule == GF_BATCH_QUEUE) &&
+           (c.tile_h == 0 || c.tile_h == 8 || c.tile_h == 16 || c.tile_h == 24);
+}
+
+gf_batch_cfg ctx_batch_cfg(gf_ctx *ctx) {
+    if (!ctx) return gf_batch_cfg{GF_BATCH_PHASES, 0};
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    return ctx->batch_cfg;
+}
+
+bool batch_cfg_ok(const gf_batch_cfg &c) { return cfg_ok(c); }
+
 gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image *q,
-                     const gf_params *pr, char *ws_base, BatchPlan *plan) {
+                     const gf_params *pr, char *ws_base, const gf_batch_cfg &cfg, BatchPlan *plan) {
     if (n < 1) return fail(GF_EINVAL, "batch of %d images", n);
+    if (!cfg_ok(cfg)) return fail(GF_EINVAL, "batch configuration {%d, %d}", cfg.schedule, cfg.tile_h);
     if (!I || !p || !q || !pr) return fail(GF_EINVAL, "batch: null array");
     gf_status st;
     int maxR = 0;
@@ -48,7 +75,8 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
     }
     plan->n = n;
     plan->dtype = I[0].dtype;
-    plan->th = batch_th(maxR, &plan->lds);
+    plan->sched = cfg.schedule;
+    plan->th = batch_th(cfg.schedule, cfg.tile_h, maxR, plan);
     plan->desc.assign(n, BDesc{});
     // workspace: control words, descriptor table, then each image's 4C planes
     size_t off = round256(sizeof(unsigned) * batch_ctl_words(n));
@@ -114,10 +142,14 @@ static int plan_grid(const BatchPlan &plan) {
 static gf_status enqueue_plan(gf_ctx *ctx, const BatchPlan &plan, void *ws, int grid, bool set_lds,
                               hipStream_t st) {
     char *base = (char *)ws;
+    const BDesc *D = (const BDesc *)(base + plan.desc_off);
     ProfScope ps(ctx, GF_K_BATCHED, st);
-    const hipError_t e = launch_batched(plan.dtype, plan.th, (const BDesc *)(base + plan.desc_off), plan.n,
-                                        (unsigned *)base, plan.total, plan.p1, plan.p2, plan.lds, grid,
-                                        set_lds, st);
+    const hipError_t e =
+        plan.sched == GF_BATCH_QUEUE
+            ? launch_batched(plan.dtype, plan.th, D, plan.n, (unsigned *)base, plan.total, plan.p1, plan.p2,
+                             plan.lds, grid, set_lds, st)
+            : launch_phases(plan.dtype, plan.th, D, plan.n, (unsigned *)base, plan.p1, plan.p2, plan.total,
+                            plan.lds_coeff, plan.lds_box, set_lds, st);
     if (e != hipSuccess) return fail(GF_EDEVICE, "batched launch: %s", hipGetErrorString(e));
     return GF_OK;
 }
@@ -186,12 +218,13 @@ gf_status gf_fast_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_im
                           const gf_params *pr, void *ws, size_t ws_bytes, void *stream) {
     gf_status st;
     BatchPlan plan;
-    if ((st = plan_batch(n, I, p, q, pr, (char *)ws, &plan)) != GF_OK) return st;
+    const gf_batch_cfg cfg = ctx_batch_cfg(ctx);
+    if ((st = plan_batch(n, I, p, q, pr, (char *)ws, cfg, &plan)) != GF_OK) return st;
     if (ctx && (st = ctx_use_device(ctx)) != GF_OK) return st;
     if (!ws) {
         if (!ctx) return fail(GF_EINVAL, "workspace is NULL and there is no context");
         if ((st = ctx_workspace(ctx, plan.ws_bytes, &ws)) != GF_OK) return st;
-        if ((st = plan_batch(n, I, p, q, pr, (char *)ws, &plan)) != GF_OK) return st;
+        if ((st = plan_batch(n, I, p, q, pr, (char *)ws, cfg, &plan)) != GF_OK) return st;
     } else if (ws_bytes < plan.ws_bytes) {
         return fail(GF_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, plan.ws_bytes);
     }
@@ -221,7 +254,7 @@ gf_status gf_batch_create(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_im
     if (ctx && (st = ctx_use_device(ctx)) != GF_OK) return st;
     gf_batch *b = new (std::nothrow) gf_batch;
     if (!b) return fail(GF_ENOMEM, "host allocation");
-    if ((st = plan_batch(n, I, p, q, pr, (char *)ws, &b->plan)) != GF_OK) {
+    if ((st = plan_batch(n, I, p, q, pr, (char *)ws, ctx_batch_cfg(ctx), &b->plan)) != GF_OK) {
         delete b;
         return st;
     }
@@ -242,7 +275,10 @@ gf_status gf_batch_create(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_im
         hipError_t e = hipMemcpyAsync((char *)ws + b->plan.desc_off, b->plan.desc.data(),
                                       sizeof(BDesc) * n, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e == hipSuccess) e = batched_allow_lds(b->plan.dtype, b->plan.th, b->plan.lds);
+        if (e == hipSuccess)
+            e = b->plan.sched == GF_BATCH_QUEUE
+                    ? batched_allow_lds(b->plan.dtype, b->plan.th, b->plan.lds)
+                    : phases_allow_lds(b->plan.dtype, b->plan.th, b->plan.lds_coeff, b->plan.lds_box);
         if (e != hipSuccess) {
             delete b;
             return fail(GF_EDEVICE, "descriptor upload: %s", hipGetErrorString(e));
@@ -275,5 +311,14 @@ gf_status gf_batch_launch(const gf_batch *b, void *stream) {
 }
 
 void gf_batch_destroy(gf_batch *b) { delete b; }
+
+gf_status gf_ctx_set_batch_cfg(gf_ctx *ctx, const gf_batch_cfg *cfg) {
+    if (!ctx) return fail(GF_EINVAL, "ctx is NULL");
+    const gf_batch_cfg c = cfg ? *cfg : gf_batch_cfg{GF_BATCH_PHASES, 0};
+    if (!cfg_ok(c)) return fail(GF_EINVAL, "batch configuration {%d, %d}", c.schedule, c.tile_h);
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    ctx->batch_cfg = c;
+    return GF_OK;
+}
 
 }  // extern "C"

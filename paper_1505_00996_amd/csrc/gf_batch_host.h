@@ -12,8 +12,10 @@ namespace gf {
 struct BatchPlan {
     int n = 0;
     gf_dtype dtype = GF_F32;
+    int sched = GF_BATCH_PHASES;
     int th = 0;               // tile height of the window-sum tiles (0: use per-image launches)
-    size_t lds = 0;           // dynamic LDS of the persistent kernel
+    size_t lds = 0;           // dynamic LDS of the persistent kernel (queue schedule)
+    size_t lds_coeff = 0, lds_box = 0;  // dynamic LDS of the phase kernels
     size_t desc_off = 0;      // byte offset of the descriptor table in the workspace
     size_t ws_bytes = 0;      // workspace bytes the plan needs
     unsigned p1 = 0, p2 = 0, total = 0;  // queue: [0,p1) coefficients, [p1,p2) box means, [p2,total) output
@@ -23,7 +25,14 @@ struct BatchPlan {
 // Validate the n problems and lay out the queue and the workspace (whose
 // device base address is ws_base; may be null when only sizes are wanted).
 gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image *q,
-                     const gf_params *pr, char *ws_base, BatchPlan *plan);
+                     const gf_params *pr, char *ws_base, const gf_batch_cfg &cfg, BatchPlan *plan);
+
+// The context's batch configuration (the default without a context).
+gf_batch_cfg ctx_batch_cfg(gf_ctx *ctx);
+bool batch_cfg_ok(const gf_batch_cfg &c);
+
+// Tile height a batch whose largest low-res radius is maxR gets (0: none fits).
+int batch_tile_h(const gf_batch_cfg &cfg, int maxR);
 
 // Upload the descriptor table and enqueue the persistent kernel on st.
 gf_status launch_plan(gf_ctx *ctx, BatchPlan &plan, void *ws, hipStream_t st);

@@ -40,6 +40,14 @@ constexpr unsigned kBatchSpinLimit = 1u << 26;  // ~3 s of polling before a wait
 hipError_t launch_batched(gf_dtype dt, int th, const BDesc *D, int n, unsigned *ctl, unsigned total,
                           unsigned p1, unsigned p2, size_t lds, int grid, bool set_lds, hipStream_t st);
 hipError_t batched_allow_lds(gf_dtype dt, int th, size_t lds);
+
+// Phase schedule: clears the control words, then the three phase grids on
+// st (coefficient tiles [0, p1),
+// box tiles [p1, p2), output blocks [p2, total)).  With set_lds the kernels'
+// dynamic-LDS limits are raised first (else phases_allow_lds must have run).
+hipError_t launch_phases(gf_dtype dt, int th, const BDesc *D, int n, unsigned *ctl, unsigned p1, unsigned p2,
+                         unsigned total, size_t lds_coeff, size_t lds_box, bool set_lds, hipStream_t st);
+hipError_t phases_allow_lds(gf_dtype dt, int th, size_t lds_coeff, size_t lds_box);
 int batched_occupancy(gf_dtype dt, int th, size_t lds);
 
 }  // namespace gf

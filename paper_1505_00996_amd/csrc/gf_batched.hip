@@ -1,6 +1,13 @@
-// Persistent batched launch: Algorithm 2 for many images of different sizes,
-// channel counts, radii and ratios in ONE kernel over a queue of tiles.
+// Batched launches: Algorithm 2 for many images of different sizes, channel
+// counts, radii and ratios.  Two schedules share one workspace layout and
+// one descriptor table:
 //
+//   phases : one ordinary grid per phase (coefficients, box means, output)
+//            over the concatenated tiles of every image -- three launches per
+//            batch whatever its size; each kernel runs at its own occupancy.
+//   queue  : ONE persistent kernel over a queue of tiles, described below.
+//
+// Queue schedule.
 // The queue is phase-major: every coefficient tile of every image (steps
 // 1-4), then every box-mean tile (step 5), then every output block (steps
 // 6-7).  A workgroup takes the next task with an atomic add on the queue
@@ -43,7 +50,7 @@ __device__ __forceinline__ int find_image(const BDesc *__restrict__ D, int n, in
     return lo;
 }
 
-template <typename T, int TH>
+template <typename T, int TH, bool COH>
 __device__ __forceinline__ void run_coeff(const BDesc &d, unsigned local, void *lds) {
     const unsigned per = (unsigned)(d.ntx_l * d.nty_l);
     const int c = (int)(local / per), r = (int)(local % per);
@@ -52,17 +59,17 @@ __device__ __forceinline__ void run_coeff(const BDesc &d, unsigned local, void *
     const T *Pc = (const T *)d.P + (int64_t)c * d.Pps;
     float *ac = d.coef + (int64_t)c * d.g.lps, *bc = d.coef + (int64_t)(d.g.C + c) * d.g.lps;
     switch (d.kind) {
-        case kSubId: coeff_tile<T, kSubId, TH, true, true>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
-        case kSubNear: coeff_tile<T, kSubNear, TH, true, true>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
-        default: coeff_tile<T, kSubLin, TH, true, true>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
+        case kSubId: coeff_tile<T, kSubId, TH, true, COH>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
+        case kSubNear: coeff_tile<T, kSubNear, TH, true, COH>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
+        default: coeff_tile<T, kSubLin, TH, true, COH>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
     }
 }
 
-template <int TH>
+template <int TH, bool COH>
 __device__ __forceinline__ void run_box(const BDesc &d, unsigned local, void *lds) {
     const unsigned per = (unsigned)(d.ntx_l * d.nty_l);
     const int m = (int)(local / per), r = (int)(local % per);
-    box_tile<TH, true>(d.coef + (int64_t)m * d.g.lps, d.mean + (int64_t)m * d.g.lps, d.g, (r / d.ntx_l) * TH,
+    box_tile<TH, COH>(d.coef + (int64_t)m * d.g.lps, d.mean + (int64_t)m * d.g.lps, d.g, (r / d.ntx_l) * TH,
                        (r % d.ntx_l) * kTileW, lds);
 }
 
@@ -236,8 +243,8 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BDesc *__restrict__ 
             skip = s_skip;
         }
         if (!skip) {
-            if (ph == 0) run_coeff<T, TH>(d, local, lds_d);
-            else if (ph == 1) run_box<TH>(d, local, lds_d);
+            if (ph == 0) run_coeff<T, TH, true>(d, local, lds_d);
+            else if (ph == 1) run_box<TH, true>(d, local, lds_d);
             else run_output<T>(d, local, (float *)lds_d);
             if (ph < 2) {
                 // this thread's coherent plane stores have completed ...
@@ -252,6 +259,93 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BDesc *__restrict__ 
         if (threadIdx.x == 0) s_task = next;
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------- phases
+//
+// Task numbering is the queue's: phase k's tasks are [start, start + count)
+// with start = 0, p1, p2.  Block -> task goes through xcd_tile, so each XCD
+// takes a contiguous run of tasks (whole images, mostly) and their halos
+// share its L2.  The kernel boundary orders the phases: plain loads/stores.
+
+// Output block of one image with the per-image kernel's code path for its
+// ratio (compile-time taps for s in {1, 2, 4, 8}).
+template <typename T, int CC>
+__device__ __forceinline__ void out_cc(const BDesc &d, int c0, int yb, int xw) {
+    const T *I = (const T *)d.I;
+    T *Q = (T *)d.Q + (int64_t)c0 * d.Qps;
+    const bool vec = d.vec != 0;
+    switch (d.g.s) {
+        case 1: output_rows<T, CC, 1>(I, d.Irs, Q, d.Qrs, d.Qps, d.mean, d.g, c0, yb, xw, vec); break;
+        case 2: output_rows<T, CC, 2>(I, d.Irs, Q, d.Qrs, d.Qps, d.mean, d.g, c0, yb, xw, vec); break;
+        case 4: output_rows<T, CC, 4>(I, d.Irs, Q, d.Qrs, d.Qps, d.mean, d.g, c0, yb, xw, vec); break;
+        case 8: output_rows<T, CC, 8>(I, d.Irs, Q, d.Qrs, d.Qps, d.mean, d.g, c0, yb, xw, vec); break;
+        default: output_rows<T, CC, 0>(I, d.Irs, Q, d.Qrs, d.Qps, d.mean, d.g, c0, yb, xw, vec); break;
+    }
+}
+
+template <typename T, int TH>
+__global__ __launch_bounds__(kThreads) void k_pcoeff(const BDesc *__restrict__ D, int n, unsigned count) {
+    extern __shared__ double lds_d[];
+    const unsigned t = (unsigned)xcd_tile((int)blockIdx.x);
+    if (t >= count) return;  // uniform per workgroup
+    const int i = find_image(D, n, 0, t);
+    run_coeff<T, TH, false>(D[i], t - D[i].base[0], lds_d);
+}
+
+template <int TH>
+__global__ __launch_bounds__(kThreads) void k_pbox(const BDesc *__restrict__ D, int n, unsigned start,
+                                                   unsigned count) {
+    extern __shared__ double lds_d[];
+    const unsigned t = (unsigned)xcd_tile((int)blockIdx.x);
+    if (t >= count) return;
+    const int i = find_image(D, n, 1, start + t);
+    run_box<TH, false>(D[i], start + t - D[i].base[1], lds_d);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pout(const BDesc *__restrict__ D, int n, unsigned start,
+                                                   unsigned count) {
+    const unsigned t = (unsigned)xcd_tile((int)blockIdx.x);
+    if (t >= count) return;
+    const int i = find_image(D, n, 2, start + t);
+    const BDesc &d = D[i];
+    const unsigned local = start + t - d.base[2];
+    const unsigned per = (unsigned)(d.ntx_o * d.nty_o);
+    const int grp = (int)(local / per), r = (int)(local % per);
+    const int c0 = 3 * grp, cc = min(3, d.g.C - c0);
+    const int yb = (r / d.ntx_o) * (4 * kOutRows) + wave_id() * kOutRows, xw = (r % d.ntx_o) * kOutTileW;
+    if (cc == 3) out_cc<T, 3>(d, c0, yb, xw);
+    else if (cc == 2) out_cc<T, 2>(d, c0, yb, xw);
+    else out_cc<T, 1>(d, c0, yb, xw);
+}
+
+unsigned grid8u(unsigned n) { return (n + 7u) / 8u * 8u; }
+
+template <typename Kn>
+hipError_t allow(Kn k, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <typename T, int TH>
+hipError_t phases_t(const BDesc *D, int n, unsigned p1, unsigned p2, unsigned total, size_t lds_coeff,
+                    size_t lds_box, bool set_lds, hipStream_t st) {
+    if (set_lds) {
+        (void)allow(k_pcoeff<T, TH>, lds_coeff);
+        (void)allow(k_pbox<TH>, lds_box);
+    }
+    const dim3 block(kThreads);
+    if (p1) hipLaunchKernelGGL((k_pcoeff<T, TH>), dim3(grid8u(p1)), block, lds_coeff, st, D, n, p1);
+    if (p2 > p1) hipLaunchKernelGGL((k_pbox<TH>), dim3(grid8u(p2 - p1)), block, lds_box, st, D, n, p1, p2 - p1);
+    if (total > p2) hipLaunchKernelGGL((k_pout<T>), dim3(grid8u(total - p2)), block, 0, st, D, n, p2, total - p2);
+    return hipGetLastError();
+}
+
+template <typename T, int TH>
+hipError_t phases_allow_t(size_t lds_coeff, size_t lds_box) {
+    hipError_t e = allow(k_pcoeff<T, TH>, lds_coeff);
+    return e != hipSuccess ? e : allow(k_pbox<TH>, lds_box);
 }
 
 // Clears the queue head, the error word and the per-image counters (a kernel
@@ -314,6 +408,39 @@ hipError_t batched_allow_lds(gf_dtype dt, int th, size_t lds) {
         case GF_BF16: GF_A(dev::bf16);
     }
 #undef GF_A
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_phases(gf_dtype dt, int th, const BDesc *D, int n, unsigned *ctl, unsigned p1, unsigned p2,
+                         unsigned total, size_t lds_coeff, size_t lds_box, bool set_lds, hipStream_t st) {
+    // the error word reads 0 after a phase-schedule launch as well
+    const int nctl = batch_ctl_words(n);
+    hipLaunchKernelGGL(k_zero, dim3((nctl + 255) / 256), dim3(256), 0, st, ctl, nctl);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define GF_P(TT)                                                                                    \
+    return th == 8 ? phases_t<TT, 8>(D, n, p1, p2, total, lds_coeff, lds_box, set_lds, st)          \
+         : th == 16 ? phases_t<TT, 16>(D, n, p1, p2, total, lds_coeff, lds_box, set_lds, st)        \
+                    : phases_t<TT, 24>(D, n, p1, p2, total, lds_coeff, lds_box, set_lds, st)
+    switch (dt) {
+        case GF_F32: GF_P(float);
+        case GF_F16: GF_P(_Float16);
+        case GF_BF16: GF_P(dev::bf16);
+    }
+#undef GF_P
+    return hipErrorInvalidValue;
+}
+
+hipError_t phases_allow_lds(gf_dtype dt, int th, size_t lds_coeff, size_t lds_box) {
+#define GF_PA(TT)                                                                 \
+    return th == 8 ? phases_allow_t<TT, 8>(lds_coeff, lds_box)                    \
+         : th == 16 ? phases_allow_t<TT, 16>(lds_coeff, lds_box) : phases_allow_t<TT, 24>(lds_coeff, lds_box)
+    switch (dt) {
+        case GF_F32: GF_PA(float);
+        case GF_F16: GF_PA(_Float16);
+        case GF_BF16: GF_PA(dev::bf16);
+    }
+#undef GF_PA
     return hipErrorInvalidValue;
 }
 

@@ -43,6 +43,7 @@ struct Request {
     gf_image I, p, q;
     gf_params pr;
     size_t footprint;  // workspace bytes of this request alone
+    int R;             // low-res radius (decides the request's tile height)
     gf_req_stats st{};
     gf_status status = GF_PENDING;
 };
@@ -118,7 +119,7 @@ class Engine {
         gf_status st = validate(I, p, q, pr);
         if (st != GF_OK) return st;
         BatchPlan one;
-        if ((st = plan_batch(1, I, p, q, pr, nullptr, &one)) != GF_OK) return st;
+        if ((st = plan_batch(1, I, p, q, pr, nullptr, ctx_batch_cfg(ctx_), &one)) != GF_OK) return st;
         if (one.th == 0) return fail(GF_ENOTSUP, "radius too large for the batched kernel");
         if (one.ws_bytes > bytes_)
             return fail(GF_ENOMEM, "request needs %zu bytes of arena, the arena holds %zu", one.ws_bytes,
@@ -134,6 +135,7 @@ class Engine {
         r.q = *q;
         r.pr = *pr;
         r.footprint = one.ws_bytes;
+        r.R = lowres_radius(pr->r, pr->s);
         r.st.t_submit = now_s();
         queue_.push_back(t);
         *ticket = t;
@@ -211,19 +213,26 @@ class Engine {
     }
 
     // Admit queued requests (arrival order) into one batch while the batch's
-    // workspace fits in a free arena range, and launch it.
+    // workspace fits in a free arena range, and launch it.  A batch holds
+    // only requests that get the same tile height on their own, so the
+    // batch's tile height is theirs and every result has the bits of the
+    // request run alone, whatever it was batched with.
     void admit() {
         while (!queue_.empty() && !free_slots_.empty()) {
             const size_t room = alloc_.largest();
+            const gf_batch_cfg cfg = ctx_batch_cfg(ctx_);
             std::vector<uint64_t> take;
             std::vector<gf_image> I, p, q;
             std::vector<gf_params> pr;
             size_t need = 0;
+            int th = -1;
             for (uint64_t tk : queue_) {
                 const Request &r = reqs_.at(tk);
+                const int rth = batch_tile_h(cfg, r.R);
+                if (th < 0) th = rth;
                 // the batch's own workspace grows by this request's planes and descriptor
                 const size_t grow = r.footprint;
-                if (need + grow > room || (int)take.size() >= kMaxBatch) break;
+                if (rth != th || need + grow > room || (int)take.size() >= kMaxBatch) break;
                 need += grow;
                 take.push_back(tk);
                 I.push_back(r.I);
@@ -233,7 +242,7 @@ class Engine {
             }
             if (take.empty()) return;  // the head does not fit yet: wait for a batch to finish
             BatchPlan plan;
-            if (plan_batch((int)take.size(), I.data(), p.data(), q.data(), pr.data(), nullptr, &plan) != GF_OK) {
+            if (plan_batch((int)take.size(), I.data(), p.data(), q.data(), pr.data(), nullptr, cfg, &plan) != GF_OK) {
                 fail_requests(take);
                 continue;
             }
@@ -241,7 +250,7 @@ class Engine {
             const size_t bytes = round256(plan.ws_bytes);
             if (!alloc_.alloc(bytes, &off)) return;  // cannot happen (need >= plan size), wait
             char *ws = arena_ + off;
-            (void)plan_batch((int)take.size(), I.data(), p.data(), q.data(), pr.data(), ws, &plan);
+            (void)plan_batch((int)take.size(), I.data(), p.data(), q.data(), pr.data(), ws, cfg, &plan);
             hipStream_t s = streams_[next_stream_++ % streams_.size()];
             Batch b{take, off, bytes, nullptr, free_slots_.back()};
             free_slots_.pop_back();

@@ -1,6 +1,6 @@
 // Tile-shape autotuner for the window-sum kernels, pinned shapes, and their
 // JSON cache (gf_ctx_set_tiles, gf_tune, gf_ctx_save_tuning,
-// gf_ctx_load_tuning).
+// gf_ctx_load_tuning); the batch autotuner (gf_tune_batched).
 #include <hip/hip_runtime_api.h>
 
 #include <stdio.h>
@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "gf_api_internal.h"
+#include "gf_batch_host.h"
 
 namespace gf {
 
@@ -160,6 +161,69 @@ gf_status gf_ctx_load_tuning(gf_ctx *ctx, const char *path) {
     }
     fclose(f);
     return st;
+}
+
+gf_status gf_tune_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_image *p, gf_image *q,
+                          const gf_params *pr, void *ws, size_t ws_bytes, void *stream, int32_t reps,
+                          gf_batch_cfg *best, gf_batch_tune_result *results, int32_t max_results,
+                          int32_t *n_results) {
+    if (!ctx) return fail(GF_EINVAL, "gf_tune_batched needs a context");
+    if (n_results) *n_results = 0;
+    if (reps < 1) reps = 5;
+    gf_status st;
+    if ((st = ctx_use_device(ctx)) != GF_OK) return st;
+    const gf_batch_cfg saved = ctx_batch_cfg(ctx);
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(GF_EDEVICE, "hipEventCreate failed");
+    }
+    gf_batch_cfg win{};
+    double win_ms = 0.0;
+    int found = 0, nres = 0;
+    st = GF_OK;
+    for (int sched : {GF_BATCH_PHASES, GF_BATCH_QUEUE}) {
+        for (int th : {8, 16, 24}) {
+            const gf_batch_cfg c{sched, th};
+            BatchPlan plan;
+            if ((st = plan_batch(n, I, p, q, pr, (char *)ws, c, &plan)) != GF_OK) break;
+            if (plan.th != th) continue;  // does not fit at this batch's largest radius
+            (void)gf_ctx_set_batch_cfg(ctx, &c);
+            if ((st = gf_fast_batched(ctx, n, I, p, q, pr, ws, ws_bytes, stream)) != GF_OK) break;
+            hipError_t e = hipEventRecord(e0, s);
+            for (int k = 0; k < reps && st == GF_OK; ++k) st = gf_fast_batched(ctx, n, I, p, q, pr, ws, ws_bytes, stream);
+            if (st != GF_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                st = fail(GF_EDEVICE, "timing: %s", hipGetErrorString(e));
+                break;
+            }
+            const double per = (double)ms / reps;
+            if (results && nres < max_results) results[nres++] = gf_batch_tune_result{c, per};
+            if (!found || per < win_ms) {
+                win = c;
+                win_ms = per;
+                found = 1;
+            }
+        }
+        if (st != GF_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (n_results) *n_results = nres;
+    if (st != GF_OK || !found) {
+        (void)gf_ctx_set_batch_cfg(ctx, &saved);
+        return st != GF_OK ? st : fail(GF_ENOTSUP, "no batched configuration fits this batch");
+    }
+    (void)gf_ctx_set_batch_cfg(ctx, &win);
+    if (best) *best = win;
+    if ((st = gf_fast_batched(ctx, n, I, p, q, pr, ws, ws_bytes, stream)) != GF_OK) return st;
+    const hipError_t e = hipStreamSynchronize(s);
+    return e == hipSuccess ? GF_OK : fail(GF_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
 }
 
 }  // extern "C"

@@ -177,3 +177,11 @@ def test_prepared_batch_rejected_on_host():
     assert create(prs=bad) == gfp.GF_EINVAL and h.value is None
     assert L.gf_batch_launch(None, None) == gfp.GF_EINVAL
     L.gf_batch_destroy(None)
+
+
+def test_batch_cfg_needs_context():
+    c = gfp.gf_batch_cfg(gfp.GF_BATCH_PHASES, 16)
+    assert L.gf_ctx_set_batch_cfg(None, ctypes.byref(c)) == gfp.GF_EINVAL
+    n = ctypes.c_int32(-1)
+    assert L.gf_tune_batched(None, 1, None, None, None, None, None, 0, None, 1, None, None, 0,
+                             ctypes.byref(n)) == gfp.GF_EINVAL

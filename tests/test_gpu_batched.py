@@ -25,14 +25,17 @@ def make(spec, k, dtype):
     return gpuutil.to_device(I, dtype), gpuutil.to_device(p, dtype)
 
 
+@pytest.mark.parametrize("schedule,th", [("phases", 16), ("queue", 16), ("phases", 8), ("queue", 24)])
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
-def test_mixed_batch_matches_oracle_and_solo(dtype):
+def test_mixed_batch_matches_oracle_and_solo(dtype, schedule, th):
     import torch
+    print(f"mixed batch {dtype} {schedule} th={th}", flush=True)
     imgs = [make(sp, k, dtype) for k, sp in enumerate(MIX)]
     Is = [a for a, _ in imgs]
     ps = [b for _, b in imgs]
     prs = [gfp.params(r, s, 1e-3, sub) for (_, _, _, r, s, sub) in MIX]
     ctx = gfp.Context(0)
+    ctx.set_batch_cfg(schedule, th)
     qs = gfp.gf_fast_batched(Is, ps, prs, ctx=ctx)
     torch.cuda.synchronize()
     for k, ((h, w, c, r, s, sub), dI, dp, q) in enumerate(zip(MIX, Is, ps, qs)):
@@ -42,7 +45,7 @@ def test_mixed_batch_matches_oracle_and_solo(dtype):
         tol = gpuutil.tolerance(dtype, exp)
         assert np.all(np.abs(got - exp) <= tol), (k, MIX[k], gpuutil.max_err(got, exp))
         # the same image alone, with the tile shapes the batched kernel uses
-        ctx.set_tiles(dI, dp, r, s, 1e-3, dict(coeff_th=16, box_th=16), sub)
+        ctx.set_tiles(dI, dp, r, s, 1e-3, dict(coeff_th=th, box_th=th), sub)
         solo = gfp.gf_fast(dI, dp, r, s, 1e-3, sub, ctx=ctx)
         torch.cuda.synchronize()
         assert torch.equal(solo, q), (k, MIX[k], float((solo.float() - q.float()).abs().max()))
@@ -93,3 +96,24 @@ def test_batch_rejects_bad_input():
     with pytest.raises(gfp.GfError) as e:
         gfp.gf_fast_batched([I1], [p1], [gfp.params(8, 4, 1e-3)], workspace=ws)
     assert e.value.status == gfp.GF_ENOMEM
+
+
+def test_batch_tuner_picks_a_measured_configuration():
+    import torch
+    imgs = [make(sp, k, "f16") for k, sp in enumerate(MIX)]
+    Is, ps = [a for a, _ in imgs], [b for _, b in imgs]
+    prs = [gfp.params(r, s, 1e-3, sub) for (_, _, _, r, s, sub) in MIX]
+    ctx = gfp.Context(0)
+    best, rows = ctx.tune_batched(Is, ps, prs, reps=2)
+    assert rows and best in [c for c, _ in rows]
+    assert min(rows, key=lambda x: x[1])[0] == best
+    assert {c["schedule"] for c, _ in rows} == {"phases", "queue"}
+    # the context now launches batches with the chosen configuration: same bits as solo runs
+    qs = gfp.gf_fast_batched(Is, ps, prs, ctx=ctx)
+    torch.cuda.synchronize()
+    for (h, w, c, r, s, sub), dI, dp, q in zip(MIX, Is, ps, qs):
+        ctx.set_tiles(dI, dp, r, s, 1e-3, dict(coeff_th=best["tile_h"], box_th=best["tile_h"]), sub)
+        solo = gfp.gf_fast(dI, dp, r, s, 1e-3, sub, ctx=ctx)
+        torch.cuda.synchronize()
+        assert torch.equal(solo, q), (h, w, c, r, s, sub, best)
+    ctx.close()

@@ -13,9 +13,9 @@ pytestmark = pytest.mark.gpu
 gfp = gpuutil.ensure_built()
 
 # (h, w, c, r, s, sub)
-PERSISTENT = [(300, 400, 3, 8, 4, "nearest"), (257, 129, 1, 5, 2, "bilinear"), (64, 64, 3, 3, 1, "nearest"),
-              (511, 333, 1, 12, 8, "nearest"), (1, 500, 1, 4, 4, "nearest"), (220, 330, 5, 7, 2, "nearest")]
-# r' = 60 does not fit the persistent kernel's staged tiles: per-image kernels
+BATCH = [(300, 400, 3, 8, 4, "nearest"), (257, 129, 1, 5, 2, "bilinear"), (64, 64, 3, 3, 1, "nearest"),
+         (511, 333, 1, 12, 8, "nearest"), (1, 500, 1, 4, 4, "nearest"), (220, 330, 5, 7, 2, "nearest")]
+# r' = 60 does not fit the batched kernels' staged tiles: per-image kernels
 PER_IMAGE = [(150, 170, 3, 60, 1, "nearest"), (90, 200, 1, 30, 2, "nearest")]
 
 
@@ -26,15 +26,17 @@ def content(spec, seed, dtype):
     return gpuutil.to_device(I, dtype), gpuutil.to_device(p, dtype)
 
 
-def run_graph_case(specs, dtype, replays=3):
+def run_graph_case(specs, dtype, schedule="phases", replays=3):
     import torch
-    print(f"graph case: {len(specs)} images, {dtype}", flush=True)
+    print(f"graph case: {len(specs)} images, {dtype}, {schedule}", flush=True)
     Is, ps = map(list, zip(*[content(sp, 10 + k, dtype) for k, sp in enumerate(specs)]))
     prs = [gfp.params(r, s, 1e-3, sub) for (_, _, _, r, s, sub) in specs]
-    b = gfp.Batch(Is, ps, prs)
+    bctx = gfp.Context(0)
+    bctx.set_batch_cfg(schedule, 16)
+    b = gfp.Batch(Is, ps, prs, ctx=bctx)
     # an eager launch of the prepared batch first (also loads its kernels)
     b.launch()
-    ref = gfp.gf_fast_batched(Is, ps, prs)
+    ref = gfp.gf_fast_batched(Is, ps, prs, ctx=bctx)
     torch.cuda.synchronize()
     for k, (q, e) in enumerate(zip(b.qs, ref)):
         assert torch.equal(q, e), (k, specs[k])
@@ -56,7 +58,7 @@ def run_graph_case(specs, dtype, replays=3):
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        ref = gfp.gf_fast_batched(Is, ps, prs)
+        ref = gfp.gf_fast_batched(Is, ps, prs, ctx=bctx)
         torch.cuda.synchronize()
         for k, (sp, q, e) in enumerate(zip(specs, b.qs, ref)):
             assert torch.equal(q, e), (rep, k, sp)
@@ -69,11 +71,13 @@ def run_graph_case(specs, dtype, replays=3):
     del g
     ctx.close()
     b.close()
+    bctx.close()
 
 
+@pytest.mark.parametrize("schedule", ["phases", "queue"])
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
-def test_graph_replays_persistent_batch(dtype):
-    run_graph_case(PERSISTENT, dtype)
+def test_graph_replays_batch(dtype, schedule):
+    run_graph_case(BATCH, dtype, schedule)
 
 
 def test_graph_replays_per_image_batch():

@@ -24,8 +24,9 @@ def requests(n, seed=7, mp_hi=1.5):
 
 
 def solo(ctx, spec, dI, dp):
-    ctx.set_tiles(dI, dp, spec.r, spec.s, spec.eps, dict(coeff_th=16, box_th=16))
-    return gfp.gf_fast(dI, dp, spec.r, spec.s, spec.eps, ctx=ctx)
+    """The request alone: a batch of one under the same (default) batch
+    configuration -- the tile height depends on the request's own radius only."""
+    return gfp.gf_fast_batched([dI], [dp], [gfp.params(spec.r, spec.s, spec.eps)], ctx=ctx)[0]
 
 
 def test_mix_equals_alone_and_oracle():
@@ -112,4 +113,32 @@ def test_status_codes():
     assert e.value.status == gfp.GF_EINVAL
     torch.cuda.synchronize()
     assert torch.equal(q, q2)
+    ctx.close()
+
+
+def test_radii_needing_different_tile_heights():
+    """Requests whose r' = 2, 30, 33 get 24-, 16- and 8-row tiles on their
+    own; interleaved, each still equals its own batch of one."""
+    import torch
+    specs = [(180, 260, 3, 8), (200, 240, 1, 120), (150, 300, 3, 8), (210, 220, 3, 132),
+             (170, 250, 1, 8), (190, 230, 3, 120)]
+    ctx = gfp.Context(0, arena_bytes=1 << 28, max_inflight=16)
+    ref = gfp.Context(0)
+    items = []
+    for k, (h, w, c, r) in enumerate(specs):
+        I = synth.photo_guide(h, w, seed=300 + k)
+        p = synth.colour_input(I, c, seed=400 + k)
+        dI, dp = gpuutil.to_device(I, "f16"), gpuutil.to_device(p, "f16")
+        q = torch.empty_like(dp)
+        items.append((h, w, c, r, dI, dp, q, ctx.gf_submit(dI, dp, q, r, 4, 1e-3)))
+    for h, w, c, r, dI, dp, q, t in items:
+        st, _ = ctx.gf_poll(t, wait_ms=-1)
+        assert st == gfp.GF_OK
+        alone = gfp.gf_fast_batched([dI], [dp], [gfp.params(r, 4, 1e-3)], ctx=ref)[0]
+        torch.cuda.synchronize()
+        assert torch.equal(alone, q), (h, w, c, r)
+        exp = oracle.fast_guided_filter(gpuutil.stored_f64(dI), gpuutil.stored_f64(dp), r, 4, 1e-3)
+        got = gpuutil.stored_f64(q)
+        assert np.all(np.abs(got - exp) <= gpuutil.tolerance("f16", exp)), (h, w, c, r)
+    ref.close()
     ctx.close()
