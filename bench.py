@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (parity and CPU baseline)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and served measurements")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="only the 256-image batch, default batch configuration, no tuning (for kernel traces)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="a short run for counter collection: a few fast steps and a copy kernel "
                          "of known size, no oracle")
@@ -84,7 +86,7 @@ def read_traffic():
     return float(m_b.group(1))
 
 
-def measure_batched(gfp, torch, dev, n=256, reps=5, seed=6):
+def measure_batched(gfp, torch, dev, n=256, reps=5, seed=6, tune=True):
     """One persistent launch over a batch of n images drawn like the
     256-image workload: H~U{256..1536}, W~U{256..2048} (swapped with prob.
     1/2), s in {2,4,8}, C in {1,3}, r = round(0.01 max(H,W)), eps = 1e-3,
@@ -104,7 +106,7 @@ def measure_batched(gfp, torch, dev, n=256, reps=5, seed=6):
     ctx = gfp.Context(0)
     ws = torch.empty(gfp.batched_workspace_bytes(Is, ps, prs), dtype=torch.uint8, device=dev)
     # the batch autotuner picks the schedule and tile height (kept by ctx)
-    best, tried = ctx.tune_batched(Is, ps, prs, qs=qs, workspace=ws, reps=2)
+    best, tried = ctx.tune_batched(Is, ps, prs, qs=qs, workspace=ws, reps=2) if tune else ({}, [])
     gfp.gf_fast_batched(Is, ps, prs, qs=qs, ctx=ctx, workspace=ws)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -137,7 +139,7 @@ def measure_batched(gfp, torch, dev, n=256, reps=5, seed=6):
                         "C in {1,3}, r = round(0.01 max(H,W)), eps=1e-3, one batched launch"}
 
 
-def measure_served(gfp, torch, dev, pool=48, seed=7, seconds=1.5):
+def measure_served(gfp, torch, dev, pool=96, seed=7, seconds=2.5):
     """Requests through gf_submit / gf_poll: log-uniform 0.25-24 MP, aspect
     1:1/4:3/3:2/16:9 either way, gray or RGB input 50/50, s = 4,
     r = round(0.01 max(H,W)), eps in {1e-2, 1e-3}, fp16, inputs resident on
@@ -227,6 +229,9 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.only_batched:
+        print(json.dumps({"batched": measure_batched(gfp, torch, dev, reps=10, tune=False)}), flush=True)
+        return
     I_np, p_np = synth.workload_12mp(H, W, C)
     sets = []
     for k in range(args.sets):
@@ -290,6 +295,19 @@ def main():
         step_fast(i)
     ms_fast = timed(step_fast, 0, args.steps)
     print(f"# fast: {ms_fast:.4f} ms/step", file=sys.stderr, flush=True)
+
+    # per-step GPU time: a pair of HIP events around every step, on the
+    # stream the kernels are launched on
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for i, (e0, e1) in enumerate(evs):
+        e0.record(stream)
+        step_fast(i)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    per_step = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    step_events = {"median_ms": round(per_step[len(per_step) // 2], 5),
+                   "p99_ms": round(per_step[min(len(per_step) - 1, int(0.99 * len(per_step)))], 5)}
 
     # the same steps again with HIP events around each kernel on its stream
     ctx.profile(True)
@@ -366,6 +384,7 @@ def main():
         "plain": {"value": round(mpix / (ms_plain * 1e-3), 1), "unit": "MPix/s",
                   "ms_per_step": round(ms_plain, 5), "steps": plain_steps},
         "speedup_vs_plain": round(ms_plain / ms_fast, 3),
+        "step_events": step_events,
         "ms_per_step_with_kernel_events": round(ms_fast_ev, 5),
         "kernels": kernels,
         "batched": batched,
@@ -396,7 +415,9 @@ def main():
         step_plain(0)
         torch.cuda.synchronize()
         q_plain = q.double().cpu().numpy()
+        t0 = time.perf_counter()
         exp_plain = oracle.guided_filter(I64, p64, R_FULL, EPS)
+        t_plain = time.perf_counter() - t0
         err_plain = float(np.max(np.abs(q_plain - exp_plain)))
         result["max_abs_err"] = err_fast
         result["plain"]["max_abs_err"] = err_plain
@@ -405,6 +426,10 @@ def main():
             "value": round(mpix * runs / t_cpu, 3), "unit": "MPix/s", "cores": 1, "kind": "oracle",
             "sample": f"{runs} full runs of the FP64 oracle's fast filter (s=4) on the same "
                       f"4000x3000 RGB workload, single thread, {t_cpu:.1f} s"}
+        # the same oracle's plain filter (one run, taken for parity above):
+        # its fast/plain ratio is the CPU counterpart of the paper's speedup
+        result["cpu_oracle_plain"] = {"value": round(mpix / t_plain, 3), "unit": "MPix/s", "cores": 1,
+                                      "fast_over_plain": round(t_plain / (t_cpu / runs), 2)}
     print(json.dumps(result), flush=True)
 
 

@@ -153,6 +153,15 @@ gf_status gf_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q
                   const gf_params *params, void *workspace, size_t workspace_bytes,
                   void *hip_stream);
 
+/*
+ * Admission unit of the request interface: the bytes of the context's arena
+ * one request of this shape occupies while it is in flight (its low-res maps
+ * and its share of the batch's control words and descriptor table).
+ * gf_submit refuses a request whose footprint exceeds the arena (GF_ENOMEM).
+ * The dtype does not change it (all maps are FP32).  0 for invalid sizes.
+ */
+size_t gf_footprint_bytes(int32_t h, int32_t w, int32_t c, gf_dtype dtype, const gf_params *params);
+
 /* Workspace (bytes) of gf_fast_batched for n images (device memory). */
 size_t gf_batched_workspace_bytes(int32_t n, const gf_image *I, const gf_image *p,
                                   const gf_params *params);

@@ -33,7 +33,7 @@ EXPORTS = ("gf_ctx_create", "gf_ctx_destroy", "gf_last_error", "gf_workspace_byt
            "gf_fast", "gf_batched_workspace_bytes", "gf_fast_batched", "gf_submit", "gf_poll",
            "gf_ctx_profile", "gf_ctx_profile_read", "gf_ctx_set_tiles", "gf_tune",
            "gf_ctx_save_tuning", "gf_ctx_load_tuning", "gf_batch_create", "gf_batch_launch",
-           "gf_batch_destroy", "gf_ctx_set_batch_cfg", "gf_tune_batched")
+           "gf_batch_destroy", "gf_ctx_set_batch_cfg", "gf_tune_batched", "gf_footprint_bytes")
 KERNELS = ("coeff", "box", "output", "batched")
 
 
@@ -131,6 +131,7 @@ def lib() -> ctypes.CDLL:
             "gf_batch_launch": (ctypes.c_int, [VP, VP]),
             "gf_batch_destroy": (None, [VP]),
             "gf_ctx_set_batch_cfg": (ctypes.c_int, [VP, P(gf_batch_cfg)]),
+            "gf_footprint_bytes": (SZ, [I32, I32, I32, ctypes.c_int, par_p]),
             "gf_tune_batched": (ctypes.c_int, [VP, I32, img_p, img_p, img_p, par_p, VP, SZ, VP, I32,
                                                P(gf_batch_cfg), P(gf_batch_tune_result), I32, P(I32)]),
         }
@@ -251,6 +252,12 @@ def _arrays(Is, ps, qs, prs):
         raise ValueError("I, p, q and params lists must have the same length")
     return ((gf_image * n)(*[image(t) for t in Is]), (gf_image * n)(*[image(t) for t in ps]),
             (gf_image * n)(*[image(t) for t in qs]), (gf_params * n)(*prs))
+
+
+def footprint_bytes(h: int, w: int, c: int, r: int, s: int, eps: float, dtype: int = GF_F32,
+                    sub="nearest") -> int:
+    """Arena bytes one request of this shape occupies (gf_footprint_bytes)."""
+    return int(lib().gf_footprint_bytes(h, w, c, dtype, ctypes.byref(params(r, s, eps, sub))))
 
 
 def batched_workspace_bytes(Is, ps, prs) -> int:

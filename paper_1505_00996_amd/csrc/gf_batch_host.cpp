@@ -103,7 +103,7 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
         d.nty_l = (g.Hl + th - 1) / th;
         d.ntx_o = (g.W + kOutTileW - 1) / kOutTileW;
         d.nty_o = (g.H + 4 * 8 - 1) / (4 * 8);
-        d.ntiles[0] = (unsigned)(d.ntx_l * d.nty_l * g.C);
+        d.ntiles[0] = (unsigned)(d.ntx_l * d.nty_l);  // a coefficient task covers every channel
         d.ntiles[1] = (unsigned)(d.ntx_l * d.nty_l * 2 * g.C);
         d.ntiles[2] = (unsigned)(d.ntx_o * d.nty_o * ((g.C + 2) / 3));
         const size_t planes = sizeof(float) * (size_t)g.lps * 2 * g.C;
@@ -212,6 +212,13 @@ size_t gf_batched_workspace_bytes(int32_t n, const gf_image *I, const gf_image *
         planes += 2 * round256(sizeof(float) * (size_t)g.lps * 2 * g.C);
     }
     return round256(sizeof(unsigned) * batch_ctl_words(n)) + round256(sizeof(BDesc) * n) + planes;
+}
+
+size_t gf_footprint_bytes(int32_t h, int32_t w, int32_t c, gf_dtype dtype, const gf_params *pr) {
+    if (!pr || (dtype != GF_F32 && dtype != GF_F16 && dtype != GF_BF16)) return 0;
+    gf_image I{nullptr, dtype, 1, h, w, w, (int64_t)w * h};
+    gf_image p{nullptr, dtype, c, h, w, w, (int64_t)w * h};
+    return gf_batched_workspace_bytes(1, &I, &p, pr);
 }
 
 gf_status gf_fast_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_image *p, gf_image *q,

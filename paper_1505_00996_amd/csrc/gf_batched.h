@@ -19,7 +19,7 @@ struct BDesc {
     int ntx_l, nty_l;        // low-res tiles: 64 columns x TH rows
     int ntx_o, nty_o;        // output blocks: 256 columns x 32 rows
     unsigned base[3];        // queue index of the image's first task in each phase
-    unsigned ntiles[3];      // tasks of each phase: C*tiles, 2C*tiles, groups*blocks
+    unsigned ntiles[3];      // tasks of each phase: tiles, 2C*tiles, groups*blocks
 };
 
 // The control words live at the start of the batch workspace: [0] queue

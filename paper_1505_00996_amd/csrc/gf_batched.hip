@@ -52,16 +52,12 @@ __device__ __forceinline__ int find_image(const BDesc *__restrict__ D, int n, in
 
 template <typename T, int TH, bool COH>
 __device__ __forceinline__ void run_coeff(const BDesc &d, unsigned local, void *lds) {
-    const unsigned per = (unsigned)(d.ntx_l * d.nty_l);
-    const int c = (int)(local / per), r = (int)(local % per);
-    const int ty0 = (r / d.ntx_l) * TH, tx0 = (r % d.ntx_l) * kTileW;
-    const T *I = (const T *)d.I;
-    const T *Pc = (const T *)d.P + (int64_t)c * d.Pps;
-    float *ac = d.coef + (int64_t)c * d.g.lps, *bc = d.coef + (int64_t)(d.g.C + c) * d.g.lps;
+    const int ty0 = ((int)local / d.ntx_l) * TH, tx0 = ((int)local % d.ntx_l) * kTileW;
+    const T *I = (const T *)d.I, *P = (const T *)d.P;
     switch (d.kind) {
-        case kSubId: coeff_tile<T, kSubId, TH, true, COH>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
-        case kSubNear: coeff_tile<T, kSubNear, TH, true, COH>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
-        default: coeff_tile<T, kSubLin, TH, true, COH>(I, d.Irs, Pc, d.Prs, ac, bc, d.g, ty0, tx0, lds); break;
+        case kSubId: coeff_tile<T, kSubId, TH, true, COH>(I, d.Irs, P, d.Prs, d.Pps, d.coef, d.g, ty0, tx0, lds); break;
+        case kSubNear: coeff_tile<T, kSubNear, TH, true, COH>(I, d.Irs, P, d.Prs, d.Pps, d.coef, d.g, ty0, tx0, lds); break;
+        default: coeff_tile<T, kSubLin, TH, true, COH>(I, d.Irs, P, d.Prs, d.Pps, d.coef, d.g, ty0, tx0, lds); break;
     }
 }
 
@@ -136,7 +132,7 @@ __device__ __forceinline__ void run_output(const BDesc &d, unsigned local, float
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int jj = x0 + j < g.W ? j : 0;  // stays inside the row
-                        out[j] = ldp<true>(Ma + o + jj) * widen(iv[i], j) + ldp<true>(Mb + o + jj);
+                        out[j] = madd(ldp<true>(Ma + o + jj), widen(iv[i], j), ldp<true>(Mb + o + jj));
                     }
                     store_q(Qc, yb + i, out);
                 }
@@ -187,11 +183,11 @@ __device__ __forceinline__ void run_output(const BDesc &d, unsigned local, float
                     f32x4 out;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const float a0 = pa[r0 + xa[j]] + wx[j] * (pa[r0 + xb[j]] - pa[r0 + xa[j]]);
-                        const float a1 = pa[r1 + xa[j]] + wx[j] * (pa[r1 + xb[j]] - pa[r1 + xa[j]]);
-                        const float b0 = pb[r0 + xa[j]] + wx[j] * (pb[r0 + xb[j]] - pb[r0 + xa[j]]);
-                        const float b1 = pb[r1 + xa[j]] + wx[j] * (pb[r1 + xb[j]] - pb[r1 + xa[j]]);
-                        out[j] = (a0 + wy * (a1 - a0)) * widen(iv[i], j) + (b0 + wy * (b1 - b0));
+                        const float a0 = lerp(pa[r0 + xa[j]], pa[r0 + xb[j]], wx[j]);
+                        const float a1 = lerp(pa[r1 + xa[j]], pa[r1 + xb[j]], wx[j]);
+                        const float b0 = lerp(pb[r0 + xa[j]], pb[r0 + xb[j]], wx[j]);
+                        const float b1 = lerp(pb[r1 + xa[j]], pb[r1 + xb[j]], wx[j]);
+                        out[j] = madd(lerp(a0, a1, wy), widen(iv[i], j), lerp(b0, b1, wy));
                     }
                     store_q(Qc, yb + i, out);
                 }

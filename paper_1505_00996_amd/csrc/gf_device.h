@@ -36,6 +36,13 @@
 namespace gf {
 namespace dev {
 
+// Floating-point expressions in this file (and in the kernels that include
+// it) are evaluated as written: no multiply and add are fused unless an fma
+// is spelled out.  The same tile code is inlined into several kernels, and
+// left to itself the compiler fuses differently in each, so one pixel could
+// get different bits from the per-image and the batched launches.
+#pragma clang fp contract(off)
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
@@ -153,6 +160,9 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 
 // Approximate reciprocal (1 ulp): the results it feeds tolerate 1e-7.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// a + w (b - a) and a x + b, each with one fused rounding
+__device__ __forceinline__ float lerp(float a, float b, float w) { return __builtin_fmaf(w, b - a, a); }
+__device__ __forceinline__ float madd(float a, float x, float b) { return __builtin_fmaf(a, x, b); }
 
 // ---------------------------------------------------------------- sampling
 //
@@ -297,17 +307,20 @@ __device__ __forceinline__ void coeff_from_sums(int n, double Su, double Suu, do
     b = mp - a * mI;           // Eq. 3
 }
 
-// One TH x 64 tile of a, b (low-res) at tile origin (ty0, tx0), for one
-// channel of p.  The statistics are formed in two phases (I alone, then I
-// with p) so that LDS holds two FP64 row-sum planes instead of four.  With
-// STAGE the samples of the region are staged in LDS first; without it (large
-// r', where the staged region would not fit) the row pass reads them through
-// the caches.
+// One TH x 64 tile of a_c, b_c (low-res) at tile origin (ty0, tx0) for every
+// channel c of p (planes P + c*Pps; a_c at coef + c*lps, b_c at
+// coef + (C+c)*lps).  The guide's window statistics (sums of u and u*u) are
+// formed once and kept in registers; then, channel by channel, those of p
+// (sums of v and u*v) and the coefficients.  LDS holds two FP64 row-sum
+// planes at a time.  With STAGE the samples of the region are staged in LDS
+// first (the guide's once, each channel's in turn); without it (large r',
+// where the staged region would not fit) the row pass reads them through the
+// caches.
 template <typename T, int K, int TH, bool STAGE, bool COH = false>
 __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
-                                           const T *__restrict__ Pc, int64_t Prs,
-                                           float *__restrict__ ac, float *__restrict__ bc,
-                                           const Geo &g, int ty0, int tx0, void *lds) {
+                                           const T *__restrict__ P, int64_t Prs, int64_t Pps,
+                                           float *__restrict__ coef, const Geo &g, int ty0, int tx0,
+                                           void *lds) {
     constexpr int LC = TH / 4;  // output rows per thread in the column pass
     const int R = g.R, SH = TH + 2 * R, SW = kTileW + 2 * R, SWp = region_stride(R);
     const int plane = SH * kRowW;
@@ -316,8 +329,6 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
     const int oy = ty0 - R, ox = tx0 - R;
     const int lane = threadIdx.x & 63, wave = wave_id();
 
-    const float cI = sample<K>(I, Irs, ty0, tx0, g);
-    const float cP = sample<K>(Pc, Prs, ty0, tx0, g);
     // u = I' - cI and v = p' - cP over the region, 0 outside the low-res map.
     // The outside case multiplies by 0 rather than selecting: a select on a
     // loaded value lets the compiler turn the load into a branch that waits
@@ -330,20 +341,16 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
                                      taps<K>(clampi(lx, 0, g.Wl - 1), g.s, g.W));
         return (v - c) * (in ? 1.f : 0.f);
     };
+    const float cI = sample<K>(I, Irs, ty0, tx0, g);
     auto gU = [&](int ry, int rx) { return gsample(I, Irs, cI, ry, rx); };
-    auto gV = [&](int ry, int rx) { return gsample(Pc, Prs, cP, ry, rx); };
-    if (STAGE) {
-        fill_tile2(sU, sV, SH, SW, SWp, gU, gV);
-        __syncthreads();
-    }
 
     const int col = lane, r0 = wave * LC;
     const int lx = tx0 + col;
     const int nx = clip_len(lx, R, g.Wl);
-    double Su[LC], Suu[LC];
 
-    // PAIR = false: rA = sum u, rB = sum u*u.  PAIR = true: rA = sum v, rB = sum u*v.
-    auto row_pass = [&](auto pair) {
+    // Row pass: rA = sum x, rB = sum u*x over each run of kRun outputs, with
+    // x = u (PAIR false) or x = v (PAIR true, v from gV / sV).
+    auto row_pass = [&](auto pair, auto gV) {
         constexpr bool PAIR = decltype(pair)::value;
         for (int it = threadIdx.x; it < SH * (kTileW / kRun); it += kThreads) {
             const int ry = it >> 3, j0 = (it & 7) * kRun;
@@ -372,8 +379,17 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
         }
     };
 
-    // phase 1: sums of u and u*u
-    row_pass(std::false_type{});
+    const T *P0 = P;
+    const float cP0 = sample<K>(P0, Prs, ty0, tx0, g);
+    auto gV0 = [&](int ry, int rx) { return gsample(P0, Prs, cP0, ry, rx); };
+    if (STAGE) {
+        fill_tile2(sU, sV, SH, SW, SWp, gU, gV0);  // guide and channel 0 in one batch
+        __syncthreads();
+    }
+
+    // guide: sums of u and u*u, once for all channels
+    double Su[LC], Suu[LC];
+    row_pass(std::false_type{}, gV0);
     __syncthreads();
     {
         double A = 0.0, B = 0.0;
@@ -391,27 +407,36 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
             Suu[t] = B;
         }
     }
-    __syncthreads();
-    // phase 2: sums of v and u*v, then a and b
-    row_pass(std::true_type{});
-    __syncthreads();
-    double A = 0.0, B = 0.0;
-    for (int k = 0; k <= 2 * R; ++k) {
-        A += rA[(r0 + k) * kRowW + col];
-        B += rB[(r0 + k) * kRowW + col];
-    }
-#pragma unroll
-    for (int t = 0; t < LC; ++t) {
-        if (t) {
-            A += rA[(r0 + t + 2 * R) * kRowW + col] - rA[(r0 + t - 1) * kRowW + col];
-            B += rB[(r0 + t + 2 * R) * kRowW + col] - rB[(r0 + t - 1) * kRowW + col];
+
+    for (int c = 0; c < g.C; ++c) {
+        const T *Pc = P + (int64_t)c * Pps;
+        const float cP = c ? sample<K>(Pc, Prs, ty0, tx0, g) : cP0;
+        auto gV = [&](int ry, int rx) { return gsample(Pc, Prs, cP, ry, rx); };
+        // sV is free: the last row pass that read it ended at a barrier
+        if (STAGE && c) fill_tile(sV, SH, SW, SWp, gV);
+        __syncthreads();  // sV staged; the previous column pass is done with rA, rB
+        // sums of v and u*v, then a and b
+        row_pass(std::true_type{}, gV);
+        __syncthreads();
+        float *ac = coef + (int64_t)c * g.lps, *bc = coef + (int64_t)(g.C + c) * g.lps;
+        double A = 0.0, B = 0.0;
+        for (int k = 0; k <= 2 * R; ++k) {
+            A += rA[(r0 + k) * kRowW + col];
+            B += rB[(r0 + k) * kRowW + col];
         }
-        const int ly = ty0 + r0 + t;
-        if (ly < g.Hl && lx < g.Wl) {
-            float a, b;
-            coeff_from_sums(clip_len(ly, R, g.Hl) * nx, Su[t], Suu[t], A, B, cI, cP, g.eps, a, b);
-            stp<COH>(ac + (int64_t)ly * g.lrs + lx, a);
-            stp<COH>(bc + (int64_t)ly * g.lrs + lx, b);
+#pragma unroll
+        for (int t = 0; t < LC; ++t) {
+            if (t) {
+                A += rA[(r0 + t + 2 * R) * kRowW + col] - rA[(r0 + t - 1) * kRowW + col];
+                B += rB[(r0 + t + 2 * R) * kRowW + col] - rB[(r0 + t - 1) * kRowW + col];
+            }
+            const int ly = ty0 + r0 + t;
+            if (ly < g.Hl && lx < g.Wl) {
+                float a, b;
+                coeff_from_sums(clip_len(ly, R, g.Hl) * nx, Su[t], Suu[t], A, B, cI, cP, g.eps, a, b);
+                stp<COH>(ac + (int64_t)ly * g.lrs + lx, a);
+                stp<COH>(bc + (int64_t)ly * g.lrs + lx, b);
+            }
         }
     }
 }
@@ -540,7 +565,10 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
                     const int y = yb + i;
                     const f32x4 a = ld4(Ma + (int64_t)y * g.lrs + x0);
                     const f32x4 b = ld4(Mb + (int64_t)y * g.lrs + x0);
-                    store_q(Qc, y, a * iv[i] + b);
+                    f32x4 out;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) out[j] = madd(a[j], iv[i][j], b[j]);
+                    store_q(Qc, y, out);
                 }
             }
         }
@@ -581,8 +609,8 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int k0 = cfloor_u(j, S) - cfloor_u(0, S);  // 0 for s = 8 as well
-                    ha[m][j] = va[k0] + wx[j] * (va[k0 + 1] - va[k0]);
-                    hb[m][j] = vb[k0] + wx[j] * (vb[k0 + 1] - vb[k0]);
+                    ha[m][j] = lerp(va[k0], va[k0 + 1], wx[j]);
+                    hb[m][j] = lerp(vb[k0], vb[k0 + 1], wx[j]);
                 }
             }
 #pragma unroll
@@ -593,9 +621,9 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
                     f32x4 out;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const float a = ha[m0][j] + wy * (ha[m0 + 1][j] - ha[m0][j]);
-                        const float b = hb[m0][j] + wy * (hb[m0 + 1][j] - hb[m0][j]);
-                        out[j] = a * iv[i][j] + b;
+                        const float a = lerp(ha[m0][j], ha[m0 + 1][j], wy);
+                        const float b = lerp(hb[m0][j], hb[m0 + 1][j], wy);
+                        out[j] = madd(a, iv[i][j], b);
                     }
                     store_q(Qc, yb + i, out);
                 }
@@ -636,11 +664,11 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
                 f32x4 out;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const float a0 = ra0[xa[j]] + wx[j] * (ra0[xb[j]] - ra0[xa[j]]);
-                    const float a1 = ra1[xa[j]] + wx[j] * (ra1[xb[j]] - ra1[xa[j]]);
-                    const float b0 = rb0[xa[j]] + wx[j] * (rb0[xb[j]] - rb0[xa[j]]);
-                    const float b1 = rb1[xa[j]] + wx[j] * (rb1[xb[j]] - rb1[xa[j]]);
-                    out[j] = (a0 + wy * (a1 - a0)) * iy[j] + (b0 + wy * (b1 - b0));
+                    const float a0 = lerp(ra0[xa[j]], ra0[xb[j]], wx[j]);
+                    const float a1 = lerp(ra1[xa[j]], ra1[xb[j]], wx[j]);
+                    const float b0 = lerp(rb0[xa[j]], rb0[xb[j]], wx[j]);
+                    const float b1 = lerp(rb1[xa[j]], rb1[xb[j]], wx[j]);
+                    out[j] = madd(lerp(a0, a1, wy), iy[j], lerp(b0, b1, wy));
                 }
                 store_q(Qc, y, out);
             }

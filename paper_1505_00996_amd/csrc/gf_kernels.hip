@@ -1,7 +1,7 @@
 // Per-image kernels of the (fast) guided filter for gfx950 and their host
 // launchers.  Algorithm 2 of He & Sun, "Fast Guided Filter", runs as three
 // launches on the caller's stream:
-//   k_coeff  (grid: low-res tiles x channels)  steps 1-4 -> a, b
+//   k_coeff  (grid: low-res tiles)             steps 1-4 -> a, b (all channels)
 //   k_box    (grid: low-res tiles x 2C maps)   step 5    -> mean_a, mean_b
 //   k_output (grid: full-res 256 x 32 blocks)  steps 6-7 -> q
 // Algorithm 1 is the same three launches at s = 1, where subsampling and
@@ -23,10 +23,7 @@ __global__ __launch_bounds__(kThreads) void k_coeff(const T *__restrict__ I, int
     extern __shared__ double lds_d[];
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;  // uniform per workgroup: no barrier is skipped by part of it
-    const int c = blockIdx.y;
-    coeff_tile<T, K, TH, STAGE>(I, Irs, P + (int64_t)c * Pps, Prs, coef + (int64_t)c * g.lps,
-                         coef + (int64_t)(g.C + c) * g.lps, g, (tile / ntx) * TH, (tile % ntx) * kTileW,
-                         lds_d);
+    coeff_tile<T, K, TH, STAGE>(I, Irs, P, Prs, Pps, coef, g, (tile / ntx) * TH, (tile % ntx) * kTileW, lds_d);
 }
 
 template <int TH>
@@ -71,7 +68,7 @@ hipError_t coeff_tk(const View &I, const View &P, float *coef, const Geo &g, con
     const int ntx = (g.Wl + kTileW - 1) / kTileW, nty = (g.Hl + th - 1) / th;
     const int ntiles = ntx * nty;
     const size_t lds = coeff_lds_bytes(t, g.R);
-    const dim3 grid(grid8(ntiles), g.C), block(kThreads);
+    const dim3 grid(grid8(ntiles)), block(kThreads);
 #define GF_COEFF(TH, STG)                                                                              \
     {                                                                                                   \
         allow_lds(k_coeff<T, K, TH, STG>, lds);                                                         \

@@ -185,3 +185,17 @@ def test_batch_cfg_needs_context():
     n = ctypes.c_int32(-1)
     assert L.gf_tune_batched(None, 1, None, None, None, None, None, 0, None, 1, None, None, 0,
                              ctypes.byref(n)) == gfp.GF_EINVAL
+
+
+def test_footprint_bytes():
+    # control words and descriptor table (256-byte granules) + a, b and their means (4C planes)
+    pr = gfp.params(16, 4, 1e-3)
+    hl, wl = 750, 1000
+    lrs = -(-wl // 16) * 16
+    lps = -(-(hl * lrs) // 64) * 64
+    planes = 2 * (-(-(4 * lps * 2 * 3) // 256) * 256)
+    fp = L.gf_footprint_bytes(3000, 4000, 3, gfp.GF_F16, ctypes.byref(pr))
+    assert planes < fp <= planes + 256 + 256 * 4
+    assert fp == L.gf_footprint_bytes(3000, 4000, 3, gfp.GF_F32, ctypes.byref(pr))
+    assert L.gf_footprint_bytes(0, 4000, 3, gfp.GF_F32, ctypes.byref(pr)) == 0
+    assert L.gf_footprint_bytes(30, 40, 3, 9, ctypes.byref(pr)) == 0
