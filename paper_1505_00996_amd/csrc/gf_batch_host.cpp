@@ -78,14 +78,19 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
     plan->sched = cfg.schedule;
     plan->th = batch_th(cfg.schedule, cfg.tile_h, maxR, plan);
     plan->desc.assign(n, BDesc{});
+    // plan order: by ratio class (stable), so each class's output blocks are contiguous
+    plan->order.resize(n);
+    for (int k = 0; k < n; ++k) plan->order[k] = k;
+    std::stable_sort(plan->order.begin(), plan->order.end(),
+                     [&](int a, int b) { return ratio_class(pr[a].s) < ratio_class(pr[b].s); });
     // workspace: control words, descriptor table, then each image's 4C planes
     size_t off = round256(sizeof(unsigned) * batch_ctl_words(n));
     plan->desc_off = off;
     off += round256(sizeof(BDesc) * n);
     unsigned base[3] = {0, 0, 0};
-    std::vector<unsigned> cnt[3];
-    for (int i = 0; i < n; ++i) {
-        BDesc &d = plan->desc[i];
+    for (int k = 0; k < n; ++k) {
+        const int i = plan->order[k];
+        BDesc &d = plan->desc[k];
         const Geo g = make_geo(I[i].h, I[i].w, p[i].c, pr[i].r, pr[i].s, pr[i].eps, (int)pr[i].sub);
         d.I = I[i].data;
         d.P = p[i].data;
@@ -117,9 +122,16 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
         }
     }
     // phases follow each other in the queue
-    for (int i = 0; i < n; ++i) {
-        plan->desc[i].base[1] += base[0];
-        plan->desc[i].base[2] += base[0] + base[1];
+    for (int k = 0; k < n; ++k) {
+        plan->desc[k].base[1] += base[0];
+        plan->desc[k].base[2] += base[0] + base[1];
+    }
+    for (int c = 0; c < kRatioClasses; ++c) plan->out.lo[c] = plan->out.hi[c] = 0;
+    for (int k = n - 1; k >= 0; --k) {  // each class's first image sets lo, its last sets hi
+        const BDesc &d = plan->desc[k];
+        const int c = ratio_class(d.g.s);
+        plan->out.lo[c] = d.base[2];
+        if (plan->out.hi[c] == 0) plan->out.hi[c] = d.base[2] + d.ntiles[2];
     }
     plan->p1 = base[0];
     plan->p2 = base[0] + base[1];
@@ -148,7 +160,7 @@ static gf_status enqueue_plan(gf_ctx *ctx, const BatchPlan &plan, void *ws, int 
         plan.sched == GF_BATCH_QUEUE
             ? launch_batched(plan.dtype, plan.th, D, plan.n, (unsigned *)base, plan.total, plan.p1, plan.p2,
                              plan.lds, grid, set_lds, st)
-            : launch_phases(plan.dtype, plan.th, D, plan.n, (unsigned *)base, plan.p1, plan.p2, plan.total,
+            : launch_phases(plan.dtype, plan.th, D, plan.n, (unsigned *)base, plan.p1, plan.p2, plan.out,
                             plan.lds_coeff, plan.lds_box, set_lds, st);
     if (e != hipSuccess) return fail(GF_EDEVICE, "batched launch: %s", hipGetErrorString(e));
     return GF_OK;
@@ -240,8 +252,9 @@ gf_status gf_fast_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_im
     if (plan.th == 0) {
         // radius too large for the persistent kernel's staged tiles: one
         // gf_fast per image on the same stream (same results)
-        for (int i = 0; i < n; ++i) {
-            const BDesc &d = plan.desc[i];
+        for (int k = 0; k < n; ++k) {
+            const BDesc &d = plan.desc[k];
+            const int i = plan.order[k];
             if ((st = run_fast(ctx, &I[i], &p[i], &q[i], &pr[i], d.coef,
                                sizeof(float) * (size_t)d.g.lps * 4 * d.g.C, s, nullptr)) != GF_OK)
                 return st;
@@ -306,8 +319,9 @@ gf_status gf_batch_launch(const gf_batch *b, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     if (b->plan.th == 0) {
         gf_status st;
-        for (int i = 0; i < b->plan.n; ++i) {
-            const BDesc &d = b->plan.desc[i];
+        for (int k = 0; k < b->plan.n; ++k) {
+            const BDesc &d = b->plan.desc[k];
+            const int i = b->plan.order[k];
             if ((st = run_fast(nullptr, &b->I[i], &b->p[i], const_cast<gf_image *>(&b->q[i]), &b->pr[i],
                                d.coef, sizeof(float) * (size_t)d.g.lps * 4 * d.g.C, s, nullptr)) != GF_OK)
                 return st;

@@ -19,7 +19,9 @@ struct BatchPlan {
     size_t desc_off = 0;      // byte offset of the descriptor table in the workspace
     size_t ws_bytes = 0;      // workspace bytes the plan needs
     unsigned p1 = 0, p2 = 0, total = 0;  // queue: [0,p1) coefficients, [p1,p2) box means, [p2,total) output
-    std::vector<BDesc> desc;
+    OutRanges out{};          // output blocks of each ratio class
+    std::vector<BDesc> desc;  // in plan order: images sorted by ratio class
+    std::vector<int> order;   // order[k] = caller's index of desc[k]
 };
 
 // Validate the n problems and lay out the queue and the workspace (whose

@@ -27,6 +27,16 @@ struct BDesc {
 // done.
 inline int batch_ctl_words(int n) { return 2 + 2 * n; }
 
+// Images of a plan are ordered by ratio class (s = 1, 2, 4, 8, any other),
+// so each class's output blocks are one contiguous range of the queue and
+// the phase schedule runs them with the per-image kernel's compile-time
+// taps: class k covers queue indices [lo[k], hi[k]).
+constexpr int kRatioClasses = 5;
+inline int ratio_class(int s) { return s == 1 ? 0 : s == 2 ? 1 : s == 4 ? 2 : s == 8 ? 3 : 4; }
+struct OutRanges {
+    unsigned lo[kRatioClasses], hi[kRatioClasses];
+};
+
 // Low-res patch under one output block (32 x 256 pixels) at s >= 2: rows
 // span at most ceil(31/s) + 2 <= 18 and columns ceil(255/s) + 2 <= 130.
 constexpr int kPatchRows = 18, kPatchCols = 130, kPatchStride = kPatchCols + 1;
@@ -46,7 +56,7 @@ hipError_t batched_allow_lds(gf_dtype dt, int th, size_t lds);
 // box tiles [p1, p2), output blocks [p2, total)).  With set_lds the kernels'
 // dynamic-LDS limits are raised first (else phases_allow_lds must have run).
 hipError_t launch_phases(gf_dtype dt, int th, const BDesc *D, int n, unsigned *ctl, unsigned p1, unsigned p2,
-                         unsigned total, size_t lds_coeff, size_t lds_box, bool set_lds, hipStream_t st);
+                         const OutRanges &out, size_t lds_coeff, size_t lds_box, bool set_lds, hipStream_t st);
 hipError_t phases_allow_lds(gf_dtype dt, int th, size_t lds_coeff, size_t lds_box);
 int batched_occupancy(gf_dtype dt, int th, size_t lds);
 

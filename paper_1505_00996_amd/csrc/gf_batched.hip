@@ -3,8 +3,9 @@
 // one descriptor table:
 //
 //   phases : one ordinary grid per phase (coefficients, box means, output)
-//            over the concatenated tiles of every image -- three launches per
-//            batch whatever its size; each kernel runs at its own occupancy.
+//            over the concatenated tiles of every image -- a fixed handful of
+//            launches per batch whatever its size (the output phase is one
+//            grid per ratio class); each kernel runs at its own occupancy.
 //   queue  : ONE persistent kernel over a queue of tiles, described below.
 //
 // Queue schedule.
@@ -86,7 +87,8 @@ __device__ __forceinline__ void run_output(const BDesc &d, unsigned local, float
     const int yb = y0 + wave_id() * kOutRows, x0 = xw + lane * kOutPx;
     const int nrows = max(0, min(kOutRows, g.H - yb));
     const bool act = x0 < g.W && nrows > 0;
-    const bool full = d.vec != 0 && x0 + 3 < g.W;
+    const bool in4 = x0 + 3 < g.W;
+    const bool full = d.vec != 0 && in4;
     const T *I = (const T *)d.I;
     T *Q = (T *)d.Q + (int64_t)c0 * d.Qps;
 
@@ -96,9 +98,12 @@ __device__ __forceinline__ void run_output(const BDesc &d, unsigned local, float
     for (int i = 0; i < kOutRows; ++i) {
         iv[i] = raw4{0, 0, 0, 0};
         if (act && i < nrows) {
-            const T *row = I + (int64_t)(yb + i) * d.Irs + x0;
+            const T *base = I + (int64_t)(yb + i) * d.Irs, *row = base + x0;
             if (full) {
                 iv[i] = ldraw4(row);
+            } else if (in4 && pair_aligned(base)) {
+                const auto lo = ldraw2(row), hi = ldraw2(row + 2);
+                iv[i] = raw4{lo.x, lo.y, hi.x, hi.y};
             } else {
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
@@ -107,9 +112,12 @@ __device__ __forceinline__ void run_output(const BDesc &d, unsigned local, float
         }
     }
     auto store_q = [&](T *plane, int y, f32x4 v) {
-        T *row = plane + (int64_t)y * d.Qrs + x0;
+        T *base = plane + (int64_t)y * d.Qrs, *row = base + x0;
         if (full) {
             st4(row, v);
+        } else if (in4 && pair_aligned(base)) {
+            st2(row, v[0], v[1]);
+            st2(row + 2, v[2], v[3]);
         } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
@@ -264,20 +272,12 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BDesc *__restrict__ 
 // takes a contiguous run of tasks (whole images, mostly) and their halos
 // share its L2.  The kernel boundary orders the phases: plain loads/stores.
 
-// Output block of one image with the per-image kernel's code path for its
-// ratio (compile-time taps for s in {1, 2, 4, 8}).
-template <typename T, int CC>
+// Output block of one image with the per-image kernel's code path (S: the
+// compile-time ratio, 0 = read at run time).
+template <typename T, int CC, int S>
 __device__ __forceinline__ void out_cc(const BDesc &d, int c0, int yb, int xw) {
-    const T *I = (const T *)d.I;
-    T *Q = (T *)d.Q + (int64_t)c0 * d.Qps;
-    const bool vec = d.vec != 0;
-    switch (d.g.s) {
-        case 1: output_rows<T, CC, 1>(I, d.Irs, Q, d.Qrs, d.Qps, d.mean, d.g, c0, yb, xw, vec); break;
-        case 2: output_rows<T, CC, 2>(I, d.Irs, Q, d.Qrs, d.Qps, d.mean, d.g, c0, yb, xw, vec); break;
-        case 4: output_rows<T, CC, 4>(I, d.Irs, Q, d.Qrs, d.Qps, d.mean, d.g, c0, yb, xw, vec); break;
-        case 8: output_rows<T, CC, 8>(I, d.Irs, Q, d.Qrs, d.Qps, d.mean, d.g, c0, yb, xw, vec); break;
-        default: output_rows<T, CC, 0>(I, d.Irs, Q, d.Qrs, d.Qps, d.mean, d.g, c0, yb, xw, vec); break;
-    }
+    output_rows<T, CC, S>((const T *)d.I, d.Irs, (T *)d.Q + (int64_t)c0 * d.Qps, d.Qrs, d.Qps, d.mean, d.g, c0,
+                          yb, xw, d.vec != 0);
 }
 
 template <typename T, int TH>
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_pbox(const BDesc *__restrict__ D, 
     run_box<TH, false>(D[i], start + t - D[i].base[1], lds_d);
 }
 
-template <typename T>
+template <typename T, int S>
 __global__ __launch_bounds__(kThreads) void k_pout(const BDesc *__restrict__ D, int n, unsigned start,
                                                    unsigned count) {
     const unsigned t = (unsigned)xcd_tile((int)blockIdx.x);
@@ -311,9 +311,9 @@ __global__ __launch_bounds__(kThreads) void k_pout(const BDesc *__restrict__ D, 
     const int grp = (int)(local / per), r = (int)(local % per);
     const int c0 = 3 * grp, cc = min(3, d.g.C - c0);
     const int yb = (r / d.ntx_o) * (4 * kOutRows) + wave_id() * kOutRows, xw = (r % d.ntx_o) * kOutTileW;
-    if (cc == 3) out_cc<T, 3>(d, c0, yb, xw);
-    else if (cc == 2) out_cc<T, 2>(d, c0, yb, xw);
-    else out_cc<T, 1>(d, c0, yb, xw);
+    if (cc == 3) out_cc<T, 3, S>(d, c0, yb, xw);
+    else if (cc == 2) out_cc<T, 2, S>(d, c0, yb, xw);
+    else out_cc<T, 1, S>(d, c0, yb, xw);
 }
 
 unsigned grid8u(unsigned n) { return (n + 7u) / 8u * 8u; }
@@ -325,7 +325,7 @@ hipError_t allow(Kn k, size_t lds) {
 }
 
 template <typename T, int TH>
-hipError_t phases_t(const BDesc *D, int n, unsigned p1, unsigned p2, unsigned total, size_t lds_coeff,
+hipError_t phases_t(const BDesc *D, int n, unsigned p1, unsigned p2, const OutRanges &out, size_t lds_coeff,
                     size_t lds_box, bool set_lds, hipStream_t st) {
     if (set_lds) {
         (void)allow(k_pcoeff<T, TH>, lds_coeff);
@@ -334,7 +334,18 @@ hipError_t phases_t(const BDesc *D, int n, unsigned p1, unsigned p2, unsigned to
     const dim3 block(kThreads);
     if (p1) hipLaunchKernelGGL((k_pcoeff<T, TH>), dim3(grid8u(p1)), block, lds_coeff, st, D, n, p1);
     if (p2 > p1) hipLaunchKernelGGL((k_pbox<TH>), dim3(grid8u(p2 - p1)), block, lds_box, st, D, n, p1, p2 - p1);
-    if (total > p2) hipLaunchKernelGGL((k_pout<T>), dim3(grid8u(total - p2)), block, 0, st, D, n, p2, total - p2);
+    for (int k = 0; k < kRatioClasses; ++k) {
+        const unsigned lo = out.lo[k], cnt = out.hi[k] - out.lo[k];
+        if (!cnt) continue;
+        const dim3 grid(grid8u(cnt));
+        switch (k) {
+            case 0: hipLaunchKernelGGL((k_pout<T, 1>), grid, block, 0, st, D, n, lo, cnt); break;
+            case 1: hipLaunchKernelGGL((k_pout<T, 2>), grid, block, 0, st, D, n, lo, cnt); break;
+            case 2: hipLaunchKernelGGL((k_pout<T, 4>), grid, block, 0, st, D, n, lo, cnt); break;
+            case 3: hipLaunchKernelGGL((k_pout<T, 8>), grid, block, 0, st, D, n, lo, cnt); break;
+            default: hipLaunchKernelGGL((k_pout<T, 0>), grid, block, 0, st, D, n, lo, cnt); break;
+        }
+    }
     return hipGetLastError();
 }
 
@@ -408,16 +419,16 @@ hipError_t batched_allow_lds(gf_dtype dt, int th, size_t lds) {
 }
 
 hipError_t launch_phases(gf_dtype dt, int th, const BDesc *D, int n, unsigned *ctl, unsigned p1, unsigned p2,
-                         unsigned total, size_t lds_coeff, size_t lds_box, bool set_lds, hipStream_t st) {
+                         const OutRanges &out, size_t lds_coeff, size_t lds_box, bool set_lds, hipStream_t st) {
     // the error word reads 0 after a phase-schedule launch as well
     const int nctl = batch_ctl_words(n);
     hipLaunchKernelGGL(k_zero, dim3((nctl + 255) / 256), dim3(256), 0, st, ctl, nctl);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
 #define GF_P(TT)                                                                                    \
-    return th == 8 ? phases_t<TT, 8>(D, n, p1, p2, total, lds_coeff, lds_box, set_lds, st)          \
-         : th == 16 ? phases_t<TT, 16>(D, n, p1, p2, total, lds_coeff, lds_box, set_lds, st)        \
-                    : phases_t<TT, 24>(D, n, p1, p2, total, lds_coeff, lds_box, set_lds, st)
+    return th == 8 ? phases_t<TT, 8>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st)            \
+         : th == 16 ? phases_t<TT, 16>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st)          \
+                    : phases_t<TT, 24>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st)
     switch (dt) {
         case GF_F32: GF_P(float);
         case GF_F16: GF_P(_Float16);

@@ -46,6 +46,9 @@ namespace dev {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 struct bf16 {
     unsigned short bits;
@@ -107,6 +110,31 @@ __device__ __forceinline__ void st4(bf16 *p, f32x4 v) {
 }
 template <typename T> __device__ __forceinline__ void st1(T *p, float v) { *p = from_f32<T>(v); }
 
+// Two consecutive elements, aligned to twice the element size (rows whose
+// start is not aligned for four-wide accesses, when it is for two-wide ones).
+__device__ __forceinline__ f32x2 ld2(const float *p) { return *(const f32x2 *)p; }
+__device__ __forceinline__ f32x2 ld2(const _Float16 *p) {
+    f16x2 h = *(const f16x2 *)p;
+    return f32x2{(float)h.x, (float)h.y};
+}
+__device__ __forceinline__ f32x2 ld2(const bf16 *p) {
+    u16x2 b = *(const u16x2 *)p;
+    return f32x2{__uint_as_float((unsigned)b.x << 16), __uint_as_float((unsigned)b.y << 16)};
+}
+__device__ __forceinline__ void st2(float *p, float a, float b) {
+    __builtin_nontemporal_store(f32x2{a, b}, (f32x2 *)p);
+}
+__device__ __forceinline__ void st2(_Float16 *p, float a, float b) {
+    __builtin_nontemporal_store(f16x2{from_f32<_Float16>(a), from_f32<_Float16>(b)}, (f16x2 *)p);
+}
+__device__ __forceinline__ void st2(bf16 *p, float a, float b) {
+    __builtin_nontemporal_store(u16x2{f32_to_bf16_bits(a), f32_to_bf16_bits(b)}, (u16x2 *)p);
+}
+// a row start that allows two-wide accesses
+template <typename T> __device__ __forceinline__ bool pair_aligned(const T *row) {
+    return ((uintptr_t)row & (2 * sizeof(T) - 1)) == 0;
+}
+
 // Four samples held in their storage width (half the registers for 16-bit
 // types) and widened when used; widening is exact.
 template <typename T> struct Raw4;
@@ -116,6 +144,9 @@ template <> struct Raw4<bf16> { typedef u16x4 type; };
 __device__ __forceinline__ f32x4 ldraw4(const float *p) { return *(const f32x4 *)p; }
 __device__ __forceinline__ f16x4 ldraw4(const _Float16 *p) { return *(const f16x4 *)p; }
 __device__ __forceinline__ u16x4 ldraw4(const bf16 *p) { return *(const u16x4 *)p; }
+__device__ __forceinline__ f32x2 ldraw2(const float *p) { return *(const f32x2 *)p; }
+__device__ __forceinline__ f16x2 ldraw2(const _Float16 *p) { return *(const f16x2 *)p; }
+__device__ __forceinline__ u16x2 ldraw2(const bf16 *p) { return *(const u16x2 *)p; }
 __device__ __forceinline__ float raw1(const float *p) { return *p; }
 __device__ __forceinline__ _Float16 raw1(const _Float16 *p) { return *p; }
 __device__ __forceinline__ unsigned short raw1(const bf16 *p) { return p->bits; }
@@ -523,16 +554,23 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
     const int x0 = xw + lane * kOutPx;
     const int nrows = min(ROWS, g.H - yb);
     if (x0 >= g.W || nrows <= 0) return;  // no barriers below
-    const bool full = vec && (x0 + 3 < g.W);
+    // Per row: four-wide accesses when every row allows them (vec), else
+    // two-wide ones on rows whose start is aligned for them (x0 is a
+    // multiple of 4), else one element at a time.
+    const bool in4 = x0 + 3 < g.W;
+    const bool full = vec && in4;
 
     f32x4 iv[ROWS];
 #pragma unroll
     for (int i = 0; i < ROWS; ++i) {
         iv[i] = f32x4{0.f, 0.f, 0.f, 0.f};
         if (i < nrows) {
-            const T *row = I + (int64_t)(yb + i) * Irs + x0;
+            const T *base = I + (int64_t)(yb + i) * Irs, *row = base + x0;
             if (full) {
                 iv[i] = ld4(row);
+            } else if (in4 && pair_aligned(base)) {
+                const f32x2 lo = ld2(row), hi = ld2(row + 2);
+                iv[i] = f32x4{lo.x, lo.y, hi.x, hi.y};
             } else {
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
@@ -541,9 +579,12 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
         }
     }
     auto store_q = [&](T *plane, int y, f32x4 v) {
-        T *row = plane + (int64_t)y * Qrs + x0;
+        T *base = plane + (int64_t)y * Qrs, *row = base + x0;
         if (full) {
             st4(row, v);
+        } else if (in4 && pair_aligned(base)) {
+            st2(row, v[0], v[1]);
+            st2(row + 2, v[2], v[3]);
         } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
