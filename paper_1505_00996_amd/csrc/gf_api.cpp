@@ -182,16 +182,19 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
     const View vQ{q->data, q->row_stride, q->plane_stride};
     hipError_t e;
     {
-        ProfScope ps(ctx, GF_K_COEFF, st);
-        e = launch_coeff(I->dtype, vI, vP, coef, g, t, st);
+        ProfScope ps(ctx, GF_K_COEFF, st, true);
+        e = launch_coeff(I->dtype, vI, vP, coef, g, t, st, ps.stamp());
+        ps.commit(e == hipSuccess);
     }
     if (e == hipSuccess) {
-        ProfScope ps(ctx, GF_K_BOX, st);
-        e = launch_box(coef, mean, g, t, st);
+        ProfScope ps(ctx, GF_K_BOX, st, true);
+        e = launch_box(coef, mean, g, t, st, ps.stamp());
+        ps.commit(e == hipSuccess);
     }
     if (e == hipSuccess) {
-        ProfScope ps(ctx, GF_K_OUTPUT, st);
-        e = launch_output(I->dtype, vI, vQ, mean, g, t, vector_ok(I, q), st);
+        ProfScope ps(ctx, GF_K_OUTPUT, st, true);
+        e = launch_output(I->dtype, vI, vQ, mean, g, t, vector_ok(I, q), st, ps.stamp());
+        ps.commit(e == hipSuccess);
     }
     if (e != hipSuccess) return fail(GF_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return GF_OK;

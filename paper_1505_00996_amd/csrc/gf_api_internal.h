@@ -52,14 +52,22 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
                    const gf_params *pr, void *ws, size_t ws_bytes, hipStream_t st,
                    const TileCfg *tiles);
 
-// Event pair around one kernel when the context is profiling (no-op otherwise).
+// Timing of one launcher call when the context is profiling (no-op
+// otherwise).  By default events are recorded on the stream before and after
+// the scope; with `in_dispatch` the scope only hands out a Stamp whose events
+// the launcher puts into the kernel dispatches, and the caller reports
+// whether the launch went through (commit) so only recorded events are read.
 struct ProfScope {
     gf_ctx *ctx;
     int kernel;
     hipStream_t st;
-    hipEvent_t start = nullptr;
-    ProfScope(gf_ctx *c, int k, hipStream_t s);
+    bool in_dispatch;
+    bool committed = false;
+    hipEvent_t start = nullptr, end = nullptr;
+    ProfScope(gf_ctx *c, int k, hipStream_t s, bool in_dispatch = false);
     ~ProfScope();
+    Stamp stamp() const { return Stamp{start, end}; }
+    void commit(bool ok) { committed = ok; }
 };
 gf_status ctx_use_device(gf_ctx *ctx);
 gf_status ctx_workspace(gf_ctx *ctx, size_t need, void **ws);

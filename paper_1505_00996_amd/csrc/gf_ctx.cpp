@@ -46,11 +46,19 @@ static hipEvent_t take_event(gf_ctx *ctx) {
     return e;
 }
 
-ProfScope::ProfScope(gf_ctx *c, int k, hipStream_t s) : ctx(c), kernel(k), st(s) {
+ProfScope::ProfScope(gf_ctx *c, int k, hipStream_t s, bool in_disp)
+    : ctx(c), kernel(k), st(s), in_dispatch(in_disp) {
     if (!ctx || !ctx->profiling) return;
     std::lock_guard<std::mutex> lk(ctx->prof_mu);
     start = take_event(ctx);
-    if (start && hipEventRecord(start, st) != hipSuccess) {
+    if (!start) return;
+    if (in_dispatch) {
+        end = take_event(ctx);
+        if (!end) {
+            ctx->event_pool.push_back(start);
+            start = nullptr;
+        }
+    } else if (hipEventRecord(start, st) != hipSuccess) {
         ctx->event_pool.push_back(start);
         start = nullptr;
     }
@@ -59,7 +67,16 @@ ProfScope::ProfScope(gf_ctx *c, int k, hipStream_t s) : ctx(c), kernel(k), st(s)
 ProfScope::~ProfScope() {
     if (!start) return;
     std::lock_guard<std::mutex> lk(ctx->prof_mu);
-    hipEvent_t end = take_event(ctx);
+    if (in_dispatch) {
+        if (committed) {
+            ctx->marks.push_back({kernel, start, end});
+        } else {
+            ctx->event_pool.push_back(start);
+            ctx->event_pool.push_back(end);
+        }
+        return;
+    }
+    end = take_event(ctx);
     if (end && hipEventRecord(end, st) == hipSuccess) {
         ctx->marks.push_back({kernel, start, end});
     } else {

@@ -288,6 +288,37 @@ __device__ __forceinline__ void fill_tile(float *dst, int SH, int SW, int SWp, F
     }
 }
 
+// A region of at most 4*kFillRows rows and 128 columns is one fill batch; its
+// loads can be issued early into registers (fill_load) and written to LDS
+// later (fill_store), so their latency overlaps other work.  Same data and
+// placement as fill_tile.
+struct FillRegs {
+    float v0[kFillRows], v1[kFillRows];
+};
+__host__ __device__ constexpr bool one_fill_batch(int SH, int SW) { return SH <= 4 * kFillRows && SW <= 128; }
+template <class F>
+__device__ __forceinline__ void fill_load(FillRegs &r, int SH, int SW, F f) {
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int cx0 = min(lane, SW - 1), cx1 = min(64 + lane, SW - 1);
+#pragma unroll
+    for (int b = 0; b < kFillRows; ++b) {
+        const int ry = min(wave + 4 * b, SH - 1);
+        r.v0[b] = f(ry, cx0);
+        r.v1[b] = f(ry, cx1);
+    }
+}
+__device__ __forceinline__ void fill_store(const FillRegs &r, float *dst, int SH, int SW, int SWp) {
+    const int lane = threadIdx.x & 63, wave = wave_id();
+#pragma unroll
+    for (int b = 0; b < kFillRows; ++b) {
+        const int ry = wave + 4 * b;
+        if (ry < SH) {
+            if (lane < SW) dst[ry * SWp + lane] = r.v0[b];
+            if (64 + lane < SW) dst[ry * SWp + 64 + lane] = r.v1[b];
+        }
+    }
+}
+
 // Two regions of the same shape in one batch (twice the loads in flight).
 template <class F1, class F2>
 __device__ __forceinline__ void fill_tile2(float *d1, float *d2, int SH, int SW, int SWp, F1 f1, F2 f2) {
@@ -384,7 +415,10 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
     auto row_pass = [&](auto pair, auto gV) {
         constexpr bool PAIR = decltype(pair)::value;
         for (int it = threadIdx.x; it < SH * (kTileW / kRun); it += kThreads) {
-            const int ry = it >> 3, j0 = (it & 7) * kRun;
+            // consecutive lanes take consecutive rows of the same run: region
+            // reads stride SWp (odd) and row-sum writes 2*kRowW words, which
+            // spread over the LDS banks (lanes on one row would collide)
+            const int j0 = (it / SH) * kRun, ry = it - (it / SH) * SH;
             const float *pu = sU + ry * SWp + j0, *pv = sV + ry * SWp + j0;
             auto U = [&](int k) -> double { return STAGE ? pu[k] : gU(ry, j0 + k); };
             auto V = [&](int k) -> double { return STAGE ? pv[k] : gV(ry, j0 + k); };
@@ -439,13 +473,26 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
         }
     }
 
+    // When a region is one fill batch, the next channel's samples are loaded
+    // while this channel's passes run.
+    const bool ahead = STAGE && one_fill_batch(SH, SW);
+    FillRegs next;
+    float cPn = 0.f;
     for (int c = 0; c < g.C; ++c) {
         const T *Pc = P + (int64_t)c * Pps;
-        const float cP = c ? sample<K>(Pc, Prs, ty0, tx0, g) : cP0;
+        const float cP = c ? cPn : cP0;
         auto gV = [&](int ry, int rx) { return gsample(Pc, Prs, cP, ry, rx); };
         // sV is free: the last row pass that read it ended at a barrier
-        if (STAGE && c) fill_tile(sV, SH, SW, SWp, gV);
+        if (STAGE && c) {
+            if (ahead) fill_store(next, sV, SH, SW, SWp);
+            else fill_tile(sV, SH, SW, SWp, gV);
+        }
         __syncthreads();  // sV staged; the previous column pass is done with rA, rB
+        if (c + 1 < g.C) {
+            const T *Pn = Pc + Pps;
+            cPn = sample<K>(Pn, Prs, ty0, tx0, g);
+            if (ahead) fill_load(next, SH, SW, [&](int ry, int rx) { return gsample(Pn, Prs, cPn, ry, rx); });
+        }
         // sums of v and u*v, then a and b
         row_pass(std::true_type{}, gV);
         __syncthreads();
@@ -490,7 +537,7 @@ __device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__r
     });
     __syncthreads();
     for (int it = threadIdx.x; it < SH * (kTileW / kRun); it += kThreads) {
-        const int ry = it >> 3, j0 = (it & 7) * kRun;
+        const int j0 = (it / SH) * kRun, ry = it - (it / SH) * SH;  // lanes down the rows (see coeff_tile)
         const float *px = sX + ry * SWp + j0;
         float A = 0.f;
         for (int k = 0; k <= 2 * R; ++k) A += px[k];

@@ -48,12 +48,20 @@ size_t coeff_lds_bytes(const TileCfg &t, int R);
 size_t box_lds_bytes(const TileCfg &t, int R);
 TileCfg default_tiles(const Geo &g);
 
+// Timing events of one launcher call (null: none).  The launcher passes them
+// to the dispatch itself (hipExtLaunchKernel), start with its first kernel
+// and stop with its last, so they time the kernels and nothing between.
+struct Stamp {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // Kernel launchers (gf_kernels.hip).  All return the launch status.
 hipError_t launch_coeff(gf_dtype dt, const View &I, const View &P, float *coef,
-                        const Geo &g, const TileCfg &t, hipStream_t st);
+                        const Geo &g, const TileCfg &t, hipStream_t st, const Stamp &ts = Stamp{});
 hipError_t launch_box(const float *src, float *dst, const Geo &g, const TileCfg &t,
-                      hipStream_t st);
+                      hipStream_t st, const Stamp &ts = Stamp{});
 hipError_t launch_output(gf_dtype dt, const View &I, const View &Q, const float *mean,
-                         const Geo &g, const TileCfg &t, bool vec, hipStream_t st);
+                         const Geo &g, const TileCfg &t, bool vec, hipStream_t st,
+                         const Stamp &ts = Stamp{});
 
 }  // namespace gf

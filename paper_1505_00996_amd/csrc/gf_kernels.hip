@@ -6,6 +6,7 @@
 //   k_output (grid: full-res 256 x 32 blocks)  steps 6-7 -> q
 // Algorithm 1 is the same three launches at s = 1, where subsampling and
 // upsampling are identities.  The per-tile work lives in gf_device.h.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "gf_device.h"
@@ -51,6 +52,14 @@ __global__ __launch_bounds__(kThreads) void k_output(const T *__restrict__ I, in
 
 int grid8(int n) { return ((n + 7) / 8) * 8; }
 
+// A launch that carries timing events in its dispatch when asked to.
+template <typename Kn, typename... A>
+void launch_k(Kn kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+              A... args) {
+    if (e0 || e1) hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, st, e0, e1, 0u, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+}
+
 // Dynamic LDS above 64 KB has to be allowed per kernel (gfx950 has 160 KB).
 template <typename Kn>
 void allow_lds(Kn kernel, size_t bytes) {
@@ -61,7 +70,7 @@ void allow_lds(Kn kernel, size_t bytes) {
 
 template <typename T, int K>
 hipError_t coeff_tk(const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
-                    hipStream_t st) {
+                    hipStream_t st, const Stamp &ts) {
     const T *Ip = (const T *)I.data, *Pp = (const T *)P.data;
     const bool staged = coeff_staged(t, g.R);
     const int th = staged ? t.coeff_th : 8;  // the unstaged kernel works on 8-row tiles
@@ -72,8 +81,8 @@ hipError_t coeff_tk(const View &I, const View &P, float *coef, const Geo &g, con
 #define GF_COEFF(TH, STG)                                                                              \
     {                                                                                                   \
         allow_lds(k_coeff<T, K, TH, STG>, lds);                                                         \
-        hipLaunchKernelGGL((k_coeff<T, K, TH, STG>), grid, block, lds, st, Ip, I.rs, Pp, P.rs, P.ps, coef, \
-                           g, ntx, ntiles);                                                             \
+        launch_k(k_coeff<T, K, TH, STG>, grid, block, lds, st, ts.start, ts.stop, Ip, I.rs, Pp, P.rs, P.ps,  \
+                 coef, g, ntx, ntiles);                                                                 \
     }
     if (!staged) {
         GF_COEFF(8, false)  // large r': only the row sums live in LDS
@@ -91,15 +100,15 @@ hipError_t coeff_tk(const View &I, const View &P, float *coef, const Geo &g, con
 
 template <typename T>
 hipError_t coeff_t(const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
-                   hipStream_t st) {
-    if (g.s == 1) return coeff_tk<T, kSubId>(I, P, coef, g, t, st);
-    if (g.sub == GF_SUB_NEAREST || (g.s & 1)) return coeff_tk<T, kSubNear>(I, P, coef, g, t, st);
-    return coeff_tk<T, kSubLin>(I, P, coef, g, t, st);
+                   hipStream_t st, const Stamp &ts) {
+    if (g.s == 1) return coeff_tk<T, kSubId>(I, P, coef, g, t, st, ts);
+    if (g.sub == GF_SUB_NEAREST || (g.s & 1)) return coeff_tk<T, kSubNear>(I, P, coef, g, t, st, ts);
+    return coeff_tk<T, kSubLin>(I, P, coef, g, t, st, ts);
 }
 
 template <typename T, int CC>
 hipError_t output_cc(const View &I, const View &Q, const float *mean, const Geo &g, int c0, bool vec,
-                     hipStream_t st) {
+                     hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const int ntx = (g.W + kOutTileW - 1) / kOutTileW;
     const int nty = (g.H + 4 * kOutRows - 1) / (4 * kOutRows);
     const int ntiles = ntx * nty;
@@ -107,8 +116,8 @@ hipError_t output_cc(const View &I, const View &Q, const float *mean, const Geo 
     T *Qp = (T *)Q.data + (int64_t)c0 * Q.ps;
     const dim3 grid(grid8(ntiles)), block(kThreads);
 #define GF_OUT(SS)                                                                                  \
-    hipLaunchKernelGGL((k_output<T, CC, SS>), grid, block, 0, st, Ip, I.rs, Qp, Q.rs, Q.ps, mean, g, \
-                       c0, ntx, ntiles, (int)vec)
+    launch_k(k_output<T, CC, SS>, grid, block, 0, st, e0, e1, Ip, I.rs, Qp, Q.rs, Q.ps, mean, g, c0, ntx, \
+             ntiles, (int)vec)
     switch (g.s) {
         case 1: GF_OUT(1); break;
         case 2: GF_OUT(2); break;
@@ -122,12 +131,13 @@ hipError_t output_cc(const View &I, const View &Q, const float *mean, const Geo 
 
 template <typename T>
 hipError_t output_t(const View &I, const View &Q, const float *mean, const Geo &g, bool vec,
-                    hipStream_t st) {
+                    hipStream_t st, const Stamp &ts) {
     for (int c0 = 0; c0 < g.C; c0 += 3) {
         const int cc = g.C - c0 < 3 ? g.C - c0 : 3;
-        hipError_t e = cc == 3 ? output_cc<T, 3>(I, Q, mean, g, c0, vec, st)
-                     : cc == 2 ? output_cc<T, 2>(I, Q, mean, g, c0, vec, st)
-                               : output_cc<T, 1>(I, Q, mean, g, c0, vec, st);
+        const hipEvent_t e0 = c0 == 0 ? ts.start : nullptr, e1 = c0 + 3 >= g.C ? ts.stop : nullptr;
+        hipError_t e = cc == 3 ? output_cc<T, 3>(I, Q, mean, g, c0, vec, st, e0, e1)
+                     : cc == 2 ? output_cc<T, 2>(I, Q, mean, g, c0, vec, st, e0, e1)
+                               : output_cc<T, 1>(I, Q, mean, g, c0, vec, st, e0, e1);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -143,16 +153,17 @@ size_t coeff_lds_bytes(const TileCfg &t, int R) {
 size_t box_lds_bytes(const TileCfg &t, int R) { return dev::box_tile_lds(t.box_th, R); }
 
 hipError_t launch_coeff(gf_dtype dt, const View &I, const View &P, float *coef, const Geo &g,
-                        const TileCfg &t, hipStream_t st) {
+                        const TileCfg &t, hipStream_t st, const Stamp &ts) {
     switch (dt) {
-        case GF_F32: return coeff_t<float>(I, P, coef, g, t, st);
-        case GF_F16: return coeff_t<_Float16>(I, P, coef, g, t, st);
-        case GF_BF16: return coeff_t<dev::bf16>(I, P, coef, g, t, st);
+        case GF_F32: return coeff_t<float>(I, P, coef, g, t, st, ts);
+        case GF_F16: return coeff_t<_Float16>(I, P, coef, g, t, st, ts);
+        case GF_BF16: return coeff_t<dev::bf16>(I, P, coef, g, t, st, ts);
     }
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_box(const float *src, float *dst, const Geo &g, const TileCfg &t, hipStream_t st) {
+hipError_t launch_box(const float *src, float *dst, const Geo &g, const TileCfg &t, hipStream_t st,
+                      const Stamp &ts) {
     const int ntx = (g.Wl + kTileW - 1) / kTileW, nty = (g.Hl + t.box_th - 1) / t.box_th;
     const int ntiles = ntx * nty;
     const size_t lds = box_lds_bytes(t, g.R);
@@ -160,7 +171,7 @@ hipError_t launch_box(const float *src, float *dst, const Geo &g, const TileCfg 
 #define GF_BOX(TH)                                                                            \
     {                                                                                         \
         allow_lds(k_box<TH>, lds);                                                            \
-        hipLaunchKernelGGL((k_box<TH>), grid, block, lds, st, src, dst, g, ntx, ntiles);      \
+        launch_k(k_box<TH>, grid, block, lds, st, ts.start, ts.stop, src, dst, g, ntx, ntiles);  \
     }
     switch (t.box_th) {
         case 8: GF_BOX(8) break;
@@ -173,11 +184,11 @@ hipError_t launch_box(const float *src, float *dst, const Geo &g, const TileCfg 
 }
 
 hipError_t launch_output(gf_dtype dt, const View &I, const View &Q, const float *mean, const Geo &g,
-                         const TileCfg &, bool vec, hipStream_t st) {
+                         const TileCfg &, bool vec, hipStream_t st, const Stamp &ts) {
     switch (dt) {
-        case GF_F32: return output_t<float>(I, Q, mean, g, vec, st);
-        case GF_F16: return output_t<_Float16>(I, Q, mean, g, vec, st);
-        case GF_BF16: return output_t<dev::bf16>(I, Q, mean, g, vec, st);
+        case GF_F32: return output_t<float>(I, Q, mean, g, vec, st, ts);
+        case GF_F16: return output_t<_Float16>(I, Q, mean, g, vec, st, ts);
+        case GF_BF16: return output_t<dev::bf16>(I, Q, mean, g, vec, st, ts);
     }
     return hipErrorInvalidValue;
 }
