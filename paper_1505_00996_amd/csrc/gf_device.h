@@ -410,6 +410,9 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
     const int lx = tx0 + col;
     const int nx = clip_len(lx, R, g.Wl);
 
+    // (Window loops have a run-time length 2r'+1; unrolling them keeps several
+    // LDS reads in flight instead of one read-wait-add per element.  The
+    // additions stay in the same order.)
     // Row pass: rA = sum x, rB = sum u*x over each run of kRun outputs, with
     // x = u (PAIR false) or x = v (PAIR true, v from gV / sV).
     auto row_pass = [&](auto pair, auto gV) {
@@ -420,26 +423,41 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
             // spread over the LDS banks (lanes on one row would collide)
             const int j0 = (it / SH) * kRun, ry = it - (it / SH) * SH;
             const float *pu = sU + ry * SWp + j0, *pv = sV + ry * SWp + j0;
-            auto U = [&](int k) -> double { return STAGE ? pu[k] : gU(ry, j0 + k); };
-            auto V = [&](int k) -> double { return STAGE ? pv[k] : gV(ry, j0 + k); };
+            auto U = [&](int k) -> float { return STAGE ? pu[k] : gU(ry, j0 + k); };
+            auto V = [&](int k) -> float { return STAGE ? pv[k] : gV(ry, j0 + k); };
+            // every read of the run before any write (see box_tile)
+            float uin[kRun], uout[kRun], xin[kRun], xout[kRun];
+#pragma unroll
+            for (int t = 1; t < kRun; ++t) {
+                uin[t] = U(t + 2 * R);
+                uout[t] = U(t - 1);
+                xin[t] = PAIR ? V(t + 2 * R) : uin[t];
+                xout[t] = PAIR ? V(t - 1) : uout[t];
+            }
             double A = 0.0, B = 0.0;
+#pragma unroll 8
             for (int k = 0; k <= 2 * R; ++k) {
                 const double u = U(k);
-                const double x = PAIR ? V(k) : u;
+                const double x = PAIR ? (double)V(k) : u;
                 A += x;
                 B = __builtin_fma(u, x, B);
             }
-            double *oa = rA + ry * kRowW + j0, *ob = rB + ry * kRowW + j0;
-            oa[0] = A;
-            ob[0] = B;
+            double ra[kRun], rb[kRun];
+            ra[0] = A;
+            rb[0] = B;
 #pragma unroll
             for (int t = 1; t < kRun; ++t) {
-                const double ui = U(t + 2 * R), uo = U(t - 1);
-                const double xi = PAIR ? V(t + 2 * R) : ui, xo = PAIR ? V(t - 1) : uo;
+                const double ui = uin[t], uo = uout[t], xi = xin[t], xo = xout[t];
                 A += xi - xo;
                 B += __builtin_fma(ui, xi, -uo * xo);
-                oa[t] = A;
-                ob[t] = B;
+                ra[t] = A;
+                rb[t] = B;
+            }
+            double *oa = rA + ry * kRowW + j0, *ob = rB + ry * kRowW + j0;
+#pragma unroll
+            for (int t = 0; t < kRun; ++t) {
+                oa[t] = ra[t];
+                ob[t] = rb[t];
             }
         }
     };
@@ -458,6 +476,7 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
     __syncthreads();
     {
         double A = 0.0, B = 0.0;
+#pragma unroll 8
         for (int k = 0; k <= 2 * R; ++k) {
             A += rA[(r0 + k) * kRowW + col];
             B += rB[(r0 + k) * kRowW + col];
@@ -498,6 +517,7 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
         __syncthreads();
         float *ac = coef + (int64_t)c * g.lps, *bc = coef + (int64_t)(g.C + c) * g.lps;
         double A = 0.0, B = 0.0;
+#pragma unroll 8
         for (int k = 0; k <= 2 * R; ++k) {
             A += rA[(r0 + k) * kRowW + col];
             B += rB[(r0 + k) * kRowW + col];
@@ -539,21 +559,33 @@ __device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__r
     for (int it = threadIdx.x; it < SH * (kTileW / kRun); it += kThreads) {
         const int j0 = (it / SH) * kRun, ry = it - (it / SH) * SH;  // lanes down the rows (see coeff_tile)
         const float *px = sX + ry * SWp + j0;
-        float A = 0.f;
-        for (int k = 0; k <= 2 * R; ++k) A += px[k];
-        float *oa = rA + ry * kRowW + j0;
-        oa[0] = A;
+        // every read of the run before any write: the row sums share LDS
+        // with the region, so a write between reads would order them
+        float xin[kRun], xout[kRun], res[kRun];
 #pragma unroll
         for (int t = 1; t < kRun; ++t) {
-            A += px[t + 2 * R] - px[t - 1];
-            oa[t] = A;
+            xin[t] = px[t + 2 * R];
+            xout[t] = px[t - 1];
         }
+        float A = 0.f;
+#pragma unroll 8
+        for (int k = 0; k <= 2 * R; ++k) A += px[k];
+        res[0] = A;
+#pragma unroll
+        for (int t = 1; t < kRun; ++t) {
+            A += xin[t] - xout[t];
+            res[t] = A;
+        }
+        float *oa = rA + ry * kRowW + j0;
+#pragma unroll
+        for (int t = 0; t < kRun; ++t) oa[t] = res[t];
     }
     __syncthreads();
     const int col = lane, r0 = wave * LC;
     const int lx = tx0 + col;
     const int nx = clip_len(lx, R, g.Wl);
     float A = 0.f;
+#pragma unroll 8
     for (int k = 0; k <= 2 * R; ++k) A += rA[(r0 + k) * kRowW + col];
 #pragma unroll
     for (int t = 0; t < LC; ++t) {
