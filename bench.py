@@ -139,6 +139,63 @@ def measure_batched(gfp, torch, dev, n=256, reps=5, seed=6, tune=True):
                         "C in {1,3}, r = round(0.01 max(H,W)), eps=1e-3, one batched launch"}
 
 
+def measure_16bit(gfp, torch, dev, steps=50, with_oracle=True):
+    """16-bit storage (fp16 and bf16): the 6000x4000 workload with near-flat
+    guide blocks, RGB input, r = 32, s = 8 (r' = 4), eps = 1e-4, two rotated
+    input sets.  gf_fast per step; per-kernel HIP events; the output kernel's
+    roofline; max |q - oracle| on the stored inputs."""
+    import numpy as np
+    import synth
+    h, w, c, r, s, eps = 4000, 6000, 3, 32, 8, 1e-4
+    I_np, p_np = synth.workload_24mp(h, w, c)
+    out = {"workload": "6000x4000 guide with near-flat 500x500 blocks + RGB input, r=32, s=8 (r'=4), "
+                       "eps=1e-4, nearest; gf_fast per step", "h": h, "w": w, "channels": c}
+    for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+        sets = []
+        for k in range(2):
+            dI = torch.from_numpy(I_np).to(dev).to(dt)
+            dp = torch.from_numpy(p_np).to(dev).to(dt)
+            sets.append((dI, dp, torch.empty_like(dp)))
+        ctx = gfp.Context(0)
+        ws = torch.empty(gfp.workspace_bytes(h, w, c, r, s, eps), dtype=torch.uint8, device=dev)
+
+        def step(i):
+            dI, dp, q = sets[i % len(sets)]
+            gfp.gf_fast(dI, dp, r, s, eps, q=q, ctx=ctx, workspace=ws)
+        for i in range(5):
+            step(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(i)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ctx.profile(True)
+        ctx.profile_read()
+        for i in range(steps):
+            step(i)
+        kt = ctx.profile_read()
+        ctx.profile(False)
+        out_ms = kt["output"][0] / max(kt["output"][1], 1)
+        ob = output_kernel_bytes(h, w, c, s, elem=2)
+        res = {"value": round(h * w / 1e6 / (ms * 1e-3), 1), "unit": "MPix/s", "ms_per_step": round(ms, 5),
+               "kernels": {k: round(v[0] / v[1], 5) for k, v in kt.items() if v[1]},
+               "output_roofline": {"achieved_GBs": round(ob / (out_ms * 1e-3) / 1e9, 1),
+                                   "frac": round(ob / (out_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                   "algorithmic_bytes_per_launch": ob}}
+        if with_oracle:
+            from oracle import oracle
+            dI, dp, q = sets[0]
+            step(0)
+            torch.cuda.synchronize()
+            exp = oracle.fast_guided_filter(dI.double().cpu().numpy(), dp.double().cpu().numpy(), r, s, eps)
+            res["max_abs_err"] = float(np.max(np.abs(q.double().cpu().numpy() - exp)))
+        out[name] = res
+        ctx.close()
+        del sets
+    return out
+
+
 def measure_served(gfp, torch, dev, pool=96, seed=7, seconds=2.5):
     """Requests through gf_submit / gf_poll: log-uniform 0.25-24 MP, aspect
     1:1/4:3/3:2/16:9 either way, gray or RGB input 50/50, s = 4,
@@ -348,8 +405,19 @@ def main():
     }
     del big, big2, out3
 
-    batched = served = None
+    # plain filter kernels (HIP events in the dispatch)
+    ctx.profile(True)
+    ctx.profile_read()
+    for i in range(plain_steps):
+        step_plain(i)
+    kt_plain = ctx.profile_read()
+    ctx.profile(False)
+
+    batched = served = sixteen = None
     if not args.no_extra:
+        sixteen = measure_16bit(gfp, torch, dev, with_oracle=not args.no_cpu)
+        print(f"# 16-bit: f16 {sixteen['f16']['value']} bf16 {sixteen['bf16']['value']} MPix/s",
+              file=sys.stderr, flush=True)
         batched = measure_batched(gfp, torch, dev)
         print(f"# batched: {batched['ms_per_batch']} ms per batch", file=sys.stderr, flush=True)
         served = measure_served(gfp, torch, dev)
@@ -382,7 +450,9 @@ def main():
                    "h": H, "w": W, "channels": C, "r": R_FULL, "s": S, "eps": EPS,
                    "input_sets_rotated": len(sets)},
         "plain": {"value": round(mpix / (ms_plain * 1e-3), 1), "unit": "MPix/s",
-                  "ms_per_step": round(ms_plain, 5), "steps": plain_steps},
+                  "ms_per_step": round(ms_plain, 5), "steps": plain_steps,
+                  "kernels": {k: round(v[0] / v[1], 5) for k, v in kt_plain.items() if v[1]}},
+        "storage_16bit": sixteen,
         "speedup_vs_plain": round(ms_plain / ms_fast, 3),
         "step_events": step_events,
         "ms_per_step_with_kernel_events": round(ms_fast_ev, 5),

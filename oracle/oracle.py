@@ -66,6 +66,8 @@ class Oracle:
             "oracle_coefficients": [_DP, _DP, i, i, i, d, _DP, _DP],
             "oracle_guided_filter": [_DP, _DP, i, i, i, i, d, _DP, _DP, _DP, _DP, _DP],
             "oracle_fast_guided_filter": [_DP, _DP, i, i, i, i, i, d, i, _DP, _DP, _DP, _DP, _DP],
+            "oracle_joint_upsample": [_DP, _DP, i, i, i, i, i, d, i, _DP],
+            "oracle_detail_enhance": [_DP, _DP, ctypes.c_size_t, d, _DP],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -164,6 +166,32 @@ class Oracle:
         return (q, ex) if intermediates else q
 
 
+    def joint_upsample(self, I, p_lo, r: int, s: int, eps: float, mode="nearest"):
+        """Joint upsampling: ``p_lo`` (c, ceil(h/s), ceil(w/s)) or 2-D, guided
+        by the full-resolution ``I`` (h, w).  Returns q at full resolution."""
+        I = _f64(I)
+        h, w = I.shape
+        hl, wl = self.lowres_size(h, s), self.lowres_size(w, s)
+        p_lo = _f64(p_lo)
+        squeeze = p_lo.ndim == 2
+        p3 = np.ascontiguousarray(p_lo.reshape(1, hl, wl)) if squeeze else p_lo
+        assert p3.shape[1:] == (hl, wl), (p3.shape, hl, wl)
+        c = p3.shape[0]
+        q = np.empty((c, h, w))
+        _check(self.lib.oracle_joint_upsample(_ptr(I), _ptr(p3), c, h, w, int(r), int(s), float(eps),
+                                              _MODES[mode], _ptr(q)), "oracle_joint_upsample")
+        return q[0] if squeeze else q
+
+    def detail_enhance(self, p, q, gain: float):
+        """e = q + gain (p - q), elementwise (p and q of one shape)."""
+        p, q = _f64(p), _f64(q)
+        assert p.shape == q.shape
+        e = np.empty_like(q)
+        _check(self.lib.oracle_detail_enhance(_ptr(p), _ptr(q), ctypes.c_size_t(q.size), float(gain), _ptr(e)),
+               "oracle_detail_enhance")
+        return e
+
+
 _default: Oracle | None = None
 
 
@@ -207,3 +235,11 @@ def guided_filter(I, p, r, eps, intermediates=False):
 
 def fast_guided_filter(I, p, r, s, eps, mode="nearest", intermediates=False):
     return default().fast_guided_filter(I, p, r, s, eps, mode, intermediates)
+
+
+def joint_upsample(I, p_lo, r, s, eps, mode="nearest"):
+    return default().joint_upsample(I, p_lo, r, s, eps, mode)
+
+
+def detail_enhance(p, q, gain):
+    return default().detail_enhance(p, q, gain)

@@ -373,4 +373,63 @@ def pin_degenerate_shapes(orc):
                1e-11, f"degenerate {h}x{w} r={r} s={s}")
 
 
+def composed_joint(I, p_lo, r, s, eps, mode):
+    """Joint upsampling assembled from library primitives: torch subsample of
+    the guide only, scipy box means, numpy elementwise steps, torch upsample."""
+    h, w = I.shape
+    rl = 0 if r == 0 else max(1, int(math.floor(r / s + 0.5)))
+    Il = torch_sub(I, s, mode)
+    mI, mp = scipy_box(Il, rl), scipy_box(p_lo, rl)
+    cI, cIp = scipy_box(Il * Il, rl), scipy_box(Il * p_lo, rl)
+    a = (cIp - mI * mp) / (cI - mI * mI + eps)
+    b = mp - a * mI
+    return torch_upsample(scipy_box(a, rl), s, h, w) * I + torch_upsample(scipy_box(b, rl), s, h, w)
+
+
+def pin_joint_composition(orc):
+    """Joint upsampling equals its assembly from library routines, for a
+    low-res input that is not a subsampled full-res image."""
+    g = _rng(31)
+    for (h, w), r, s, eps, mode in [((37, 45), 8, 4, 1e-2, "nearest"), ((30, 21), 5, 2, 1e-3, "bilinear"),
+                                    ((29, 33), 6, 3, 1e-1, "nearest"), ((8, 50), 12, 8, 1e-2, "bilinear")]:
+        I = g.uniform(0, 1, size=(h, w))
+        p_lo = g.uniform(0, 1, size=(-(-h // s), -(-w // s)))
+        _close(orc.joint_upsample(I, p_lo, r, s, eps, mode), composed_joint(I, p_lo, r, s, eps, mode), 1e-11,
+               f"joint {h}x{w} r={r} s={s} {mode}")
+
+
+def pin_joint_of_subsampled_is_fast(orc):
+    """Given p subsampled by the library routine, joint upsampling is the fast
+    filter of the full-resolution p (every channel)."""
+    g = _rng(32)
+    for (h, w), r, s, mode in [((33, 40), 8, 4, "nearest"), ((26, 31), 4, 2, "bilinear")]:
+        I = g.uniform(0, 1, size=(h, w))
+        p = g.uniform(0, 1, size=(2, h, w))
+        p_lo = np.stack([torch_sub(p[k], s, mode) for k in range(2)])
+        _close(orc.joint_upsample(I, p_lo, r, s, 1e-2, mode), orc.fast_guided_filter(I, p, r, s, 1e-2, mode),
+               1e-13, f"joint of subsampled p {h}x{w} s={s} {mode}")
+
+
+def pin_joint_constant(orc):
+    """A constant low-res input comes back as that constant at full resolution."""
+    g = _rng(33)
+    I = g.uniform(0, 1, size=(21, 34))
+    for mode in ("nearest", "bilinear"):
+        _close(orc.joint_upsample(I, np.full((6, 9), 0.5), 8, 4, 1e-3, mode), np.full((21, 34), 0.5), 0.0,
+               f"joint const {mode}")
+
+
+def pin_detail_gain_endpoints(orc):
+    """Detail enhancement with gain 0 is the filtered image, with gain 1 the
+    input; a constant input is unchanged at any gain."""
+    g = _rng(34)
+    I = g.uniform(0, 1, size=(17, 23))
+    p = np.clip(I + g.normal(0, 0.1, size=(17, 23)), 0, 1)
+    q = orc.fast_guided_filter(I, p, 8, 4, 1e-2)
+    assert np.array_equal(orc.detail_enhance(p, q, 0.0), q)
+    _close(orc.detail_enhance(p, q, 1.0), p, 2e-16, "gain 1")
+    c = np.full_like(p, 0.25)
+    _close(orc.detail_enhance(c, orc.fast_guided_filter(I, c, 8, 4, 1e-2), 5.0), c, 1e-15, "constant input")
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

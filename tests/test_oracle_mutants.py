@@ -38,6 +38,13 @@ MUTANTS = {
                               "(1.0 - wx) * ((1.0 - wy) * v00 + wy * v01) + wx * ((1.0 - wy) * v10 + wy * v11);\n        }\n    }\n    return 0;\n}\n\n/*\n * Algorithm 1"),
     "upsample_wrong_tap": ("int ya = iclamp((int)fu, 0, hl - 1)", "int ya = iclamp((int)fu + 1, 0, hl - 1)"),
     "fast_output_uses_mean_b_twice": ("qk[i] = ua[i] * I[i] + ub[i]", "qk[i] = ub[i] * I[i] + ub[i]"),
+    "joint_uses_full_radius": ("oracle_coefficients(Is, pc, hs, ws, rs, eps, ak, bk)",
+                               "oracle_coefficients(Is, pc, hs, ws, r, eps, ak, bk)"),
+    "joint_output_swapped": ("qc[i] = uak[i] * I[i] + ubk[i]", "qc[i] = ubk[i] * I[i] + uak[i]"),
+    "joint_guide_wrong_mode": ("oracle_subsample(I, h, w, s, mode, Is)", "oracle_subsample(I, h, w, s, 1 - mode, Is)"),
+    "joint_skips_b_mean": ("oracle_box_mean(bk, hs, ws, rs, mbk)", "oracle_box_mean(bk, hs, ws, 0, mbk)"),
+    "detail_sign": ("e[i] = q[i] + gain * (p[i] - q[i])", "e[i] = q[i] + gain * (q[i] - p[i])"),
+    "detail_base_is_input": ("e[i] = q[i] + gain * (p[i] - q[i])", "e[i] = p[i] + gain * (p[i] - q[i])"),
 }
 
 
