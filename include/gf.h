@@ -162,6 +162,34 @@ gf_status gf_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q
  */
 size_t gf_footprint_bytes(int32_t h, int32_t w, int32_t c, gf_dtype dtype, const gf_params *params);
 
+/*
+ * Joint upsampling: the input arrives at low resolution and only the guide is
+ * subsampled (the paper's introduction names joint upsampling as where this
+ * subsampling first appeared).  I: 1 x h x w; p_low: c x ceil(h/s) x
+ * ceil(w/s); q: c x h x w; one dtype.  Algorithm 2 runs with p' = p_low:
+ * I' = subsample(I, s), a and b of Eqs. 2-3 at r' = r/s, their box means,
+ * bilinear upsampling and q = mean_a .* I + mean_b on the full-resolution I.
+ * The full-resolution p is never read.  With p_low the nearest subsample of
+ * a full-resolution p, q equals gf_fast(I, p) bit for bit.  Workspace,
+ * streams and errors as gf_fast (gf_workspace_bytes(h, w, c, params)).
+ */
+gf_status gf_joint_upsample(gf_ctx *ctx, const gf_image *I, const gf_image *p_low, gf_image *q,
+                            const gf_params *params, void *workspace, size_t workspace_bytes,
+                            void *hip_stream);
+
+/*
+ * Detail enhancement (the paper's first application): the filter output q of
+ * gf_fast (gf_plain at s = 1) is the base layer and p - q the detail layer;
+ * e = q + gain * (p - q) is written to `e` (c x h x w, like q) in place of q.
+ * The paper's example amplifies the detail five times (gain 5).  q stays in
+ * FP32 registers; e is formed with one FMA and rounded once for storage.  The
+ * output pass also reads p (e * c bytes per pixel more than gf_fast).  gain
+ * must be finite (GF_EINVAL); otherwise as gf_fast.
+ */
+gf_status gf_detail_enhance(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *e,
+                            const gf_params *params, double gain, void *workspace,
+                            size_t workspace_bytes, void *hip_stream);
+
 /* Workspace (bytes) of gf_fast_batched for n images (device memory). */
 size_t gf_batched_workspace_bytes(int32_t n, const gf_image *I, const gf_image *p,
                                   const gf_params *params);

@@ -33,7 +33,8 @@ EXPORTS = ("gf_ctx_create", "gf_ctx_destroy", "gf_last_error", "gf_workspace_byt
            "gf_fast", "gf_batched_workspace_bytes", "gf_fast_batched", "gf_submit", "gf_poll",
            "gf_ctx_profile", "gf_ctx_profile_read", "gf_ctx_set_tiles", "gf_tune",
            "gf_ctx_save_tuning", "gf_ctx_load_tuning", "gf_batch_create", "gf_batch_launch",
-           "gf_batch_destroy", "gf_ctx_set_batch_cfg", "gf_tune_batched", "gf_footprint_bytes")
+           "gf_batch_destroy", "gf_ctx_set_batch_cfg", "gf_tune_batched", "gf_footprint_bytes", "gf_joint_upsample",
+           "gf_detail_enhance")
 KERNELS = ("coeff", "box", "output", "batched")
 
 
@@ -116,6 +117,8 @@ def lib() -> ctypes.CDLL:
             "gf_workspace_bytes": (SZ, [I32, I32, I32, par_p]),
             "gf_plain": (ctypes.c_int, [VP, img_p, img_p, img_p, I32, D, ctypes.c_int, VP, SZ, VP]),
             "gf_fast": (ctypes.c_int, [VP, img_p, img_p, img_p, par_p, VP, SZ, VP]),
+            "gf_joint_upsample": (ctypes.c_int, [VP, img_p, img_p, img_p, par_p, VP, SZ, VP]),
+            "gf_detail_enhance": (ctypes.c_int, [VP, img_p, img_p, img_p, par_p, D, VP, SZ, VP]),
             "gf_batched_workspace_bytes": (SZ, [I32, img_p, img_p, par_p]),
             "gf_fast_batched": (ctypes.c_int, [VP, I32, img_p, img_p, img_p, par_p, VP, SZ, VP]),
             "gf_submit": (ctypes.c_int, [VP, img_p, img_p, img_p, par_p, P(ctypes.c_uint64)]),
@@ -228,6 +231,41 @@ def gf_fast(I, p, r: int, s: int, eps: float, sub: str = "nearest", q=None, ctx=
                          ctypes.byref(image(q)), ctypes.byref(pr), ctypes.c_void_p(workspace.data_ptr()),
                          workspace.numel() * workspace.element_size(), _stream(stream)), ctx)
     return q
+
+
+def gf_joint_upsample(I, p_low, r: int, s: int, eps: float, sub: str = "nearest", q=None, ctx=None,
+                      workspace=None, stream=None):
+    """Joint upsampling: ``p_low`` (c, ceil(h/s), ceil(w/s)) or 2-D, guided by
+    ``I`` (h, w); returns q at full resolution (c, h, w) or (h, w)."""
+    h, w = I.shape[-2:]
+    if q is None:
+        import torch
+        q = torch.empty(p_low.shape[:-2] + (h, w), dtype=p_low.dtype, device=p_low.device)
+    pr = params(r, s, eps, sub)
+    c = 1 if p_low.dim() == 2 else p_low.shape[0]
+    if workspace is None:
+        workspace = _workspace(int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(pr))), I.device)
+    _check(lib().gf_joint_upsample(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p_low)),
+                                   ctypes.byref(image(q)), ctypes.byref(pr), ctypes.c_void_p(workspace.data_ptr()),
+                                   workspace.numel() * workspace.element_size(), _stream(stream)), ctx)
+    return q
+
+
+def gf_detail_enhance(I, p, r: int, s: int, eps: float, gain: float, sub: str = "nearest", e=None, ctx=None,
+                      workspace=None, stream=None):
+    """Detail enhancement: e = q + gain (p - q) with q the fast filter of p
+    (plain at s = 1).  Returns e (shape of p)."""
+    e = _out_like(p, e)
+    pr = params(r, s, eps, sub)
+    h, w = I.shape[-2:]
+    c = 1 if p.dim() == 2 else p.shape[0]
+    if workspace is None:
+        workspace = _workspace(int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(pr))), p.device)
+    _check(lib().gf_detail_enhance(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p)),
+                                   ctypes.byref(image(e)), ctypes.byref(pr), float(gain),
+                                   ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+                                   _stream(stream)), ctx)
+    return e
 
 
 def gf_plain(I, p, r: int, eps: float, q=None, ctx=None, workspace=None, stream=None):

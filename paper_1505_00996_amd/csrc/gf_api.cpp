@@ -124,16 +124,19 @@ static gf_status check_image(const gf_image *im, const char *name) {
 }
 
 gf_status validate(const gf_image *I, const gf_image *p, const gf_image *q,
-                   const gf_params *pr) {
+                   const gf_params *pr, bool p_low) {
     gf_status st;
     if ((st = check_image(I, "I")) != GF_OK) return st;
     if ((st = check_image(p, "p")) != GF_OK) return st;
     if ((st = check_image(q, "q")) != GF_OK) return st;
     if (!pr) return fail(GF_EINVAL, "params: null");
     if (I->c != 1) return fail(GF_ENOTSUP, "I: colour guidance (c=%d) is not supported; I must be gray", I->c);
-    if (p->h != I->h || p->w != I->w || q->h != I->h || q->w != I->w)
-        return fail(GF_EINVAL, "shape mismatch: I %dx%d, p %dx%d, q %dx%d", I->h, I->w, p->h,
-                    p->w, q->h, q->w);
+    if (pr->s < 1) return fail(GF_EINVAL, "s = %d < 1", pr->s);
+    // p is full resolution, or (joint upsampling) ceil(h/s) x ceil(w/s)
+    const int ph = p_low ? (I->h + pr->s - 1) / pr->s : I->h, pw = p_low ? (I->w + pr->s - 1) / pr->s : I->w;
+    if (p->h != ph || p->w != pw || q->h != I->h || q->w != I->w)
+        return fail(GF_EINVAL, "shape mismatch: I %dx%d, p %dx%d (expected %dx%d), q %dx%d", I->h, I->w, p->h,
+                    p->w, ph, pw, q->h, q->w);
     if (p->c != q->c) return fail(GF_EINVAL, "channel mismatch: p has %d, q has %d", p->c, q->c);
     if (p->dtype != I->dtype || q->dtype != I->dtype)
         return fail(GF_EINVAL, "dtype mismatch between I, p and q");
@@ -165,7 +168,7 @@ bool vector_ok(const gf_image *I, const gf_image *q) {
 
 gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
                    const gf_params *pr, void *ws, size_t ws_bytes, hipStream_t st,
-                   const TileCfg *tiles) {
+                   const TileCfg *tiles, bool p_low, const float *gain) {
     const Geo g = make_geo(I->h, I->w, p->c, pr->r, pr->s, pr->eps, (int)pr->sub);
     // pinned or tuned shapes that do not fit this radius fall back to the built-in choice
     const TileCfg t = (tiles && tiles_fit(g, *tiles)) ? *tiles : default_tiles(g);
@@ -183,7 +186,7 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
     hipError_t e;
     {
         ProfScope ps(ctx, GF_K_COEFF, st, true);
-        e = launch_coeff(I->dtype, vI, vP, coef, g, t, st, ps.stamp());
+        e = launch_coeff(I->dtype, vI, vP, coef, g, t, st, ps.stamp(), p_low);
         ps.commit(e == hipSuccess);
     }
     if (e == hipSuccess) {
@@ -193,7 +196,13 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
     }
     if (e == hipSuccess) {
         ProfScope ps(ctx, GF_K_OUTPUT, st, true);
-        e = launch_output(I->dtype, vI, vQ, mean, g, t, vector_ok(I, q), st, ps.stamp());
+        Detail dt;
+        if (gain) {
+            dt.p = vP;
+            dt.gain = *gain;
+        }
+        e = launch_output(I->dtype, vI, vQ, mean, g, t, vector_ok(I, q) && (!gain || vector_ok(p, p)), st,
+                          ps.stamp(), dt);
         ps.commit(e == hipSuccess);
     }
     if (e != hipSuccess) return fail(GF_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -235,9 +244,9 @@ size_t gf_workspace_bytes(int32_t h, int32_t w, int32_t c, const gf_params *pr) 
     return workspace_bytes(make_geo(h, w, c, pr->r, pr->s, pr->eps, (int)pr->sub));
 }
 
-gf_status gf_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
-                  const gf_params *pr, void *ws, size_t ws_bytes, void *stream) {
-    gf_status st = validate(I, p, q, pr);
+static gf_status fast_entry(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q, const gf_params *pr,
+                            void *ws, size_t ws_bytes, void *stream, bool p_low, const float *gain = nullptr) {
+    gf_status st = validate(I, p, q, pr, p_low);
     if (st != GF_OK) return st;
     if (!ws) {
         if (!ctx) return fail(GF_EINVAL, "workspace is NULL and there is no context");
@@ -250,7 +259,24 @@ gf_status gf_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q
     }
     TileCfg tuned;
     const bool have = ctx && ctx_tiles(ctx, I, p, pr, &tuned);
-    return run_fast(ctx, I, p, q, pr, ws, ws_bytes, (hipStream_t)stream, have ? &tuned : nullptr);
+    return run_fast(ctx, I, p, q, pr, ws, ws_bytes, (hipStream_t)stream, have ? &tuned : nullptr, p_low, gain);
+}
+
+gf_status gf_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
+                  const gf_params *pr, void *ws, size_t ws_bytes, void *stream) {
+    return fast_entry(ctx, I, p, q, pr, ws, ws_bytes, stream, false);
+}
+
+gf_status gf_joint_upsample(gf_ctx *ctx, const gf_image *I, const gf_image *p_low, gf_image *q,
+                            const gf_params *pr, void *ws, size_t ws_bytes, void *stream) {
+    return fast_entry(ctx, I, p_low, q, pr, ws, ws_bytes, stream, true);
+}
+
+gf_status gf_detail_enhance(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *e,
+                            const gf_params *pr, double gain, void *ws, size_t ws_bytes, void *stream) {
+    const float g = (float)gain;
+    if (!isfinite(gain) || !isfinite(g)) return fail(GF_EINVAL, "gain = %g must be finite (in FP32)", gain);
+    return fast_entry(ctx, I, p, e, pr, ws, ws_bytes, stream, false, &g);
 }
 
 gf_status gf_plain(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q, int32_t r,

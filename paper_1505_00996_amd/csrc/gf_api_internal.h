@@ -46,11 +46,13 @@ const char *last_error();
 int lowres_radius(int r, int s);
 bool tiles_fit(const Geo &g, const TileCfg &t);
 size_t workspace_bytes(const Geo &g);
-gf_status validate(const gf_image *I, const gf_image *p, const gf_image *q, const gf_params *pr);
+// p_low: p is the low-resolution input of joint upsampling (ceil(h/s) x ceil(w/s)).
+gf_status validate(const gf_image *I, const gf_image *p, const gf_image *q, const gf_params *pr,
+                   bool p_low = false);
 bool vector_ok(const gf_image *I, const gf_image *q);
 gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
                    const gf_params *pr, void *ws, size_t ws_bytes, hipStream_t st,
-                   const TileCfg *tiles);
+                   const TileCfg *tiles, bool p_low = false, const float *gain = nullptr);
 
 // Timing of one launcher call when the context is profiling (no-op
 // otherwise).  By default events are recorded on the stream before and after

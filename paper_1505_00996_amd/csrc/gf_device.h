@@ -378,7 +378,9 @@ __device__ __forceinline__ void coeff_from_sums(int n, double Su, double Suu, do
 // first (the guide's once, each channel's in turn); without it (large r',
 // where the staged region would not fit) the row pass reads them through the
 // caches.
-template <typename T, int K, int TH, bool STAGE, bool COH = false>
+// KP: how p is sampled -- like I (Algorithm 2), or kSubId when p is given at
+// low resolution already (joint upsampling: its rows are the low-res rows).
+template <typename T, int K, int TH, bool STAGE, bool COH = false, int KP = K>
 __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
                                            const T *__restrict__ P, int64_t Prs, int64_t Pps,
                                            float *__restrict__ coef, const Geo &g, int ty0, int tx0,
@@ -396,15 +398,18 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
     // loaded value lets the compiler turn the load into a branch that waits
     // for it, one load at a time.  The sample read there is an in-image one
     // (clamped address), so the product is an exact 0 for finite images.
-    auto gsample = [&](const T *img, int64_t rs, float c, int ry, int rx) -> float {
+    auto gsample = [&](auto kind, const T *img, int64_t rs, float c, int ry, int rx) -> float {
+        constexpr int KK = decltype(kind)::value;
         const int ly = oy + ry, lx = ox + rx;
         const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
-        const float v = sample_rc<K>(img, rs, taps<K>(clampi(ly, 0, g.Hl - 1), g.s, g.H),
-                                     taps<K>(clampi(lx, 0, g.Wl - 1), g.s, g.W));
+        const float v = sample_rc<KK>(img, rs, taps<KK>(clampi(ly, 0, g.Hl - 1), g.s, g.H),
+                                      taps<KK>(clampi(lx, 0, g.Wl - 1), g.s, g.W));
         return (v - c) * (in ? 1.f : 0.f);
     };
+    using KI = std::integral_constant<int, K>;
+    using KQ = std::integral_constant<int, KP>;
     const float cI = sample<K>(I, Irs, ty0, tx0, g);
-    auto gU = [&](int ry, int rx) { return gsample(I, Irs, cI, ry, rx); };
+    auto gU = [&](int ry, int rx) { return gsample(KI{}, I, Irs, cI, ry, rx); };
 
     const int col = lane, r0 = wave * LC;
     const int lx = tx0 + col;
@@ -463,8 +468,8 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
     };
 
     const T *P0 = P;
-    const float cP0 = sample<K>(P0, Prs, ty0, tx0, g);
-    auto gV0 = [&](int ry, int rx) { return gsample(P0, Prs, cP0, ry, rx); };
+    const float cP0 = sample<KP>(P0, Prs, ty0, tx0, g);
+    auto gV0 = [&](int ry, int rx) { return gsample(KQ{}, P0, Prs, cP0, ry, rx); };
     if (STAGE) {
         fill_tile2(sU, sV, SH, SW, SWp, gU, gV0);  // guide and channel 0 in one batch
         __syncthreads();
@@ -500,7 +505,7 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
     for (int c = 0; c < g.C; ++c) {
         const T *Pc = P + (int64_t)c * Pps;
         const float cP = c ? cPn : cP0;
-        auto gV = [&](int ry, int rx) { return gsample(Pc, Prs, cP, ry, rx); };
+        auto gV = [&](int ry, int rx) { return gsample(KQ{}, Pc, Prs, cP, ry, rx); };
         // sV is free: the last row pass that read it ended at a barrier
         if (STAGE && c) {
             if (ahead) fill_store(next, sV, SH, SW, SWp);
@@ -509,8 +514,8 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
         __syncthreads();  // sV staged; the previous column pass is done with rA, rB
         if (c + 1 < g.C) {
             const T *Pn = Pc + Pps;
-            cPn = sample<K>(Pn, Prs, ty0, tx0, g);
-            if (ahead) fill_load(next, SH, SW, [&](int ry, int rx) { return gsample(Pn, Prs, cPn, ry, rx); });
+            cPn = sample<KP>(Pn, Prs, ty0, tx0, g);
+            if (ahead) fill_load(next, SH, SW, [&](int ry, int rx) { return gsample(KQ{}, Pn, Prs, cPn, ry, rx); });
         }
         // sums of v and u*v, then a and b
         row_pass(std::true_type{}, gV);
@@ -624,10 +629,15 @@ constexpr float cfrac_u(int x, int s) {
 // q for CC channels (planes Q + c*Qps) of the wave's 8 x 256 block at
 // (yb, xw); mean_a_c = M + (c0+c)*lps, mean_b_c = M + (C+c0+c)*lps.
 // S: compile-time ratio, 0 = read g.s at run time.
-template <typename T, int CC, int S>
+// EPI (detail enhancement): with P the c0-th plane of p (same layout as Q),
+// each output becomes e = q + gain (p - q), formed from the FP32 q before
+// the store's rounding.
+template <typename T, int CC, int S, bool EPI = false>
 __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs, T *__restrict__ Q,
                                             int64_t Qrs, int64_t Qps, const float *__restrict__ M,
-                                            const Geo &g, int c0, int yb, int xw, bool vec) {
+                                            const Geo &g, int c0, int yb, int xw, bool vec,
+                                            const T *__restrict__ P = nullptr, int64_t Prs = 0,
+                                            int64_t Pps = 0, float gain = 0.f) {
     constexpr int ROWS = kOutRows;
     const int lane = threadIdx.x & 63;
     const int x0 = xw + lane * kOutPx;
@@ -639,24 +649,24 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
     const bool in4 = x0 + 3 < g.W;
     const bool full = vec && in4;
 
+    auto load_row = [&](const T *plane, int64_t rs, int y) -> f32x4 {
+        f32x4 v = {0.f, 0.f, 0.f, 0.f};
+        const T *base = plane + (int64_t)y * rs, *row = base + x0;
+        if (full) {
+            v = ld4(row);
+        } else if (in4 && pair_aligned(base)) {
+            const f32x2 lo = ld2(row), hi = ld2(row + 2);
+            v = f32x4{lo.x, lo.y, hi.x, hi.y};
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (x0 + j < g.W) v[j] = ld(row + j);
+        }
+        return v;
+    };
     f32x4 iv[ROWS];
 #pragma unroll
-    for (int i = 0; i < ROWS; ++i) {
-        iv[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-        if (i < nrows) {
-            const T *base = I + (int64_t)(yb + i) * Irs, *row = base + x0;
-            if (full) {
-                iv[i] = ld4(row);
-            } else if (in4 && pair_aligned(base)) {
-                const f32x2 lo = ld2(row), hi = ld2(row + 2);
-                iv[i] = f32x4{lo.x, lo.y, hi.x, hi.y};
-            } else {
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (x0 + j < g.W) iv[i][j] = ld(row + j);
-            }
-        }
-    }
+    for (int i = 0; i < ROWS; ++i) iv[i] = i < nrows ? load_row(I, Irs, yb + i) : f32x4{0.f, 0.f, 0.f, 0.f};
     auto store_q = [&](T *plane, int y, f32x4 v) {
         T *base = plane + (int64_t)y * Qrs, *row = base + x0;
         if (full) {
@@ -670,6 +680,22 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
                 if (x0 + j < g.W) st1(row + j, v[j]);
         }
     };
+    // the rows of channel c of p, for the detail epilogue (loaded together)
+    f32x4 pv[EPI ? ROWS : 1] = {};
+    auto load_p = [&](int c) {
+        if constexpr (EPI) {
+            const T *Pc = P + (int64_t)c * Pps;
+#pragma unroll
+            for (int i = 0; i < ROWS; ++i) pv[i] = i < nrows ? load_row(Pc, Prs, yb + i) : f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto finish = [&](f32x4 q, f32x4 pr) -> f32x4 {
+        if constexpr (EPI) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) q[j] = lerp(q[j], pr[j], gain);
+        }
+        return q;
+    };
 
     if constexpr (S == 1) {
         // Algorithm 1: the maps are full resolution; rows are padded to a
@@ -679,6 +705,7 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
             const float *Ma = M + (int64_t)(c0 + c) * g.lps;
             const float *Mb = M + (int64_t)(g.C + c0 + c) * g.lps;
             T *Qc = Q + (int64_t)c * Qps;
+            load_p(c);
 #pragma unroll
             for (int i = 0; i < ROWS; ++i) {
                 if (i < nrows) {
@@ -688,7 +715,7 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
                     f32x4 out;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) out[j] = madd(a[j], iv[i][j], b[j]);
-                    store_q(Qc, y, out);
+                    store_q(Qc, y, finish(out, pv[EPI ? i : 0]));
                 }
             }
         }
@@ -715,6 +742,7 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
             const float *Ma = M + (int64_t)(c0 + c) * g.lps;
             const float *Mb = M + (int64_t)(g.C + c0 + c) * g.lps;
             T *Qc = Q + (int64_t)c * Qps;
+            load_p(c);
             float ha[NL][4], hb[NL][4];
 #pragma unroll
             for (int m = 0; m < NL; ++m) {
@@ -745,7 +773,7 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
                         const float b = lerp(hb[m0][j], hb[m0 + 1][j], wy);
                         out[j] = madd(a, iv[i][j], b);
                     }
-                    store_q(Qc, yb + i, out);
+                    store_q(Qc, yb + i, finish(out, pv[EPI ? i : 0]));
                 }
             }
         }
@@ -790,6 +818,7 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
                     const float b1 = lerp(rb1[xa[j]], rb1[xb[j]], wx[j]);
                     out[j] = madd(lerp(a0, a1, wy), iy[j], lerp(b0, b1, wy));
                 }
+                if constexpr (EPI) out = finish(out, load_row(P + (int64_t)c * Pps, Prs, y));
                 store_q(Qc, y, out);
             }
         }

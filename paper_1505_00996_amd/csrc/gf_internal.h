@@ -55,13 +55,22 @@ struct Stamp {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 
+// Output epilogue: detail enhancement e = q + gain (p - q), p full resolution
+// with the layout of q (data null: plain q).
+struct Detail {
+    View p{};
+    float gain = 0.f;
+};
+
 // Kernel launchers (gf_kernels.hip).  All return the launch status.
+// p_low: p is given at low resolution (joint upsampling) and read as is.
 hipError_t launch_coeff(gf_dtype dt, const View &I, const View &P, float *coef,
-                        const Geo &g, const TileCfg &t, hipStream_t st, const Stamp &ts = Stamp{});
+                        const Geo &g, const TileCfg &t, hipStream_t st, const Stamp &ts = Stamp{},
+                        bool p_low = false);
 hipError_t launch_box(const float *src, float *dst, const Geo &g, const TileCfg &t,
                       hipStream_t st, const Stamp &ts = Stamp{});
 hipError_t launch_output(gf_dtype dt, const View &I, const View &Q, const float *mean,
                          const Geo &g, const TileCfg &t, bool vec, hipStream_t st,
-                         const Stamp &ts = Stamp{});
+                         const Stamp &ts = Stamp{}, const Detail &detail = Detail{});
 
 }  // namespace gf

@@ -199,3 +199,21 @@ def test_footprint_bytes():
     assert fp == L.gf_footprint_bytes(3000, 4000, 3, gfp.GF_F32, ctypes.byref(pr))
     assert L.gf_footprint_bytes(0, 4000, 3, gfp.GF_F32, ctypes.byref(pr)) == 0
     assert L.gf_footprint_bytes(30, 40, 3, 9, ctypes.byref(pr)) == 0
+
+
+def test_joint_upsample_shapes_checked_on_host():
+    # p_low must be ceil(h/s) x ceil(w/s); q full resolution
+    I = img(A_I, 1, 64, 80)
+    q = img(A_Q, 3, 64, 80)
+    pr = gfp.params(8, 4, 1e-2)
+
+    def call(p, q=q, pr=pr):
+        return L.gf_joint_upsample(None, ctypes.byref(I), ctypes.byref(p), ctypes.byref(q), ctypes.byref(pr),
+                                   ctypes.c_void_p(0x40000000), 1024, None)
+    assert call(img(A_P, 3, 64, 80)) == gfp.GF_EINVAL          # full-resolution p
+    assert call(img(A_P, 3, 16, 21)) == gfp.GF_EINVAL          # wrong low-res width
+    assert call(img(A_P, 3, 16, 20), q=img(A_Q, 3, 16, 20)) == gfp.GF_EINVAL  # low-res q
+    bad = gfp.params(8, 0, 1e-2)
+    assert call(img(A_P, 3, 16, 20), pr=bad) == gfp.GF_EINVAL  # s = 0
+    # right shapes: validation passes, the tiny workspace is then refused
+    assert call(img(A_P, 3, 16, 20)) == gfp.GF_ENOMEM
