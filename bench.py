@@ -141,7 +141,7 @@ def measure_batched(gfp, torch, dev, n=256, reps=5, seed=6, tune=True):
 
 def measure_16bit(gfp, torch, dev, steps=50, with_oracle=True):
     """16-bit storage (fp16 and bf16): the 6000x4000 workload with near-flat
-    guide blocks, RGB input, r = 32, s = 8 (r' = 4), eps = 1e-4, two rotated
+    guide blocks, RGB input, r = 32, s = 8 (r' = 4), eps = 1e-4, four rotated
     input sets.  gf_fast per step; per-kernel HIP events; the output kernel's
     roofline; max |q - oracle| on the stored inputs."""
     import numpy as np
@@ -152,7 +152,7 @@ def measure_16bit(gfp, torch, dev, steps=50, with_oracle=True):
                        "eps=1e-4, nearest; gf_fast per step", "h": h, "w": w, "channels": c}
     for name, dt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
         sets = []
-        for k in range(2):
+        for k in range(4):  # 4 x 192 MB: inputs are not served from the last-level cache
             dI = torch.from_numpy(I_np).to(dev).to(dt)
             dp = torch.from_numpy(p_np).to(dev).to(dt)
             sets.append((dI, dp, torch.empty_like(dp)))
@@ -189,6 +189,91 @@ def measure_16bit(gfp, torch, dev, steps=50, with_oracle=True):
             step(0)
             torch.cuda.synchronize()
             exp = oracle.fast_guided_filter(dI.double().cpu().numpy(), dp.double().cpu().numpy(), r, s, eps)
+            res["max_abs_err"] = float(np.max(np.abs(q.double().cpu().numpy() - exp)))
+        out[name] = res
+        ctx.close()
+        del sets
+    return out
+
+
+def measure_apps(gfp, torch, dev, I_np, p_np, steps=50, with_oracle=True):
+    """The paper's applications and joint upsampling on the 4000x3000 workload
+    (fp32, nearest, s = 4, four rotated input sets): MPix/s, per-kernel HIP
+    event times, the output pass against its algorithmic bytes, and
+    max |out - oracle| on the stored inputs."""
+    import numpy as np
+    h, w = I_np.shape
+    c = p_np.shape[0]
+    s = 4
+    hl, wl = lowres(h, s), lowres(w, s)
+    # joint upsampling input: a smooth low-res RGB field (not a subsample)
+    yy, xx = np.meshgrid(np.linspace(0, 1, hl), np.linspace(0, 1, wl), indexing="ij")
+    plo_np = np.stack([0.5 + 0.3 * np.sin(3 * yy + 2 * k) * np.cos(4 * xx - k) for k in range(c)]).astype(np.float32)
+    mask_np = (I_np > 0.5).astype(np.float32)  # feathering: a hard mask refined along the guide's edges
+    specs = [
+        # name, op, input, channels, r, eps, extra, output-pass bytes per full-res pixel (+ low-res maps)
+        ("detail_enhancement", "detail", p_np, c, 16, 0.1 ** 2, 5.0),
+        ("flash_no_flash", "fast", p_np, c, 8, 0.02 ** 2, None),
+        ("feathering", "fast", mask_np[None], 1, 60, 0.001 ** 2, None),
+        ("joint_upsampling", "joint", plo_np, c, 16, 1e-3, None),
+    ]
+    out = {"workload": "4000x3000 gray guide, fp32, s=4 (nearest); detail enhancement r=16 eps=0.1^2 gain 5 "
+                       "on RGB p; flash/no-flash r=8 eps=0.02^2 on RGB p; feathering r=60 eps=0.001^2 on a "
+                       "binary mask; joint upsampling of a 1000x750 RGB input, r=16 eps=1e-3"}
+    for name, op, x_np, cc, r, eps, gain in specs:
+        sets = []
+        for k in range(4):  # 4 rotated sets: inputs are not served from the last-level cache
+            dI = torch.from_numpy(I_np).to(dev)
+            dx = torch.from_numpy(np.ascontiguousarray(x_np)).to(dev)
+            sets.append((dI, dx, torch.empty((cc, h, w), dtype=torch.float32, device=dev)))
+        ctx = gfp.Context(0)
+        ws = torch.empty(gfp.workspace_bytes(h, w, cc, r, s, eps), dtype=torch.uint8, device=dev)
+
+        def step(i):
+            dI, dx, q = sets[i % len(sets)]
+            if op == "fast":
+                gfp.gf_fast(dI, dx, r, s, eps, q=q, ctx=ctx, workspace=ws)
+            elif op == "detail":
+                gfp.gf_detail_enhance(dI, dx, r, s, eps, gain, e=q, ctx=ctx, workspace=ws)
+            else:
+                gfp.gf_joint_upsample(dI, dx, r, s, eps, q=q, ctx=ctx, workspace=ws)
+        for i in range(5):
+            step(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(i)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ctx.profile(True)
+        ctx.profile_read()
+        for i in range(steps):
+            step(i)
+        kt = ctx.profile_read()
+        ctx.profile(False)
+        # output pass: I read, out written (and p read for detail), 2C low-res maps read
+        ob = h * w * 4 * (1 + cc + (cc if op == "detail" else 0)) + 2 * cc * hl * wl * 4
+        out_ms = kt["output"][0] / max(kt["output"][1], 1)
+        res = {"value": round(h * w / 1e6 / (ms * 1e-3), 1), "unit": "MPix/s", "ms_per_step": round(ms, 5),
+               "r": r, "eps": eps, "channels": cc,
+               "kernels": {k: round(v[0] / v[1], 5) for k, v in kt.items() if v[1]},
+               "output_pass": {"achieved_GBs": round(ob / (out_ms * 1e-3) / 1e9, 1),
+                               "frac": round(ob / (out_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "algorithmic_bytes_per_launch": ob}}
+        if gain is not None:
+            res["gain"] = gain
+        if with_oracle:
+            from oracle import oracle
+            dI, dx, q = sets[0]
+            step(0)
+            torch.cuda.synchronize()
+            I64, x64 = I_np.astype(np.float64), np.asarray(x_np, dtype=np.float64)
+            if op == "joint":
+                exp = oracle.joint_upsample(I64, x64, r, s, eps)
+            else:
+                exp = oracle.fast_guided_filter(I64, x64, r, s, eps)
+                if op == "detail":
+                    exp = oracle.detail_enhance(x64, exp, gain)
             res["max_abs_err"] = float(np.max(np.abs(q.double().cpu().numpy() - exp)))
         out[name] = res
         ctx.close()
@@ -413,8 +498,11 @@ def main():
     kt_plain = ctx.profile_read()
     ctx.profile(False)
 
-    batched = served = sixteen = None
+    batched = served = sixteen = apps = None
     if not args.no_extra:
+        apps = measure_apps(gfp, torch, dev, I_np, p_np, with_oracle=not args.no_cpu)
+        print("# apps: " + ", ".join(f"{k} {v['value']}" for k, v in apps.items() if isinstance(v, dict)),
+              file=sys.stderr, flush=True)
         sixteen = measure_16bit(gfp, torch, dev, with_oracle=not args.no_cpu)
         print(f"# 16-bit: f16 {sixteen['f16']['value']} bf16 {sixteen['bf16']['value']} MPix/s",
               file=sys.stderr, flush=True)
@@ -453,6 +541,7 @@ def main():
                   "ms_per_step": round(ms_plain, 5), "steps": plain_steps,
                   "kernels": {k: round(v[0] / v[1], 5) for k, v in kt_plain.items() if v[1]}},
         "storage_16bit": sixteen,
+        "applications": apps,
         "speedup_vs_plain": round(ms_plain / ms_fast, 3),
         "step_events": step_events,
         "ms_per_step_with_kernel_events": round(ms_fast_ev, 5),
