@@ -171,13 +171,13 @@ __device__ __forceinline__ void run_output(const BDesc &d, unsigned local, float
     for (int c = 0; c < cc; ++c) {
         const float *Ma = d.mean + (int64_t)(c0 + c) * g.lps + (int64_t)py0 * g.lrs + px0;
         const float *Mb = d.mean + (int64_t)(g.C + c0 + c) * g.lps + (int64_t)py0 * g.lrs + px0;
-        __syncthreads();  // the previous channel's patch has been read
+        lds_sync();  // the previous channel's patch has been read
         for (int k = threadIdx.x; k < nr * nc; k += kThreads) {
             const int ry = k / nc, rx = k - ry * nc;
             pa[ry * kPatchStride + rx] = ldp<true>(Ma + (int64_t)ry * g.lrs + rx);
             pb[ry * kPatchStride + rx] = ldp<true>(Mb + (int64_t)ry * g.lrs + rx);
         }
-        __syncthreads();
+        lds_sync();
         if (act) {
             T *Qc = Q + (int64_t)c * d.Qps;
 #pragma unroll

@@ -12,7 +12,7 @@
 //                 (steps 6-7); the HBM-bound pass.
 //
 // Every tile function is called by a whole 256-thread workgroup (4 waves);
-// coeff_tile and box_tile use __syncthreads and LDS passed in by the caller.
+// coeff_tile and box_tile use workgroup barriers (lds_sync) and LDS passed in by the caller.
 //
 // Window sums: a row pass (each thread slides a (2r'+1)-wide window over
 // kRun consecutive outputs of one region row) writes row sums to LDS; a
@@ -191,6 +191,17 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 
 // Approximate reciprocal (1 ulp): the results it feeds tolerate 1e-7.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Workgroup barrier that orders LDS accesses only.  A thread's outstanding
+// global loads stay in flight across it; __syncthreads also waits for them
+// (its fence covers all memory), which would cancel the prefetches the tile
+// code issues ahead of LDS passes.  Every barrier in the tile code only
+// separates LDS writers from LDS readers.
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 // a + w (b - a) and a x + b, each with one fused rounding
 __device__ __forceinline__ float lerp(float a, float b, float w) { return __builtin_fmaf(w, b - a, a); }
 __device__ __forceinline__ float madd(float a, float x, float b) { return __builtin_fmaf(a, x, b); }
@@ -472,13 +483,13 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
     auto gV0 = [&](int ry, int rx) { return gsample(KQ{}, P0, Prs, cP0, ry, rx); };
     if (STAGE) {
         fill_tile2(sU, sV, SH, SW, SWp, gU, gV0);  // guide and channel 0 in one batch
-        __syncthreads();
+        lds_sync();
     }
 
     // guide: sums of u and u*u, once for all channels
     double Su[LC], Suu[LC];
     row_pass(std::false_type{}, gV0);
-    __syncthreads();
+    lds_sync();
     {
         double A = 0.0, B = 0.0;
 #pragma unroll 8
@@ -511,7 +522,7 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
             if (ahead) fill_store(next, sV, SH, SW, SWp);
             else fill_tile(sV, SH, SW, SWp, gV);
         }
-        __syncthreads();  // sV staged; the previous column pass is done with rA, rB
+        lds_sync();  // sV staged; the previous column pass is done with rA, rB
         if (c + 1 < g.C) {
             const T *Pn = Pc + Pps;
             cPn = sample<KP>(Pn, Prs, ty0, tx0, g);
@@ -519,7 +530,7 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
         }
         // sums of v and u*v, then a and b
         row_pass(std::true_type{}, gV);
-        __syncthreads();
+        lds_sync();
         float *ac = coef + (int64_t)c * g.lps, *bc = coef + (int64_t)(g.C + c) * g.lps;
         double A = 0.0, B = 0.0;
 #pragma unroll 8
@@ -560,7 +571,7 @@ __device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__r
         const float v = ldp<COH>(S + (int64_t)clampi(ly, 0, g.Hl - 1) * g.lrs + clampi(lx, 0, g.Wl - 1));
         return v * (in ? 1.f : 0.f);  // product, not select: see coeff_tile
     });
-    __syncthreads();
+    lds_sync();
     for (int it = threadIdx.x; it < SH * (kTileW / kRun); it += kThreads) {
         const int j0 = (it / SH) * kRun, ry = it - (it / SH) * SH;  // lanes down the rows (see coeff_tile)
         const float *px = sX + ry * SWp + j0;
@@ -585,7 +596,7 @@ __device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__r
 #pragma unroll
         for (int t = 0; t < kRun; ++t) oa[t] = res[t];
     }
-    __syncthreads();
+    lds_sync();
     const int col = lane, r0 = wave * LC;
     const int lx = tx0 + col;
     const int nx = clip_len(lx, R, g.Wl);
