@@ -27,13 +27,21 @@
  *     centre s*y + (s-1)/2 with two clamped taps (no antialias prefilter);
  *   - bilinear upsampling uses half-pixel centres, u = (y+0.5)/s - 0.5, with
  *     taps clamped to the low-res map;
- *   - a multi-channel p is filtered channel by channel with the same gray I.
+ *   - a multi-channel p is filtered channel by channel with the same gray I;
+ *   - optional conventions of other libraries: a padded border, where the
+ *     image is extended past its edges (replicating the edge pixel, or
+ *     mirroring about it without repeating it: "reflect-101") and every
+ *     window mean divides by (2r+1)^2; and area subsampling, the mean of the
+ *     s x s block of full-res pixels [s*y, s*y+s) x [s*x, s*x+s) restricted
+ *     to the image.
  *
  * Parity status: every function here is pinned by the CPU tests (brute-force
  * window loops, scipy/torch special cases, a least-squares solve of the
  * windowed ridge regression, and closed-form invariants of Eqs. 1-4; joint
  * upsampling against its assembly from library routines and against the fast
- * filter of a subsampled input; detail enhancement at its gain end points).
+ * filter of a subsampled input; detail enhancement at its gain end points;
+ * the padded borders against numpy's edge and reflect padding and scipy's
+ * uniform filter, area subsampling against torch's average pooling).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -41,6 +49,11 @@
 
 #define ORACLE_NEAREST 0
 #define ORACLE_BILINEAR 1
+#define ORACLE_AREA 2
+
+#define ORACLE_CLIP 0
+#define ORACLE_REPLICATE 1
+#define ORACLE_REFLECT101 2
 
 static int imin(int a, int b) { return a < b ? a : b; }
 static int imax(int a, int b) { return a > b ? a : b; }
@@ -103,6 +116,63 @@ int oracle_box_mean(const double *x, int h, int w, int r, double *out)
 }
 
 /*
+ * Position i of an n-pixel axis extended past its ends, as an index into the
+ * axis.  Replicate repeats the end pixel.  Reflect-101 mirrors the axis about
+ * its first and last pixels without repeating them (... 2 1 | 0 1 2 ... n-1 |
+ * n-2 n-3 ...), as many times as a window wider than the axis needs; a
+ * one-pixel axis is that pixel everywhere.
+ */
+static int border_index(int i, int n, int border)
+{
+    if (border == ORACLE_REPLICATE) return iclamp(i, 0, n - 1);
+    if (n == 1) return 0;
+    while (i < 0 || i > n - 1) {
+        if (i < 0) i = -i;
+        if (i > n - 1) i = 2 * (n - 1) - i;
+    }
+    return i;
+}
+
+/*
+ * f_mean with a padded border: every pixel's (2r+1)x(2r+1) window reads the
+ * image extended past its edges (border_index), so every window holds
+ * (2r+1)^2 samples and the mean divides by that.  Row sums first, then the
+ * sum of 2r+1 row sums, both in window order.
+ */
+static int box_mean_padded(const double *x, int h, int w, int r, int border, double *out)
+{
+    double *rowsum = (double *)malloc(sizeof(double) * (size_t)h * (size_t)w);
+    if (!rowsum) return -2;
+    for (int y = 0; y < h; ++y) {
+        for (int xx = 0; xx < w; ++xx) {
+            double acc = 0.0;
+            for (int k = -r; k <= r; ++k) acc += x[(size_t)y * w + border_index(xx + k, w, border)];
+            rowsum[(size_t)y * w + xx] = acc;
+        }
+    }
+    const double count = (double)(2 * r + 1) * (double)(2 * r + 1);
+    for (int y = 0; y < h; ++y) {
+        for (int xx = 0; xx < w; ++xx) {
+            double acc = 0.0;
+            for (int k = -r; k <= r; ++k) acc += rowsum[(size_t)border_index(y + k, h, border) * w + xx];
+            out[(size_t)y * w + xx] = acc / count;
+        }
+    }
+    free(rowsum);
+    return 0;
+}
+
+/* f_mean under the given border convention (clip-normalised, replicate or
+ * reflect-101). */
+int oracle_box_mean_border(const double *x, int h, int w, int r, int border, double *out)
+{
+    if (border == ORACLE_CLIP) return oracle_box_mean(x, h, w, r, out);
+    if (h <= 0 || w <= 0 || r < 0) return -1;
+    if (border != ORACLE_REPLICATE && border != ORACLE_REFLECT101) return -1;
+    return box_mean_padded(x, h, w, r, border, out);
+}
+
+/*
  * f_subsample(x, s) of Algorithm 2, step 1 (the paper allows nearest-neighbour
  * or bilinear).  Output is ceil(h/s) x ceil(w/s).
  *   nearest : x(min(s*y + s/2, h-1), min(s*x + s/2, w-1)).
@@ -124,9 +194,33 @@ static void axis_sample(int j, int s, int n, int mode, int *t0, int *t1, double 
     *t1 = iclamp((int)f + 1, 0, n - 1);
 }
 
+/*
+ * Area subsampling: low-res pixel (y, x) is the mean of the full-res pixels
+ * of the block [s*y, s*y+s) x [s*x, s*x+s) that lie inside the image (the
+ * last block of an axis whose length is not a multiple of s is shorter).
+ */
+static void area_subsample(const double *x, int h, int w, int s, double *out)
+{
+    int hl = oracle_lowres_size(h, s), wl = oracle_lowres_size(w, s);
+    for (int y = 0; y < hl; ++y) {
+        int y0 = s * y, y1 = imin(h, s * y + s);
+        for (int xx = 0; xx < wl; ++xx) {
+            int x0 = s * xx, x1 = imin(w, s * xx + s);
+            double acc = 0.0;
+            for (int i = y0; i < y1; ++i)
+                for (int j = x0; j < x1; ++j) acc += x[(size_t)i * w + j];
+            out[(size_t)y * wl + xx] = acc / ((double)(y1 - y0) * (double)(x1 - x0));
+        }
+    }
+}
+
 int oracle_subsample(const double *x, int h, int w, int s, int mode, double *out)
 {
     if (h <= 0 || w <= 0 || s < 1) return -1;
+    if (mode == ORACLE_AREA) {
+        area_subsample(x, h, w, s, out);
+        return 0;
+    }
     if (mode != ORACLE_NEAREST && mode != ORACLE_BILINEAR) return -1;
     int hl = oracle_lowres_size(h, s), wl = oracle_lowres_size(w, s);
     for (int y = 0; y < hl; ++y) {
@@ -178,9 +272,9 @@ int oracle_upsample(const double *lo, int hl, int wl, int s, int h, int w, doubl
  * Algorithm 1, steps 1-3, for one channel of p: the per-window linear
  * coefficients of Eqs. 2-3,
  *   a = (mean(I.*p) - mean(I) mean(p)) / (var(I) + eps),  b = mean(p) - a mean(I),
- * with every mean a clip-normalised box mean of radius r.
+ * with every mean a box mean of radius r under the border convention.
  */
-int oracle_coefficients(const double *I, const double *p, int h, int w, int r, double eps,
+static int coefficients(const double *I, const double *p, int h, int w, int r, double eps, int border,
                         double *a, double *b)
 {
     size_t n = (size_t)h * (size_t)w;
@@ -193,12 +287,12 @@ int oracle_coefficients(const double *I, const double *p, int h, int w, int r, d
     if (!mean_I || !mean_p || !corr_I || !corr_Ip || !tmp) { rc = -2; goto done; }
 
     /* step 1: four mean filters; the products are formed pixel by pixel first */
-    if ((rc = oracle_box_mean(I, h, w, r, mean_I))) goto done;
-    if ((rc = oracle_box_mean(p, h, w, r, mean_p))) goto done;
+    if ((rc = oracle_box_mean_border(I, h, w, r, border, mean_I))) goto done;
+    if ((rc = oracle_box_mean_border(p, h, w, r, border, mean_p))) goto done;
     for (size_t i = 0; i < n; ++i) tmp[i] = I[i] * I[i];
-    if ((rc = oracle_box_mean(tmp, h, w, r, corr_I))) goto done;
+    if ((rc = oracle_box_mean_border(tmp, h, w, r, border, corr_I))) goto done;
     for (size_t i = 0; i < n; ++i) tmp[i] = I[i] * p[i];
-    if ((rc = oracle_box_mean(tmp, h, w, r, corr_Ip))) goto done;
+    if ((rc = oracle_box_mean_border(tmp, h, w, r, border, corr_Ip))) goto done;
 
     /* steps 2-3: variance, covariance, then the closed forms of Eqs. 2-3 */
     for (size_t i = 0; i < n; ++i) {
@@ -212,15 +306,22 @@ done:
     return rc;
 }
 
+int oracle_coefficients(const double *I, const double *p, int h, int w, int r, double eps,
+                        double *a, double *b)
+{
+    return coefficients(I, p, h, w, r, eps, ORACLE_CLIP, a, b);
+}
+
 /*
  * Algorithm 1 (the guided filter) for a c-channel p with gray guide I.
  * Per channel: a, b from Eqs. 2-3 (steps 1-3), their box means (step 4) and
  * q = mean_a .* I + mean_b (step 5, Eq. 4).
  * Optional outputs (may be NULL), c*h*w each: a, b, mean_a, mean_b.
+ * Every mean uses the border convention `border` (ORACLE_CLIP: clip-normalised).
  */
-int oracle_guided_filter(const double *I, const double *p, int c, int h, int w, int r,
-                         double eps, double *q, double *a_out, double *b_out,
-                         double *mean_a_out, double *mean_b_out)
+int oracle_guided_filter_ex(const double *I, const double *p, int c, int h, int w, int r,
+                            double eps, int border, double *q, double *a_out, double *b_out,
+                            double *mean_a_out, double *mean_b_out)
 {
     if (h <= 0 || w <= 0 || c <= 0 || r < 0 || !(eps > 0.0)) return -1;
     size_t n = (size_t)h * (size_t)w;
@@ -233,9 +334,9 @@ int oracle_guided_filter(const double *I, const double *p, int c, int h, int w, 
     for (int k = 0; k < c; ++k) {
         const double *pk = p + (size_t)k * n;
         double *qk = q + (size_t)k * n;
-        if ((rc = oracle_coefficients(I, pk, h, w, r, eps, a, b))) goto done;
-        if ((rc = oracle_box_mean(a, h, w, r, ma))) goto done;
-        if ((rc = oracle_box_mean(b, h, w, r, mb))) goto done;
+        if ((rc = coefficients(I, pk, h, w, r, eps, border, a, b))) goto done;
+        if ((rc = oracle_box_mean_border(a, h, w, r, border, ma))) goto done;
+        if ((rc = oracle_box_mean_border(b, h, w, r, border, mb))) goto done;
         for (size_t i = 0; i < n; ++i) qk[i] = ma[i] * I[i] + mb[i];
         if (a_out) memcpy(a_out + (size_t)k * n, a, sizeof(double) * n);
         if (b_out) memcpy(b_out + (size_t)k * n, b, sizeof(double) * n);
@@ -247,6 +348,14 @@ done:
     return rc;
 }
 
+int oracle_guided_filter(const double *I, const double *p, int c, int h, int w, int r,
+                         double eps, double *q, double *a_out, double *b_out,
+                         double *mean_a_out, double *mean_b_out)
+{
+    return oracle_guided_filter_ex(I, p, c, h, w, r, eps, ORACLE_CLIP, q, a_out, b_out, mean_a_out,
+                                   mean_b_out);
+}
+
 /*
  * Algorithm 2 (the Fast Guided Filter) for a c-channel p with gray guide I.
  *   step 1: I' = f_subsample(I, s), p' = f_subsample(p, s), r' = r/s;
@@ -254,14 +363,15 @@ done:
  *   step 6: mean_a, mean_b bilinearly upsampled to h x w;
  *   step 7: q = mean_a .* I + mean_b against the full-resolution I.
  * Optional low-resolution outputs (may be NULL), c*hl*wl each: a, b,
- * mean_a, mean_b before upsampling.
+ * mean_a, mean_b before upsampling.  `mode` is the subsampling (nearest,
+ * bilinear or area); every low-res mean uses the border convention `border`.
  */
-int oracle_fast_guided_filter(const double *I, const double *p, int c, int h, int w, int r,
-                              int s, double eps, int mode, double *q, double *a_lo,
-                              double *b_lo, double *mean_a_lo, double *mean_b_lo)
+int oracle_fast_guided_filter_ex(const double *I, const double *p, int c, int h, int w, int r,
+                                 int s, double eps, int mode, int border, double *q, double *a_lo,
+                                 double *b_lo, double *mean_a_lo, double *mean_b_lo)
 {
     if (h <= 0 || w <= 0 || c <= 0 || r < 0 || s < 1 || !(eps > 0.0)) return -1;
-    if (mode != ORACLE_NEAREST && mode != ORACLE_BILINEAR) return -1;
+    if (mode != ORACLE_NEAREST && mode != ORACLE_BILINEAR && mode != ORACLE_AREA) return -1;
     int hl = oracle_lowres_size(h, s), wl = oracle_lowres_size(w, s);
     int rl = oracle_lowres_radius(r, s);
     size_t n = (size_t)h * (size_t)w, nl = (size_t)hl * (size_t)wl;
@@ -281,9 +391,9 @@ int oracle_fast_guided_filter(const double *I, const double *p, int c, int h, in
         const double *pk = p + (size_t)k * n;
         double *qk = q + (size_t)k * n;
         if ((rc = oracle_subsample(pk, h, w, s, mode, pl))) goto done;
-        if ((rc = oracle_coefficients(Il, pl, hl, wl, rl, eps, a, b))) goto done;
-        if ((rc = oracle_box_mean(a, hl, wl, rl, ma))) goto done;
-        if ((rc = oracle_box_mean(b, hl, wl, rl, mb))) goto done;
+        if ((rc = coefficients(Il, pl, hl, wl, rl, eps, border, a, b))) goto done;
+        if ((rc = oracle_box_mean_border(a, hl, wl, rl, border, ma))) goto done;
+        if ((rc = oracle_box_mean_border(b, hl, wl, rl, border, mb))) goto done;
         if ((rc = oracle_upsample(ma, hl, wl, s, h, w, ua))) goto done;
         if ((rc = oracle_upsample(mb, hl, wl, s, h, w, ub))) goto done;
         for (size_t i = 0; i < n; ++i) qk[i] = ua[i] * I[i] + ub[i];
@@ -297,6 +407,15 @@ done:
     return rc;
 }
 
+int oracle_fast_guided_filter(const double *I, const double *p, int c, int h, int w, int r,
+                              int s, double eps, int mode, double *q, double *a_lo,
+                              double *b_lo, double *mean_a_lo, double *mean_b_lo)
+{
+    if (mode != ORACLE_NEAREST && mode != ORACLE_BILINEAR) return -1;
+    return oracle_fast_guided_filter_ex(I, p, c, h, w, r, s, eps, mode, ORACLE_CLIP, q, a_lo, b_lo,
+                                        mean_a_lo, mean_b_lo);
+}
+
 /*
  * Joint upsampling (the use of the subsampling the paper's introduction
  * mentions): the input is given at low resolution, p_lo with c channels of
@@ -304,12 +423,13 @@ done:
  * (Algorithm 2 step 1 for I alone).  Steps 2-7 of Algorithm 2 then run
  * unchanged with p' = p_lo: coefficients at r' = r/s, their box means,
  * bilinear upsampling, q = mean_a .* I + mean_b on the full-resolution I.
+ * Subsampling `mode` and border convention `border` as in the fast filter.
  */
-int oracle_joint_upsample(const double *I, const double *p_lo, int c, int h, int w, int r, int s,
-                          double eps, int mode, double *q)
+int oracle_joint_upsample_ex(const double *I, const double *p_lo, int c, int h, int w, int r, int s,
+                             double eps, int mode, int border, double *q)
 {
     if (h <= 0 || w <= 0 || c <= 0 || r < 0 || s < 1 || !(eps > 0.0)) return -1;
-    if (mode != ORACLE_NEAREST && mode != ORACLE_BILINEAR) return -1;
+    if (mode != ORACLE_NEAREST && mode != ORACLE_BILINEAR && mode != ORACLE_AREA) return -1;
     int hs = oracle_lowres_size(h, s), ws = oracle_lowres_size(w, s);
     int rs = oracle_lowres_radius(r, s);
     size_t n = (size_t)h * (size_t)w, ns = (size_t)hs * (size_t)ws;
@@ -327,9 +447,9 @@ int oracle_joint_upsample(const double *I, const double *p_lo, int c, int h, int
     for (int k = 0; k < c; ++k) {
         const double *pc = p_lo + (size_t)k * ns;                   /* p' is given */
         double *qc = q + (size_t)k * n;
-        if ((rc = oracle_coefficients(Is, pc, hs, ws, rs, eps, ak, bk))) goto done;
-        if ((rc = oracle_box_mean(ak, hs, ws, rs, mak))) goto done;
-        if ((rc = oracle_box_mean(bk, hs, ws, rs, mbk))) goto done;
+        if ((rc = coefficients(Is, pc, hs, ws, rs, eps, border, ak, bk))) goto done;
+        if ((rc = oracle_box_mean_border(ak, hs, ws, rs, border, mak))) goto done;
+        if ((rc = oracle_box_mean_border(bk, hs, ws, rs, border, mbk))) goto done;
         if ((rc = oracle_upsample(mak, hs, ws, s, h, w, uak))) goto done;
         if ((rc = oracle_upsample(mbk, hs, ws, s, h, w, ubk))) goto done;
         for (size_t i = 0; i < n; ++i) qc[i] = uak[i] * I[i] + ubk[i];
@@ -337,6 +457,13 @@ int oracle_joint_upsample(const double *I, const double *p_lo, int c, int h, int
 done:
     free(Is); free(ak); free(bk); free(mak); free(mbk); free(uak); free(ubk);
     return rc;
+}
+
+int oracle_joint_upsample(const double *I, const double *p_lo, int c, int h, int w, int r, int s,
+                          double eps, int mode, double *q)
+{
+    if (mode != ORACLE_NEAREST && mode != ORACLE_BILINEAR) return -1;
+    return oracle_joint_upsample_ex(I, p_lo, c, h, w, r, s, eps, mode, ORACLE_CLIP, q);
 }
 
 /*

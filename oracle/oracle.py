@@ -21,7 +21,13 @@ LIB = os.path.join(_HERE, "liboracle.so")
 
 NEAREST = 0
 BILINEAR = 1
-_MODES = {"nearest": NEAREST, "bilinear": BILINEAR, NEAREST: NEAREST, BILINEAR: BILINEAR}
+AREA = 2
+_MODES = {"nearest": NEAREST, "bilinear": BILINEAR, "area": AREA, NEAREST: NEAREST, BILINEAR: BILINEAR,
+          AREA: AREA}
+# window means: clip-normalised, or over the image padded by edge replication / reflect-101
+CLIP, REPLICATE, REFLECT101 = 0, 1, 2
+_BORDERS = {"clip": CLIP, "replicate": REPLICATE, "reflect101": REFLECT101, CLIP: CLIP,
+            REPLICATE: REPLICATE, REFLECT101: REFLECT101}
 
 # IEEE double arithmetic as written: no fast-math, no FMA contraction.
 CFLAGS = ["-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off"]
@@ -61,12 +67,16 @@ class Oracle:
             "oracle_lowres_radius": [i, i],
             "oracle_lowres_size": [i, i],
             "oracle_box_mean": [_DP, i, i, i, _DP],
+            "oracle_box_mean_border": [_DP, i, i, i, i, _DP],
             "oracle_subsample": [_DP, i, i, i, i, _DP],
             "oracle_upsample": [_DP, i, i, i, i, i, _DP],
             "oracle_coefficients": [_DP, _DP, i, i, i, d, _DP, _DP],
             "oracle_guided_filter": [_DP, _DP, i, i, i, i, d, _DP, _DP, _DP, _DP, _DP],
+            "oracle_guided_filter_ex": [_DP, _DP, i, i, i, i, d, i, _DP, _DP, _DP, _DP, _DP],
             "oracle_fast_guided_filter": [_DP, _DP, i, i, i, i, i, d, i, _DP, _DP, _DP, _DP, _DP],
+            "oracle_fast_guided_filter_ex": [_DP, _DP, i, i, i, i, i, d, i, i, _DP, _DP, _DP, _DP, _DP],
             "oracle_joint_upsample": [_DP, _DP, i, i, i, i, i, d, i, _DP],
+            "oracle_joint_upsample_ex": [_DP, _DP, i, i, i, i, i, d, i, i, _DP],
             "oracle_detail_enhance": [_DP, _DP, ctypes.c_size_t, d, _DP],
         }
         for name, args in sig.items():
@@ -83,12 +93,17 @@ class Oracle:
     def lowres_size(self, n: int, s: int) -> int:
         return int(self.lib.oracle_lowres_size(int(n), int(s)))
 
-    def box_mean(self, x, r: int) -> np.ndarray:
-        """Clip-normalised (2r+1)^2 box mean of a 2-D array."""
+    def box_mean(self, x, r: int, border="clip") -> np.ndarray:
+        """(2r+1)^2 box mean of a 2-D array: clip-normalised, or over the
+        image padded by replication / reflect-101."""
         x = _f64(x)
         h, w = x.shape
         out = np.empty_like(x)
-        _check(self.lib.oracle_box_mean(_ptr(x), h, w, int(r), _ptr(out)), "oracle_box_mean")
+        if _BORDERS[border] == CLIP:
+            _check(self.lib.oracle_box_mean(_ptr(x), h, w, int(r), _ptr(out)), "oracle_box_mean")
+        else:
+            _check(self.lib.oracle_box_mean_border(_ptr(x), h, w, int(r), _BORDERS[border], _ptr(out)),
+                   "oracle_box_mean_border")
         return out
 
     def subsample(self, x, s: int, mode="nearest") -> np.ndarray:
@@ -125,7 +140,7 @@ class Oracle:
         assert p.ndim == 3 and p.shape[1:] == (h, w), p.shape
         return p, False
 
-    def guided_filter(self, I, p, r: int, eps: float, intermediates: bool = False):
+    def guided_filter(self, I, p, r: int, eps: float, intermediates: bool = False, border="clip"):
         """Algorithm 1.  ``I`` is (h, w); ``p`` is (h, w) or (c, h, w).
 
         Returns q shaped like p, or (q, {a, b, mean_a, mean_b}).
@@ -137,16 +152,22 @@ class Oracle:
         q = np.empty_like(p3)
         ex = ({k: np.empty_like(p3) for k in ("a", "b", "mean_a", "mean_b")}
               if intermediates else {})
-        _check(self.lib.oracle_guided_filter(
-            _ptr(I), _ptr(p3), c, h, w, int(r), float(eps), _ptr(q),
-            _ptr(ex.get("a")), _ptr(ex.get("b")), _ptr(ex.get("mean_a")),
-            _ptr(ex.get("mean_b"))), "oracle_guided_filter")
+        if _BORDERS[border] == CLIP:
+            _check(self.lib.oracle_guided_filter(
+                _ptr(I), _ptr(p3), c, h, w, int(r), float(eps), _ptr(q),
+                _ptr(ex.get("a")), _ptr(ex.get("b")), _ptr(ex.get("mean_a")),
+                _ptr(ex.get("mean_b"))), "oracle_guided_filter")
+        else:
+            _check(self.lib.oracle_guided_filter_ex(
+                _ptr(I), _ptr(p3), c, h, w, int(r), float(eps), _BORDERS[border], _ptr(q),
+                _ptr(ex.get("a")), _ptr(ex.get("b")), _ptr(ex.get("mean_a")),
+                _ptr(ex.get("mean_b"))), "oracle_guided_filter_ex")
         if squeeze:
             q, ex = q[0], {k: v[0] for k, v in ex.items()}
         return (q, ex) if intermediates else q
 
     def fast_guided_filter(self, I, p, r: int, s: int, eps: float, mode="nearest",
-                           intermediates: bool = False):
+                           intermediates: bool = False, border="clip"):
         """Algorithm 2.  Low-resolution intermediates (a, b, mean_a, mean_b)
         come back at ceil(h/s) x ceil(w/s) when ``intermediates`` is set."""
         I = _f64(I)
@@ -157,16 +178,22 @@ class Oracle:
         q = np.empty_like(p3)
         ex = ({k: np.empty((c, hl, wl)) for k in ("a", "b", "mean_a", "mean_b")}
               if intermediates else {})
-        _check(self.lib.oracle_fast_guided_filter(
-            _ptr(I), _ptr(p3), c, h, w, int(r), int(s), float(eps), _MODES[mode], _ptr(q),
-            _ptr(ex.get("a")), _ptr(ex.get("b")), _ptr(ex.get("mean_a")),
-            _ptr(ex.get("mean_b"))), "oracle_fast_guided_filter")
+        if _BORDERS[border] == CLIP and _MODES[mode] != AREA:
+            _check(self.lib.oracle_fast_guided_filter(
+                _ptr(I), _ptr(p3), c, h, w, int(r), int(s), float(eps), _MODES[mode], _ptr(q),
+                _ptr(ex.get("a")), _ptr(ex.get("b")), _ptr(ex.get("mean_a")),
+                _ptr(ex.get("mean_b"))), "oracle_fast_guided_filter")
+        else:
+            _check(self.lib.oracle_fast_guided_filter_ex(
+                _ptr(I), _ptr(p3), c, h, w, int(r), int(s), float(eps), _MODES[mode], _BORDERS[border],
+                _ptr(q), _ptr(ex.get("a")), _ptr(ex.get("b")), _ptr(ex.get("mean_a")),
+                _ptr(ex.get("mean_b"))), "oracle_fast_guided_filter_ex")
         if squeeze:
             q, ex = q[0], {k: v[0] for k, v in ex.items()}
         return (q, ex) if intermediates else q
 
 
-    def joint_upsample(self, I, p_lo, r: int, s: int, eps: float, mode="nearest"):
+    def joint_upsample(self, I, p_lo, r: int, s: int, eps: float, mode="nearest", border="clip"):
         """Joint upsampling: ``p_lo`` (c, ceil(h/s), ceil(w/s)) or 2-D, guided
         by the full-resolution ``I`` (h, w).  Returns q at full resolution."""
         I = _f64(I)
@@ -178,8 +205,13 @@ class Oracle:
         assert p3.shape[1:] == (hl, wl), (p3.shape, hl, wl)
         c = p3.shape[0]
         q = np.empty((c, h, w))
-        _check(self.lib.oracle_joint_upsample(_ptr(I), _ptr(p3), c, h, w, int(r), int(s), float(eps),
-                                              _MODES[mode], _ptr(q)), "oracle_joint_upsample")
+        if _BORDERS[border] == CLIP and _MODES[mode] != AREA:
+            _check(self.lib.oracle_joint_upsample(_ptr(I), _ptr(p3), c, h, w, int(r), int(s), float(eps),
+                                                  _MODES[mode], _ptr(q)), "oracle_joint_upsample")
+        else:
+            _check(self.lib.oracle_joint_upsample_ex(_ptr(I), _ptr(p3), c, h, w, int(r), int(s), float(eps),
+                                                     _MODES[mode], _BORDERS[border], _ptr(q)),
+                   "oracle_joint_upsample_ex")
         return q[0] if squeeze else q
 
     def detail_enhance(self, p, q, gain: float):
@@ -213,8 +245,8 @@ def lowres_size(n, s):
     return default().lowres_size(n, s)
 
 
-def box_mean(x, r):
-    return default().box_mean(x, r)
+def box_mean(x, r, border="clip"):
+    return default().box_mean(x, r, border)
 
 
 def subsample(x, s, mode="nearest"):
@@ -229,16 +261,16 @@ def coefficients(I, p, r, eps):
     return default().coefficients(I, p, r, eps)
 
 
-def guided_filter(I, p, r, eps, intermediates=False):
-    return default().guided_filter(I, p, r, eps, intermediates)
+def guided_filter(I, p, r, eps, intermediates=False, border="clip"):
+    return default().guided_filter(I, p, r, eps, intermediates, border)
 
 
-def fast_guided_filter(I, p, r, s, eps, mode="nearest", intermediates=False):
-    return default().fast_guided_filter(I, p, r, s, eps, mode, intermediates)
+def fast_guided_filter(I, p, r, s, eps, mode="nearest", intermediates=False, border="clip"):
+    return default().fast_guided_filter(I, p, r, s, eps, mode, intermediates, border)
 
 
-def joint_upsample(I, p_lo, r, s, eps, mode="nearest"):
-    return default().joint_upsample(I, p_lo, r, s, eps, mode)
+def joint_upsample(I, p_lo, r, s, eps, mode="nearest", border="clip"):
+    return default().joint_upsample(I, p_lo, r, s, eps, mode, border)
 
 
 def detail_enhance(p, q, gain):

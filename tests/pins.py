@@ -432,4 +432,148 @@ def pin_detail_gain_endpoints(orc):
     _close(orc.detail_enhance(c, orc.fast_guided_filter(I, c, 8, 4, 1e-2), 5.0), c, 1e-15, "constant input")
 
 
+# ---------------------------------------------------------------- borders and area subsampling
+
+_NP_PAD = {"replicate": "edge", "reflect101": "reflect"}     # numpy's names for the same extensions
+_SCIPY_MODE = {"replicate": "nearest", "reflect101": "mirror"}
+
+
+def padded_window_mean(x, r, border):
+    """Literal mean of every (2r+1)^2 window of the image padded by numpy."""
+    from numpy.lib.stride_tricks import sliding_window_view
+    xp = np.pad(np.asarray(x, dtype=np.float64), r, mode=_NP_PAD[border])
+    return sliding_window_view(xp, (2 * r + 1, 2 * r + 1)).mean(axis=(-1, -2))
+
+
+def lib_box(x, r, border):
+    """Box mean by scipy: clip-normalised, or its uniform filter in the padded modes."""
+    if border == "clip":
+        return scipy_box(x, r)
+    return ndi.uniform_filter(np.asarray(x, dtype=np.float64), size=2 * r + 1, mode=_SCIPY_MODE[border])
+
+
+def torch_area_sub(x, s):
+    """Mean of each s x s block (blocks at a ragged edge averaged over their in-image part)."""
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64))[None, None]
+    return F.avg_pool2d(t, kernel_size=s, stride=s, ceil_mode=True)[0, 0].numpy()
+
+
+def lib_sub(x, s, mode):
+    return torch_area_sub(x, s) if mode == "area" else torch_sub(x, s, mode)
+
+
+def composed_general(I, p_lo, r, s, eps, mode, border, joint=False):
+    """Algorithm 2 from library routines for any subsampling and border:
+    torch subsampling (or average pooling), scipy box means, torch upsample.
+    With joint, p_lo is the low-res input and only I is subsampled."""
+    h, w = I.shape
+    rl = 0 if r == 0 else max(1, int(math.floor(r / s + 0.5)))
+    Il = lib_sub(I, s, mode) if s > 1 else I
+    pl = p_lo if (joint or s == 1) else lib_sub(p_lo, s, mode)
+    mI, mp = lib_box(Il, rl, border), lib_box(pl, rl, border)
+    cI, cIp = lib_box(Il * Il, rl, border), lib_box(Il * pl, rl, border)
+    a = (cIp - mI * mp) / (cI - mI * mI + eps)
+    b = mp - a * mI
+    ma, mb = lib_box(a, rl, border), lib_box(b, rl, border)
+    if s == 1:
+        return ma * I + mb
+    return torch_upsample(ma, s, h, w) * I + torch_upsample(mb, s, h, w)
+
+
+def pin_box_padded_numpy(orc):
+    """Padded box means equal the literal window mean over numpy's edge /
+    reflect padding, also for windows wider than the image (repeated
+    reflection) and one-pixel axes."""
+    g = _rng(41)
+    for h, w in [(1, 1), (1, 7), (6, 1), (3, 5), (8, 8), (12, 9), (2, 2)]:
+        x = _dyadic(g, (h, w))
+        for r in [0, 1, 2, 5, 13]:
+            for border in ("replicate", "reflect101"):
+                _close(orc.box_mean(x, r, border), padded_window_mean(x, r, border), 4e-16,
+                       f"padded box {border} {h}x{w} r={r}")
+
+
+def pin_box_padded_scipy(orc):
+    """Padded box means equal scipy's uniform filter in 'nearest' (replicate)
+    and 'mirror' (reflect-101) modes."""
+    g = _rng(42)
+    x = g.uniform(-1, 2, size=(23, 31))
+    for r in [1, 4, 11, 40]:
+        for border in ("replicate", "reflect101"):
+            _close(orc.box_mean(x, r, border), lib_box(x, r, border), 1e-12, f"scipy box {border} r={r}")
+
+
+def pin_area_subsample_pool(orc):
+    """Area subsampling equals torch's average pooling with an s x s window and
+    stride s (ceil mode: the ragged last block is averaged over its in-image
+    part), and a reshape-mean when s divides the sides."""
+    g = _rng(43)
+    for h, w in [(16, 24), (13, 10), (9, 17), (1, 9), (7, 1)]:
+        x = g.uniform(0, 1, size=(h, w))
+        for s in [1, 2, 3, 4, 5, 8]:
+            _close(orc.subsample(x, s, "area"), torch_area_sub(x, s), 1e-15, f"area s={s} {h}x{w}")
+    x = g.uniform(0, 1, size=(24, 32))
+    _close(orc.subsample(x, 4, "area"), x.reshape(6, 4, 8, 4).mean(axis=(1, 3)), 1e-15, "area reshape")
+
+
+def pin_border_area_composition(orc):
+    """The plain and fast filters and joint upsampling under every border and
+    subsampling convention equal their assembly from library routines."""
+    g = _rng(44)
+    cases = [((37, 45), 8, 4, 1e-2, "nearest", "replicate"), ((37, 45), 8, 4, 1e-2, "bilinear", "reflect101"),
+             ((30, 21), 5, 2, 1e-3, "area", "clip"), ((29, 33), 6, 3, 1e-1, "area", "reflect101"),
+             ((13, 50), 12, 4, 1e-2, "area", "replicate"), ((40, 40), 3, 1, 1e-2, "nearest", "reflect101"),
+             ((9, 11), 6, 1, 1e-2, "nearest", "replicate"), ((10, 12), 24, 8, 1e-2, "nearest", "reflect101")]
+    for (h, w), r, s, eps, mode, border in cases:
+        I = g.uniform(0, 1, size=(h, w))
+        p = np.clip(I + g.normal(0, 0.1, size=(h, w)), 0, 1)
+        what = f"{h}x{w} r={r} s={s} {mode} {border}"
+        _close(orc.fast_guided_filter(I, p, r, s, eps, mode, border=border),
+               composed_general(I, p, r, s, eps, mode, border), 1e-11, "fast " + what)
+        if s == 1:
+            _close(orc.guided_filter(I, p, r, eps, border=border), composed_general(I, p, r, 1, eps, mode, border),
+                   1e-11, "plain " + what)
+        else:
+            p_lo = g.uniform(0, 1, size=(-(-h // s), -(-w // s)))
+            _close(orc.joint_upsample(I, p_lo, r, s, eps, mode, border=border),
+                   composed_general(I, p_lo, r, s, eps, mode, border, joint=True), 1e-11, "joint " + what)
+
+
+def pin_padded_coefficients_lstsq(orc):
+    """With a padded border, a_k, b_k solve the ridge regression over the
+    (2r+1)^2 samples of the padded window (edge samples counted as often as
+    the padding repeats them)."""
+    g = _rng(45)
+    h, w = 6, 7
+    I = g.uniform(0, 1, size=(h, w))
+    p = 0.6 * I + g.uniform(0, 0.5, size=(h, w))
+    for border in ("replicate", "reflect101"):
+        for r, eps in [(1, 1e-2), (3, 0.2), (8, 1e-3)]:
+            _, ex = orc.guided_filter(I, p, r, eps, intermediates=True, border=border)
+            Ip, pp = np.pad(I, r, mode=_NP_PAD[border]), np.pad(p, r, mode=_NP_PAD[border])
+            n = (2 * r + 1) ** 2
+            for ky, kx in [(0, 0), (0, w - 1), (h - 1, 3), (2, 3), (h - 1, w - 1)]:
+                Iw = Ip[ky:ky + 2 * r + 1, kx:kx + 2 * r + 1].ravel()
+                pw = pp[ky:ky + 2 * r + 1, kx:kx + 2 * r + 1].ravel()
+                A = np.vstack([np.stack([Iw, np.ones(n)], 1), [[math.sqrt(n * eps), 0.0]]])
+                sol = np.linalg.lstsq(A, np.concatenate([pw, [0.0]]), rcond=None)[0]
+                assert abs(ex["a"][ky, kx] - sol[0]) < 1e-10, (border, r, ky, kx, ex["a"][ky, kx], sol[0])
+                assert abs(ex["b"][ky, kx] - sol[1]) < 1e-10, (border, r, ky, kx, ex["b"][ky, kx], sol[1])
+
+
+def pin_border_constant(orc):
+    """A constant input is returned exactly under every border; with a
+    constant guide, q is the border's box mean of the box mean of p."""
+    g = _rng(46)
+    I = g.uniform(0, 1, size=(19, 26))
+    for border in ("replicate", "reflect101"):
+        for mode in ("nearest", "area"):
+            _close(orc.fast_guided_filter(I, np.full((19, 26), 0.375), 8, 4, 1e-3, mode, border=border),
+                   np.full((19, 26), 0.375), 1e-14, f"constant p {border} {mode}")
+        p = g.uniform(0, 1, size=(19, 26))
+        exp = padded_window_mean(padded_window_mean(p, 3, border), 3, border)
+        _close(orc.guided_filter(np.full((19, 26), 0.5), p, 3, 1e-2, border=border), exp, 1e-14,
+               f"constant guide {border}")
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -23,11 +23,12 @@ MUTANTS = {
     "eps_halved": ("cov_Ip / (var_I + eps)", "cov_Ip / (var_I + 0.5 * eps)"),
     "b_sign": ("mean_p[i] - a[i] * mean_I[i]", "mean_p[i] + a[i] * mean_I[i]"),
     "corr_Ip_is_corr_I": ("tmp[i] = I[i] * p[i]", "tmp[i] = I[i] * I[i]"),
-    "mean_b_from_a": ("oracle_box_mean(b, h, w, r, mb)", "oracle_box_mean(a, h, w, r, mb)"),
+    "mean_b_from_a": ("oracle_box_mean_border(b, h, w, r, border, mb)", "oracle_box_mean_border(a, h, w, r, border, mb)"),
     "plain_output_swapped": ("qk[i] = ma[i] * I[i] + mb[i]", "qk[i] = mb[i] * I[i] + ma[i]"),
-    "fast_uses_full_radius": ("oracle_coefficients(Il, pl, hl, wl, rl, eps, a, b)",
-                              "oracle_coefficients(Il, pl, hl, wl, r, eps, a, b)"),
-    "fast_skips_coefficient_mean": ("oracle_box_mean(a, hl, wl, rl, ma)", "oracle_box_mean(a, hl, wl, 0, ma)"),
+    "fast_uses_full_radius": ("coefficients(Il, pl, hl, wl, rl, eps, border, a, b)",
+                              "coefficients(Il, pl, hl, wl, r, eps, border, a, b)"),
+    "fast_skips_coefficient_mean": ("oracle_box_mean_border(a, hl, wl, rl, border, ma)",
+                                    "oracle_box_mean_border(a, hl, wl, 0, border, ma)"),
     "lowres_radius_truncates": ("int rl = (2 * r + s) / (2 * s);", "int rl = r / s;"),
     "nearest_top_left": ("*t0 = imin(s * j + s / 2, n - 1);", "*t0 = imin(s * j, n - 1);"),
     "bilinear_centre": ("double u = (double)s * j + 0.5 * (double)(s - 1);",
@@ -38,13 +39,27 @@ MUTANTS = {
                               "(1.0 - wx) * ((1.0 - wy) * v00 + wy * v01) + wx * ((1.0 - wy) * v10 + wy * v11);\n        }\n    }\n    return 0;\n}\n\n/*\n * Algorithm 1"),
     "upsample_wrong_tap": ("int ya = iclamp((int)fu, 0, hl - 1)", "int ya = iclamp((int)fu + 1, 0, hl - 1)"),
     "fast_output_uses_mean_b_twice": ("qk[i] = ua[i] * I[i] + ub[i]", "qk[i] = ub[i] * I[i] + ub[i]"),
-    "joint_uses_full_radius": ("oracle_coefficients(Is, pc, hs, ws, rs, eps, ak, bk)",
-                               "oracle_coefficients(Is, pc, hs, ws, r, eps, ak, bk)"),
+    "joint_uses_full_radius": ("coefficients(Is, pc, hs, ws, rs, eps, border, ak, bk)",
+                               "coefficients(Is, pc, hs, ws, r, eps, border, ak, bk)"),
     "joint_output_swapped": ("qc[i] = uak[i] * I[i] + ubk[i]", "qc[i] = ubk[i] * I[i] + uak[i]"),
     "joint_guide_wrong_mode": ("oracle_subsample(I, h, w, s, mode, Is)", "oracle_subsample(I, h, w, s, 1 - mode, Is)"),
-    "joint_skips_b_mean": ("oracle_box_mean(bk, hs, ws, rs, mbk)", "oracle_box_mean(bk, hs, ws, 0, mbk)"),
+    "joint_skips_b_mean": ("oracle_box_mean_border(bk, hs, ws, rs, border, mbk)",
+                           "oracle_box_mean_border(bk, hs, ws, 0, border, mbk)"),
     "detail_sign": ("e[i] = q[i] + gain * (p[i] - q[i])", "e[i] = q[i] + gain * (q[i] - p[i])"),
     "detail_base_is_input": ("e[i] = q[i] + gain * (p[i] - q[i])", "e[i] = p[i] + gain * (p[i] - q[i])"),
+    "reflect_repeats_low_edge": ("if (i < 0) i = -i;", "if (i < 0) i = -i - 1;"),
+    "reflect_repeats_high_edge": ("if (i > n - 1) i = 2 * (n - 1) - i;", "if (i > n - 1) i = 2 * n - 1 - i;"),
+    "replicate_wraps_around": ("if (border == ORACLE_REPLICATE) return iclamp(i, 0, n - 1);",
+                               "if (border == ORACLE_REPLICATE) return (i % n + n) % n;"),
+    "padded_count_short": ("const double count = (double)(2 * r + 1) * (double)(2 * r + 1);",
+                           "const double count = (double)(2 * r + 1) * (double)(2 * r);"),
+    "padded_row_window_short": ("for (int k = -r; k <= r; ++k) acc += x[", "for (int k = -r; k < r; ++k) acc += x["),
+    "padded_column_reflects_rows_only": ("acc += rowsum[(size_t)border_index(y + k, h, border) * w + xx]",
+                                         "acc += rowsum[(size_t)iclamp(y + k, 0, h - 1) * w + xx]"),
+    "fast_ignores_border": ("if ((rc = coefficients(Il, pl, hl, wl, rl, eps, border, a, b))) goto done;",
+                            "if ((rc = coefficients(Il, pl, hl, wl, rl, eps, ORACLE_CLIP, a, b))) goto done;"),
+    "area_divides_by_full_block": ("acc / ((double)(y1 - y0) * (double)(x1 - x0))", "acc / ((double)s * (double)s)"),
+    "area_block_shifted": ("int x0 = s * xx, x1 = imin(w, s * xx + s);", "int x0 = s * xx + s / 2, x1 = imin(w, s * xx + s);"),
 }
 
 
