@@ -211,32 +211,35 @@ def measure_apps(gfp, torch, dev, I_np, p_np, steps=50, with_oracle=True):
     plo_np = np.stack([0.5 + 0.3 * np.sin(3 * yy + 2 * k) * np.cos(4 * xx - k) for k in range(c)]).astype(np.float32)
     mask_np = (I_np > 0.5).astype(np.float32)  # feathering: a hard mask refined along the guide's edges
     specs = [
-        # name, op, input, channels, r, eps, extra, output-pass bytes per full-res pixel (+ low-res maps)
-        ("detail_enhancement", "detail", p_np, c, 16, 0.1 ** 2, 5.0),
-        ("flash_no_flash", "fast", p_np, c, 8, 0.02 ** 2, None),
-        ("feathering", "fast", mask_np[None], 1, 60, 0.001 ** 2, None),
-        ("joint_upsampling", "joint", plo_np, c, 16, 1e-3, None),
+        # name, op, input, channels, r, eps, gain, subsampling, border
+        ("detail_enhancement", "detail", p_np, c, 16, 0.1 ** 2, 5.0, "nearest", "clip"),
+        ("flash_no_flash", "fast", p_np, c, 8, 0.02 ** 2, None, "nearest", "clip"),
+        ("feathering", "fast", mask_np[None], 1, 60, 0.001 ** 2, None, "nearest", "clip"),
+        ("joint_upsampling", "joint", plo_np, c, 16, 1e-3, None, "nearest", "clip"),
+        ("area_subsampling", "fast", p_np, c, 16, 1e-2, None, "area", "clip"),
+        ("reflect101_border", "fast", p_np, c, 16, 1e-2, None, "nearest", "reflect101"),
     ]
     out = {"workload": "4000x3000 gray guide, fp32, s=4 (nearest); detail enhancement r=16 eps=0.1^2 gain 5 "
                        "on RGB p; flash/no-flash r=8 eps=0.02^2 on RGB p; feathering r=60 eps=0.001^2 on a "
-                       "binary mask; joint upsampling of a 1000x750 RGB input, r=16 eps=1e-3"}
-    for name, op, x_np, cc, r, eps, gain in specs:
+                       "binary mask; joint upsampling of a 1000x750 RGB input, r=16 eps=1e-3; the headline "
+                       "filter (RGB p, r=16, eps=1e-2) with area subsampling and with a reflect-101 border"}
+    for name, op, x_np, cc, r, eps, gain, sub, border in specs:
         sets = []
         for k in range(4):  # 4 rotated sets: inputs are not served from the last-level cache
             dI = torch.from_numpy(I_np).to(dev)
             dx = torch.from_numpy(np.ascontiguousarray(x_np)).to(dev)
             sets.append((dI, dx, torch.empty((cc, h, w), dtype=torch.float32, device=dev)))
         ctx = gfp.Context(0)
-        ws = torch.empty(gfp.workspace_bytes(h, w, cc, r, s, eps), dtype=torch.uint8, device=dev)
+        ws = torch.empty(gfp.workspace_bytes(h, w, cc, r, s, eps, sub, border), dtype=torch.uint8, device=dev)
 
         def step(i):
             dI, dx, q = sets[i % len(sets)]
             if op == "fast":
-                gfp.gf_fast(dI, dx, r, s, eps, q=q, ctx=ctx, workspace=ws)
+                gfp.gf_fast(dI, dx, r, s, eps, sub, q=q, ctx=ctx, workspace=ws, border=border)
             elif op == "detail":
-                gfp.gf_detail_enhance(dI, dx, r, s, eps, gain, e=q, ctx=ctx, workspace=ws)
+                gfp.gf_detail_enhance(dI, dx, r, s, eps, gain, sub, e=q, ctx=ctx, workspace=ws, border=border)
             else:
-                gfp.gf_joint_upsample(dI, dx, r, s, eps, q=q, ctx=ctx, workspace=ws)
+                gfp.gf_joint_upsample(dI, dx, r, s, eps, sub, q=q, ctx=ctx, workspace=ws, border=border)
         for i in range(5):
             step(i)
         torch.cuda.synchronize()
@@ -262,6 +265,15 @@ def measure_apps(gfp, torch, dev, I_np, p_np, steps=50, with_oracle=True):
                                "algorithmic_bytes_per_launch": ob}}
         if gain is not None:
             res["gain"] = gain
+        if sub != "nearest" or border != "clip":
+            res.update(subsampling=sub, border=border)
+        if "area" in kt and kt["area"][1]:
+            # area pass: all of I and p read, 1 + C low-res FP32 planes written
+            ab = h * w * 4 * (1 + cc) + (1 + cc) * hl * wl * 4
+            a_ms = kt["area"][0] / kt["area"][1]
+            res["area_pass"] = {"achieved_GBs": round(ab / (a_ms * 1e-3) / 1e9, 1),
+                                "frac": round(ab / (a_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                "algorithmic_bytes_per_launch": ab}
         if with_oracle:
             from oracle import oracle
             dI, dx, q = sets[0]
@@ -269,9 +281,9 @@ def measure_apps(gfp, torch, dev, I_np, p_np, steps=50, with_oracle=True):
             torch.cuda.synchronize()
             I64, x64 = I_np.astype(np.float64), np.asarray(x_np, dtype=np.float64)
             if op == "joint":
-                exp = oracle.joint_upsample(I64, x64, r, s, eps)
+                exp = oracle.joint_upsample(I64, x64, r, s, eps, sub, border=border)
             else:
-                exp = oracle.fast_guided_filter(I64, x64, r, s, eps)
+                exp = oracle.fast_guided_filter(I64, x64, r, s, eps, sub, border=border)
                 if op == "detail":
                     exp = oracle.detail_enhance(x64, exp, gain)
             res["max_abs_err"] = float(np.max(np.abs(q.double().cpu().numpy() - exp)))

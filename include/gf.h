@@ -29,6 +29,18 @@
  *     taps clamped to the low-res map;
  *   - a multi-channel p is filtered channel by channel with the same gray I.
  *
+ * Options for the conventions of other image libraries (gf_params):
+ *   - GF_BORDER_REPLICATE / GF_BORDER_REFLECT101: every box mean (of the
+ *     statistics and of a, b) reads the map extended past its edges, by
+ *     repeating the edge pixel or by mirroring about it without repeating it
+ *     (... 2 1 | 0 1 ... n-1 | n-2 ..., repeated for windows wider than the
+ *     map), and divides by (2r+1)^2.  Upsampling still clamps its taps;
+ *   - GF_SUB_AREA: the low-res pixel (y, x) is the mean of the full-res
+ *     block [s*y, s*y+s) x [s*x, s*x+s) clipped to the image.  It reads all
+ *     of I and p, in a pass of its own (FP64 block sums, the mean stored as
+ *     FP32 in the workspace); batched launches of a batch that holds such an
+ *     image run image by image, and gf_submit refuses it.
+ *
  * Arithmetic: all window sums, coefficients and interpolation in FP32
  * (window sums of mean-shifted values, tile by tile); images may be stored as
  * FP32, FP16 or BF16, and 16-bit outputs are rounded to nearest even.
@@ -67,7 +79,7 @@ typedef enum {
     GF_EINVAL = -1,     /* invalid argument, shape, stride, aliasing or ticket */
     GF_ENOMEM = -2,     /* workspace too small, or the request can never fit the arena */
     GF_EBUSY = -3,      /* request queue full; try again after polling */
-    GF_ENOTSUP = -4,    /* valid but unsupported option (border, radius too large) */
+    GF_ENOTSUP = -4,    /* valid but unsupported option (colour guide, radius too large) */
     GF_EDEVICE = -5,    /* a HIP call failed */
     GF_ETIMEDOUT = -6   /* gf_poll: wait time elapsed */
 } gf_status;
@@ -75,10 +87,12 @@ typedef enum {
 typedef enum { GF_F32 = 0, GF_F16 = 1, GF_BF16 = 2 } gf_dtype;
 
 typedef enum {
-    GF_BORDER_CLIP = 0  /* window clipped to the image, mean over in-image pixels */
+    GF_BORDER_CLIP = 0,       /* window clipped to the image, mean over in-image pixels */
+    GF_BORDER_REPLICATE = 1,  /* image extended by its edge pixels, mean over (2r+1)^2 */
+    GF_BORDER_REFLECT101 = 2  /* image mirrored about its edge pixels, mean over (2r+1)^2 */
 } gf_border;
 
-typedef enum { GF_SUB_NEAREST = 0, GF_SUB_BILINEAR = 1 } gf_subsample;
+typedef enum { GF_SUB_NEAREST = 0, GF_SUB_BILINEAR = 1, GF_SUB_AREA = 2 } gf_subsample;
 
 /*
  * A c x h x w image in device memory.  Element (k, y, x) is at
@@ -319,7 +333,8 @@ typedef enum {
     GF_K_BOX = 1,     /* box means of a, b (step 5) */
     GF_K_OUTPUT = 2,  /* bilinear upsample + q = mean_a*I + mean_b (steps 6-7) */
     GF_K_BATCHED = 3, /* the persistent kernel of gf_fast_batched */
-    GF_NKERNELS = 4
+    GF_K_AREA = 4,    /* area subsampling of I and p (GF_SUB_AREA only) */
+    GF_NKERNELS = 5
 } gf_kernel_id;
 
 typedef struct {

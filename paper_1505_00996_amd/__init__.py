@@ -24,9 +24,10 @@ GF_EINVAL, GF_ENOMEM, GF_EBUSY, GF_ENOTSUP, GF_EDEVICE, GF_ETIMEDOUT = -1, -2, -
 STATUS_NAMES = {0: "GF_OK", 1: "GF_PENDING", -1: "GF_EINVAL", -2: "GF_ENOMEM", -3: "GF_EBUSY",
                 -4: "GF_ENOTSUP", -5: "GF_EDEVICE", -6: "GF_ETIMEDOUT"}
 GF_F32, GF_F16, GF_BF16 = 0, 1, 2
-GF_BORDER_CLIP = 0
-GF_SUB_NEAREST, GF_SUB_BILINEAR = 0, 1
-SUBSAMPLE = {"nearest": GF_SUB_NEAREST, "bilinear": GF_SUB_BILINEAR}
+GF_BORDER_CLIP, GF_BORDER_REPLICATE, GF_BORDER_REFLECT101 = 0, 1, 2
+BORDERS = {"clip": GF_BORDER_CLIP, "replicate": GF_BORDER_REPLICATE, "reflect101": GF_BORDER_REFLECT101}
+GF_SUB_NEAREST, GF_SUB_BILINEAR, GF_SUB_AREA = 0, 1, 2
+SUBSAMPLE = {"nearest": GF_SUB_NEAREST, "bilinear": GF_SUB_BILINEAR, "area": GF_SUB_AREA}
 
 # Every symbol include/gf.h declares.
 EXPORTS = ("gf_ctx_create", "gf_ctx_destroy", "gf_last_error", "gf_workspace_bytes", "gf_plain",
@@ -35,7 +36,7 @@ EXPORTS = ("gf_ctx_create", "gf_ctx_destroy", "gf_last_error", "gf_workspace_byt
            "gf_ctx_save_tuning", "gf_ctx_load_tuning", "gf_batch_create", "gf_batch_launch",
            "gf_batch_destroy", "gf_ctx_set_batch_cfg", "gf_tune_batched", "gf_footprint_bytes", "gf_joint_upsample",
            "gf_detail_enhance")
-KERNELS = ("coeff", "box", "output", "batched")
+KERNELS = ("coeff", "box", "output", "batched", "area")
 
 
 class gf_image(ctypes.Structure):
@@ -183,8 +184,9 @@ def image(t) -> gf_image:
     return gf_image(t.data_ptr(), _dtype_code(t), c, h, w, rs, ps)
 
 
-def params(r: int, s: int, eps: float, sub: str | int = "nearest") -> gf_params:
-    return gf_params(int(r), int(s), float(eps), GF_BORDER_CLIP,
+def params(r: int, s: int, eps: float, sub: str | int = "nearest", border: str | int = "clip") -> gf_params:
+    """Filter parameters; ``sub`` in SUBSAMPLE, ``border`` in BORDERS (or their codes)."""
+    return gf_params(int(r), int(s), float(eps), BORDERS[border] if isinstance(border, str) else int(border),
                      SUBSAMPLE[sub] if isinstance(sub, str) else int(sub))
 
 
@@ -197,8 +199,8 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def workspace_bytes(h: int, w: int, c: int, r: int, s: int, eps: float, sub="nearest") -> int:
-    return int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(params(r, s, eps, sub))))
+def workspace_bytes(h: int, w: int, c: int, r: int, s: int, eps: float, sub="nearest", border="clip") -> int:
+    return int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(params(r, s, eps, sub, border))))
 
 
 def _workspace(nbytes: int, device):
@@ -217,11 +219,11 @@ def _out_like(p, q):
 
 
 def gf_fast(I, p, r: int, s: int, eps: float, sub: str = "nearest", q=None, ctx=None,
-            workspace=None, stream=None):
+            workspace=None, stream=None, border: str = "clip"):
     """Algorithm 2 on the GPU: returns q (shape of p).  ``I`` is (H, W);
     ``p`` is (H, W) or (C, H, W); same dtype (float32 / float16 / bfloat16)."""
     q = _out_like(p, q)
-    pr = params(r, s, eps, sub)
+    pr = params(r, s, eps, sub, border)
     h, w = I.shape[-2:]
     c = 1 if p.dim() == 2 else p.shape[0]
     need = int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(pr)))
@@ -234,14 +236,14 @@ def gf_fast(I, p, r: int, s: int, eps: float, sub: str = "nearest", q=None, ctx=
 
 
 def gf_joint_upsample(I, p_low, r: int, s: int, eps: float, sub: str = "nearest", q=None, ctx=None,
-                      workspace=None, stream=None):
+                      workspace=None, stream=None, border: str = "clip"):
     """Joint upsampling: ``p_low`` (c, ceil(h/s), ceil(w/s)) or 2-D, guided by
     ``I`` (h, w); returns q at full resolution (c, h, w) or (h, w)."""
     h, w = I.shape[-2:]
     if q is None:
         import torch
         q = torch.empty(p_low.shape[:-2] + (h, w), dtype=p_low.dtype, device=p_low.device)
-    pr = params(r, s, eps, sub)
+    pr = params(r, s, eps, sub, border)
     c = 1 if p_low.dim() == 2 else p_low.shape[0]
     if workspace is None:
         workspace = _workspace(int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(pr))), I.device)
@@ -252,11 +254,11 @@ def gf_joint_upsample(I, p_low, r: int, s: int, eps: float, sub: str = "nearest"
 
 
 def gf_detail_enhance(I, p, r: int, s: int, eps: float, gain: float, sub: str = "nearest", e=None, ctx=None,
-                      workspace=None, stream=None):
+                      workspace=None, stream=None, border: str = "clip"):
     """Detail enhancement: e = q + gain (p - q) with q the fast filter of p
     (plain at s = 1).  Returns e (shape of p)."""
     e = _out_like(p, e)
-    pr = params(r, s, eps, sub)
+    pr = params(r, s, eps, sub, border)
     h, w = I.shape[-2:]
     c = 1 if p.dim() == 2 else p.shape[0]
     if workspace is None:
@@ -268,17 +270,17 @@ def gf_detail_enhance(I, p, r: int, s: int, eps: float, gain: float, sub: str = 
     return e
 
 
-def gf_plain(I, p, r: int, eps: float, q=None, ctx=None, workspace=None, stream=None):
+def gf_plain(I, p, r: int, eps: float, q=None, ctx=None, workspace=None, stream=None, border: str = "clip"):
     """Algorithm 1 on the GPU (full resolution): returns q (shape of p)."""
     q = _out_like(p, q)
-    pr = params(r, 1, eps)
+    pr = params(r, 1, eps, "nearest", border)
     h, w = I.shape[-2:]
     c = 1 if p.dim() == 2 else p.shape[0]
     need = int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(pr)))
     if workspace is None:
         workspace = _workspace(need, p.device)
     _check(lib().gf_plain(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p)),
-                          ctypes.byref(image(q)), int(r), float(eps), GF_BORDER_CLIP,
+                          ctypes.byref(image(q)), int(r), float(eps), pr.border,
                           ctypes.c_void_p(workspace.data_ptr()),
                           workspace.numel() * workspace.element_size(), _stream(stream)), ctx)
     return q
@@ -293,9 +295,9 @@ def _arrays(Is, ps, qs, prs):
 
 
 def footprint_bytes(h: int, w: int, c: int, r: int, s: int, eps: float, dtype: int = GF_F32,
-                    sub="nearest") -> int:
+                    sub="nearest", border="clip") -> int:
     """Arena bytes one request of this shape occupies (gf_footprint_bytes)."""
-    return int(lib().gf_footprint_bytes(h, w, c, dtype, ctypes.byref(params(r, s, eps, sub))))
+    return int(lib().gf_footprint_bytes(h, w, c, dtype, ctypes.byref(params(r, s, eps, sub, border))))
 
 
 def batched_workspace_bytes(Is, ps, prs) -> int:
@@ -418,13 +420,13 @@ class Context:
                                       ctypes.byref(t) if t is not None else None), self)
 
     def tune(self, I, p, r: int, s: int, eps: float, sub: str = "nearest", q=None, reps: int = 5,
-             stream=None):
+             stream=None, border: str = "clip"):
         """Autotune the window-sum kernels for this problem's class.
         Returns (best tiles dict, [(kernel, tiles dict, ms), ...])."""
         q = _out_like(p, q)
         h, w = I.shape[-2:]
         c = 1 if p.dim() == 2 else p.shape[0]
-        pr = params(r, s, eps, sub)
+        pr = params(r, s, eps, sub, border)
         ws = _workspace(lib().gf_workspace_bytes(h, w, c, ctypes.byref(pr)), p.device)
         best = gf_tiles()
         res = (gf_tune_result * 64)()
@@ -468,12 +470,12 @@ class Context:
                                      int(reps), ctypes.byref(best), res, 16, ctypes.byref(cnt)), self)
         return best.as_dict(), [(res[i].cfg.as_dict(), res[i].ms) for i in range(cnt.value)]
 
-    def gf_submit(self, I, p, q, r: int, s: int, eps: float, sub: str = "nearest") -> int:
+    def gf_submit(self, I, p, q, r: int, s: int, eps: float, sub: str = "nearest", border: str = "clip") -> int:
         """Queue a request; returns its ticket.  I, p, q are kept alive here
         until gf_poll reports the request finished."""
         t = ctypes.c_uint64()
         _check(lib().gf_submit(self._h, ctypes.byref(image(I)), ctypes.byref(image(p)),
-                               ctypes.byref(image(q)), ctypes.byref(params(r, s, eps, sub)),
+                               ctypes.byref(image(q)), ctypes.byref(params(r, s, eps, sub, border)),
                                ctypes.byref(t)), self)
         self._keep[t.value] = (I, p, q)
         return t.value

@@ -7,6 +7,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -36,17 +37,39 @@ int lowres_radius(int r, int s) {
     return rl < 1 ? 1 : rl;
 }
 
-Geo make_geo(int H, int W, int C, int r, int s, double eps, int sub) {
+// Applications of the reflection F(m) = (n-1) - |(n-1) - |m|| that bring
+// every position in [-R, n-1+R] into [0, n) (the device applies them in
+// pad_index); 1 when the window is no wider than the axis allows.
+static int reflections(int n, int R) {
+    if (n <= 1) return 1;
+    int most = 1;
+    for (int i : {-R, n - 1 + R}) {
+        int m = i, k = 0;
+        do {
+            m = n - 1 - std::abs(n - 1 - std::abs(m));
+            ++k;
+        } while (m < 0 || m > n - 1);
+        most = std::max(most, k);
+    }
+    return most;
+}
+
+Geo make_geo(int H, int W, int C, const gf_params &pr) {
     Geo g;
+    const int s = pr.s;
     g.H = H;
     g.W = W;
     g.s = s;
     g.Hl = (H + s - 1) / s;
     g.Wl = (W + s - 1) / s;
-    g.R = lowres_radius(r, s);
+    g.R = lowres_radius(pr.r, s);
     g.C = C;
-    g.sub = sub;
-    g.eps = (float)eps;
+    g.sub = (int)pr.sub;
+    g.border = (int)pr.border;
+    const bool refl = pr.border == GF_BORDER_REFLECT101;
+    g.refl_h = refl ? reflections(g.Hl, g.R) : 0;
+    g.refl_w = refl ? reflections(g.Wl, g.R) : 0;
+    g.eps = (float)pr.eps;
     g.lrs = round_up(g.Wl, 16);
     g.lps = round_up((int64_t)g.Hl * g.lrs, 64);
     return g;
@@ -84,8 +107,9 @@ bool tiles_fit(const Geo &g, const TileCfg &t) {
 }
 
 size_t workspace_bytes(const Geo &g) {
-    // a, b (2C planes) and their box means (2C planes), FP32
-    return sizeof(float) * (size_t)(4 * g.C) * (size_t)g.lps;
+    // a, b (2C planes) and their box means (2C planes), FP32; with area
+    // subsampling also I' and the C channels of p' (1 + C planes)
+    return sizeof(float) * (size_t)(4 * g.C + (area_pass(g) ? 1 + g.C : 0)) * (size_t)g.lps;
 }
 
 static size_t elem_size(gf_dtype d) { return d == GF_F32 ? 4 : 2; }
@@ -146,8 +170,9 @@ gf_status validate(const gf_image *I, const gf_image *p, const gf_image *q,
     if (!(pr->eps > 0.0) || !isfinite(pr->eps) || !((float)pr->eps > 0.0f) ||
         !isfinite((float)pr->eps))
         return fail(GF_EINVAL, "eps = %g must be positive and finite (in FP32)", pr->eps);
-    if (pr->border != GF_BORDER_CLIP) return fail(GF_ENOTSUP, "border %d not supported", (int)pr->border);
-    if (pr->sub != GF_SUB_NEAREST && pr->sub != GF_SUB_BILINEAR)
+    if (pr->border != GF_BORDER_CLIP && pr->border != GF_BORDER_REPLICATE && pr->border != GF_BORDER_REFLECT101)
+        return fail(GF_EINVAL, "unknown border convention %d", (int)pr->border);
+    if (pr->sub != GF_SUB_NEAREST && pr->sub != GF_SUB_BILINEAR && pr->sub != GF_SUB_AREA)
         return fail(GF_EINVAL, "unknown subsampling mode %d", (int)pr->sub);
     if (I->h > (1 << 24) || I->w > (1 << 24)) return fail(GF_ENOTSUP, "image side above 2^24");
     if (lowres_radius(pr->r, pr->s) > kMaxRadius)
@@ -169,7 +194,7 @@ bool vector_ok(const gf_image *I, const gf_image *q) {
 gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
                    const gf_params *pr, void *ws, size_t ws_bytes, hipStream_t st,
                    const TileCfg *tiles, bool p_low, const float *gain) {
-    const Geo g = make_geo(I->h, I->w, p->c, pr->r, pr->s, pr->eps, (int)pr->sub);
+    const Geo g = make_geo(I->h, I->w, p->c, *pr);
     // pinned or tuned shapes that do not fit this radius fall back to the built-in choice
     const TileCfg t = (tiles && tiles_fit(g, *tiles)) ? *tiles : default_tiles(g);
     if (!tiles_fit(g, t)) return fail(GF_ENOTSUP, "tile shapes do not fit in LDS for r'=%d", g.R);
@@ -180,13 +205,20 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
     if ((uintptr_t)ws % 256) return fail(GF_EINVAL, "workspace not 256-byte aligned");
     float *coef = (float *)ws;
     float *mean = coef + (size_t)(2 * g.C) * g.lps;
+    float *lowres = mean + (size_t)(2 * g.C) * g.lps;  // area subsampling: I', then p'
     const View vI{I->data, I->row_stride, I->plane_stride};
     const View vP{p->data, p->row_stride, p->plane_stride};
     const View vQ{q->data, q->row_stride, q->plane_stride};
-    hipError_t e;
-    {
+    hipError_t e = hipSuccess;
+    if (area_pass(g)) {
+        ProfScope ps(ctx, GF_K_AREA, st, true);
+        e = launch_area(I->dtype, vI, vP, p_low, lowres, g, st, ps.stamp());
+        ps.commit(e == hipSuccess);
+    }
+    if (e == hipSuccess) {
         ProfScope ps(ctx, GF_K_COEFF, st, true);
-        e = launch_coeff(I->dtype, vI, vP, coef, g, t, st, ps.stamp(), p_low);
+        e = area_pass(g) ? launch_coeff_lowres(lowres, lowres + g.lps, coef, g, t, st, ps.stamp())
+                         : launch_coeff(I->dtype, vI, vP, coef, g, t, st, ps.stamp(), p_low);
         ps.commit(e == hipSuccess);
     }
     if (e == hipSuccess) {
@@ -241,7 +273,7 @@ const char *gf_last_error(const gf_ctx *) { return gf::last_error(); }
 
 size_t gf_workspace_bytes(int32_t h, int32_t w, int32_t c, const gf_params *pr) {
     if (!pr || h < 1 || w < 1 || c < 1 || pr->s < 1 || pr->r < 0) return 0;
-    return workspace_bytes(make_geo(h, w, c, pr->r, pr->s, pr->eps, (int)pr->sub));
+    return workspace_bytes(make_geo(h, w, c, *pr));
 }
 
 static gf_status fast_entry(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q, const gf_params *pr,
@@ -250,7 +282,7 @@ static gf_status fast_entry(gf_ctx *ctx, const gf_image *I, const gf_image *p, g
     if (st != GF_OK) return st;
     if (!ws) {
         if (!ctx) return fail(GF_EINVAL, "workspace is NULL and there is no context");
-        const Geo g = make_geo(I->h, I->w, p->c, pr->r, pr->s, pr->eps, (int)pr->sub);
+        const Geo g = make_geo(I->h, I->w, p->c, *pr);
         if ((st = ctx_use_device(ctx)) != GF_OK) return st;
         ws_bytes = workspace_bytes(g);
         if ((st = ctx_workspace(ctx, ws_bytes, &ws)) != GF_OK) return st;

@@ -67,16 +67,20 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
     if (!I || !p || !q || !pr) return fail(GF_EINVAL, "batch: null array");
     gf_status st;
     int maxR = 0;
+    bool area = false;
     for (int i = 0; i < n; ++i) {
         if ((st = validate(&I[i], &p[i], &q[i], &pr[i])) != GF_OK)
             return fail(st, "image %d: %s", i, last_error());
         if (I[i].dtype != I[0].dtype) return fail(GF_EINVAL, "image %d: dtype differs from image 0", i);
         maxR = std::max(maxR, lowres_radius(pr[i].r, pr[i].s));
+        area = area || (pr[i].sub == GF_SUB_AREA && pr[i].s > 1);
     }
     plan->n = n;
     plan->dtype = I[0].dtype;
     plan->sched = cfg.schedule;
-    plan->th = batch_th(cfg.schedule, cfg.tile_h, maxR, plan);
+    // area subsampling has a pass of its own that the batched kernels do not
+    // run: such a batch goes image by image
+    plan->th = area ? 0 : batch_th(cfg.schedule, cfg.tile_h, maxR, plan);
     plan->desc.assign(n, BDesc{});
     // plan order: by ratio class (stable), so each class's output blocks are contiguous
     plan->order.resize(n);
@@ -84,6 +88,7 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
     std::stable_sort(plan->order.begin(), plan->order.end(),
                      [&](int a, int b) { return ratio_class(pr[a].s) < ratio_class(pr[b].s); });
     // workspace: control words, descriptor table, then each image's 4C planes
+    // (and its 1 + C area-subsampled planes)
     size_t off = round256(sizeof(unsigned) * batch_ctl_words(n));
     plan->desc_off = off;
     off += round256(sizeof(BDesc) * n);
@@ -91,7 +96,7 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
     for (int k = 0; k < n; ++k) {
         const int i = plan->order[k];
         BDesc &d = plan->desc[k];
-        const Geo g = make_geo(I[i].h, I[i].w, p[i].c, pr[i].r, pr[i].s, pr[i].eps, (int)pr[i].sub);
+        const Geo g = make_geo(I[i].h, I[i].w, p[i].c, pr[i]);
         d.I = I[i].data;
         d.P = p[i].data;
         d.Q = q[i].data;
@@ -101,7 +106,7 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
         d.Qrs = q[i].row_stride;
         d.Qps = q[i].plane_stride;
         d.g = g;
-        d.kind = g.s == 1 ? 0 : ((g.sub == GF_SUB_NEAREST || (g.s & 1)) ? 1 : 2);
+        d.kind = (g.s == 1 || area_pass(g)) ? 0 : ((g.sub == GF_SUB_NEAREST || (g.s & 1)) ? 1 : 2);
         d.vec = vector_ok(&I[i], &q[i]) ? 1 : 0;
         const int th = plan->th ? plan->th : 8;
         d.ntx_l = (g.Wl + kTileW - 1) / kTileW;
@@ -116,6 +121,7 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
         off += round256(planes);
         d.mean = (float *)(ws_base + off);
         off += round256(planes);
+        if (area_pass(g)) off += round256(sizeof(float) * (size_t)g.lps * (1 + g.C));
         for (int ph = 0; ph < 3; ++ph) {
             d.base[ph] = base[ph];
             base[ph] += d.ntiles[ph];
@@ -220,8 +226,9 @@ size_t gf_batched_workspace_bytes(int32_t n, const gf_image *I, const gf_image *
     size_t planes = 0;
     for (int i = 0; i < n; ++i) {
         if (I[i].h < 1 || I[i].w < 1 || p[i].c < 1 || pr[i].s < 1 || pr[i].r < 0) return 0;
-        const Geo g = make_geo(I[i].h, I[i].w, p[i].c, pr[i].r, pr[i].s, pr[i].eps, (int)pr[i].sub);
+        const Geo g = make_geo(I[i].h, I[i].w, p[i].c, pr[i]);
         planes += 2 * round256(sizeof(float) * (size_t)g.lps * 2 * g.C);
+        if (area_pass(g)) planes += round256(sizeof(float) * (size_t)g.lps * (1 + g.C));
     }
     return round256(sizeof(unsigned) * batch_ctl_words(n)) + round256(sizeof(BDesc) * n) + planes;
 }
@@ -250,13 +257,13 @@ gf_status gf_fast_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_im
     if ((uintptr_t)ws % 256) return fail(GF_EINVAL, "workspace not 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     if (plan.th == 0) {
-        // radius too large for the persistent kernel's staged tiles: one
-        // gf_fast per image on the same stream (same results)
+        // radius too large for the persistent kernel's staged tiles, or area
+        // subsampling: one gf_fast per image on the same stream (same results)
         for (int k = 0; k < n; ++k) {
             const BDesc &d = plan.desc[k];
             const int i = plan.order[k];
-            if ((st = run_fast(ctx, &I[i], &p[i], &q[i], &pr[i], d.coef,
-                               sizeof(float) * (size_t)d.g.lps * 4 * d.g.C, s, nullptr)) != GF_OK)
+            if ((st = run_fast(ctx, &I[i], &p[i], &q[i], &pr[i], d.coef, workspace_bytes(d.g), s, nullptr)) !=
+                GF_OK)
                 return st;
         }
         return GF_OK;
@@ -323,7 +330,7 @@ gf_status gf_batch_launch(const gf_batch *b, void *stream) {
             const BDesc &d = b->plan.desc[k];
             const int i = b->plan.order[k];
             if ((st = run_fast(nullptr, &b->I[i], &b->p[i], const_cast<gf_image *>(&b->q[i]), &b->pr[i],
-                               d.coef, sizeof(float) * (size_t)d.g.lps * 4 * d.g.C, s, nullptr)) != GF_OK)
+                               d.coef, workspace_bytes(d.g), s, nullptr)) != GF_OK)
                 return st;
         }
         return GF_OK;

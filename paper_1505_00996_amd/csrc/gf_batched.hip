@@ -51,23 +51,41 @@ __device__ __forceinline__ int find_image(const BDesc *__restrict__ D, int n, in
     return lo;
 }
 
+// The border class is per image, so a task picks its tile code at run time
+// (uniform across the workgroup).
+template <typename T, int TH, bool COH, int BD>
+__device__ __forceinline__ void run_coeff_b(const BDesc &d, int ty0, int tx0, void *lds) {
+    const T *I = (const T *)d.I, *P = (const T *)d.P;
+    switch (d.kind) {
+        case kSubId:
+            coeff_tile<T, kSubId, TH, true, COH, kSubId, BD>(I, d.Irs, P, d.Prs, d.Pps, d.coef, d.g, ty0, tx0, lds);
+            break;
+        case kSubNear:
+            coeff_tile<T, kSubNear, TH, true, COH, kSubNear, BD>(I, d.Irs, P, d.Prs, d.Pps, d.coef, d.g, ty0, tx0,
+                                                                 lds);
+            break;
+        default:
+            coeff_tile<T, kSubLin, TH, true, COH, kSubLin, BD>(I, d.Irs, P, d.Prs, d.Pps, d.coef, d.g, ty0, tx0, lds);
+            break;
+    }
+}
+
 template <typename T, int TH, bool COH>
 __device__ __forceinline__ void run_coeff(const BDesc &d, unsigned local, void *lds) {
     const int ty0 = ((int)local / d.ntx_l) * TH, tx0 = ((int)local % d.ntx_l) * kTileW;
-    const T *I = (const T *)d.I, *P = (const T *)d.P;
-    switch (d.kind) {
-        case kSubId: coeff_tile<T, kSubId, TH, true, COH>(I, d.Irs, P, d.Prs, d.Pps, d.coef, d.g, ty0, tx0, lds); break;
-        case kSubNear: coeff_tile<T, kSubNear, TH, true, COH>(I, d.Irs, P, d.Prs, d.Pps, d.coef, d.g, ty0, tx0, lds); break;
-        default: coeff_tile<T, kSubLin, TH, true, COH>(I, d.Irs, P, d.Prs, d.Pps, d.coef, d.g, ty0, tx0, lds); break;
-    }
+    if (d.g.border == GF_BORDER_CLIP) run_coeff_b<T, TH, COH, kClip>(d, ty0, tx0, lds);
+    else run_coeff_b<T, TH, COH, kPadded>(d, ty0, tx0, lds);
 }
 
 template <int TH, bool COH>
 __device__ __forceinline__ void run_box(const BDesc &d, unsigned local, void *lds) {
     const unsigned per = (unsigned)(d.ntx_l * d.nty_l);
     const int m = (int)(local / per), r = (int)(local % per);
-    box_tile<TH, COH>(d.coef + (int64_t)m * d.g.lps, d.mean + (int64_t)m * d.g.lps, d.g, (r / d.ntx_l) * TH,
-                       (r % d.ntx_l) * kTileW, lds);
+    const float *src = d.coef + (int64_t)m * d.g.lps;
+    float *dst = d.mean + (int64_t)m * d.g.lps;
+    const int ty0 = (r / d.ntx_l) * TH, tx0 = (r % d.ntx_l) * kTileW;
+    if (d.g.border == GF_BORDER_CLIP) box_tile<TH, COH, kClip>(src, dst, d.g, ty0, tx0, lds);
+    else box_tile<TH, COH, kPadded>(src, dst, d.g, ty0, tx0, lds);
 }
 
 // One output block (32 rows x 256 columns, up to three channels).  The

@@ -6,7 +6,8 @@
 //   coeff_tile  : subsample I and p (step 1) while staging a low-res tile and
 //                 its r' halo in LDS; window sums of I', I'^2, p', I'p'
 //                 (step 2); var, cov (step 3) and a, b of Eqs. 2-3 (step 4).
-//   box_tile    : clip-normalised box mean of one coefficient map (step 5).
+//   box_tile    : box mean of one coefficient map (step 5), clip-normalised
+//                 or over the map padded by replication / reflect-101.
 //   output_tile : bilinear upsampling of mean_a, mean_b fused with
 //                 q = mean_a * I + mean_b against the full-resolution I
 //                 (steps 6-7); the HBM-bound pass.
@@ -184,6 +185,33 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 // Number of in-image positions of a radius-R window centred at i on an n-axis.
 __device__ __forceinline__ int clip_len(int i, int R, int n) {
     return min(n - 1, i + R) - max(0, i - R) + 1;
+}
+
+// Border classes of the window-sum tiles, fixed per kernel so the clip
+// path carries no code of the others:
+//   kClip   the window's in-map samples only (outside ones weigh 0), mean
+//           over their count;
+//   kPadded the map extended past its edges as g.border says (replicate or
+//           reflect-101), mean over (2r'+1)^2.
+constexpr int kClip = 0, kPadded = 1;
+
+// Index that position i of an n-long map axis reads under a padded border.
+// Replicate clamps.  Reflect-101 applies the reflection about both ends,
+// F(m) = (n-1) - |(n-1) - |m||, which is exact for -(n-1) <= m <= 2(n-1),
+// `reps` times (reps > 1 only for windows wider than the axis; the host
+// counts them), then clamps, which also makes a one-pixel axis read its
+// pixel and keeps the rows a ragged tile reads past its outputs in bounds.
+__device__ __forceinline__ int pad_index(int i, int n, int border, int reps) {
+    if (border == GF_BORDER_REFLECT101) {
+        int m = n - 1 - abs(n - 1 - abs(i));
+        for (int t = 1; t < reps; ++t) m = n - 1 - abs(n - 1 - abs(m));
+        i = m;
+    }
+    return clampi(i, 0, n - 1);
+}
+template <int BD>
+__device__ __forceinline__ int window_len(int i, int R, int n) {
+    return BD == kClip ? clip_len(i, R, n) : 2 * R + 1;
 }
 
 // Wave index as a scalar, so values derived from it stay in SGPRs.
@@ -391,7 +419,8 @@ __device__ __forceinline__ void coeff_from_sums(int n, double Su, double Suu, do
 // caches.
 // KP: how p is sampled -- like I (Algorithm 2), or kSubId when p is given at
 // low resolution already (joint upsampling: its rows are the low-res rows).
-template <typename T, int K, int TH, bool STAGE, bool COH = false, int KP = K>
+// BD: border class (kClip, kPadded).
+template <typename T, int K, int TH, bool STAGE, bool COH = false, int KP = K, int BD = kClip>
 __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
                                            const T *__restrict__ P, int64_t Prs, int64_t Pps,
                                            float *__restrict__ coef, const Geo &g, int ty0, int tx0,
@@ -404,18 +433,25 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
     const int oy = ty0 - R, ox = tx0 - R;
     const int lane = threadIdx.x & 63, wave = wave_id();
 
-    // u = I' - cI and v = p' - cP over the region, 0 outside the low-res map.
-    // The outside case multiplies by 0 rather than selecting: a select on a
+    // u = I' - cI and v = p' - cP over the region; outside the low-res map
+    // 0 (kClip) or the sample the border extension puts there (kPadded).
+    // The clip case multiplies by 0 rather than selecting: a select on a
     // loaded value lets the compiler turn the load into a branch that waits
     // for it, one load at a time.  The sample read there is an in-image one
     // (clamped address), so the product is an exact 0 for finite images.
     auto gsample = [&](auto kind, const T *img, int64_t rs, float c, int ry, int rx) -> float {
         constexpr int KK = decltype(kind)::value;
         const int ly = oy + ry, lx = ox + rx;
-        const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
-        const float v = sample_rc<KK>(img, rs, taps<KK>(clampi(ly, 0, g.Hl - 1), g.s, g.H),
-                                      taps<KK>(clampi(lx, 0, g.Wl - 1), g.s, g.W));
-        return (v - c) * (in ? 1.f : 0.f);
+        if constexpr (BD == kClip) {
+            const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
+            const float v = sample_rc<KK>(img, rs, taps<KK>(clampi(ly, 0, g.Hl - 1), g.s, g.H),
+                                          taps<KK>(clampi(lx, 0, g.Wl - 1), g.s, g.W));
+            return (v - c) * (in ? 1.f : 0.f);
+        } else {
+            const float v = sample_rc<KK>(img, rs, taps<KK>(pad_index(ly, g.Hl, g.border, g.refl_h), g.s, g.H),
+                                          taps<KK>(pad_index(lx, g.Wl, g.border, g.refl_w), g.s, g.W));
+            return v - c;
+        }
     };
     using KI = std::integral_constant<int, K>;
     using KQ = std::integral_constant<int, KP>;
@@ -424,7 +460,7 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
 
     const int col = lane, r0 = wave * LC;
     const int lx = tx0 + col;
-    const int nx = clip_len(lx, R, g.Wl);
+    const int nx = window_len<BD>(lx, R, g.Wl);
 
     // (Window loops have a run-time length 2r'+1; unrolling them keeps several
     // LDS reads in flight instead of one read-wait-add per element.  The
@@ -547,7 +583,7 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
             const int ly = ty0 + r0 + t;
             if (ly < g.Hl && lx < g.Wl) {
                 float a, b;
-                coeff_from_sums(clip_len(ly, R, g.Hl) * nx, Su[t], Suu[t], A, B, cI, cP, g.eps, a, b);
+                coeff_from_sums(window_len<BD>(ly, R, g.Hl) * nx, Su[t], Suu[t], A, B, cI, cP, g.eps, a, b);
                 stp<COH>(ac + (int64_t)ly * g.lrs + lx, a);
                 stp<COH>(bc + (int64_t)ly * g.lrs + lx, b);
             }
@@ -555,8 +591,8 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
     }
 }
 
-// One TH x 64 tile of the clip-normalised box mean of a low-res FP32 plane.
-template <int TH, bool COH = false>
+// One TH x 64 tile of the box mean of a low-res FP32 plane (border class BD).
+template <int TH, bool COH = false, int BD = kClip>
 __device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__restrict__ D,
                                          const Geo &g, int ty0, int tx0, void *lds) {
     constexpr int LC = TH / 4;
@@ -567,9 +603,14 @@ __device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__r
     const int lane = threadIdx.x & 63, wave = wave_id();
     fill_tile(sX, SH, SW, SWp, [&](int ry, int rx) -> float {
         const int ly = oy + ry, lx = ox + rx;
-        const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
-        const float v = ldp<COH>(S + (int64_t)clampi(ly, 0, g.Hl - 1) * g.lrs + clampi(lx, 0, g.Wl - 1));
-        return v * (in ? 1.f : 0.f);  // product, not select: see coeff_tile
+        if constexpr (BD == kClip) {
+            const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
+            const float v = ldp<COH>(S + (int64_t)clampi(ly, 0, g.Hl - 1) * g.lrs + clampi(lx, 0, g.Wl - 1));
+            return v * (in ? 1.f : 0.f);  // product, not select: see coeff_tile
+        } else {
+            return ldp<COH>(S + (int64_t)pad_index(ly, g.Hl, g.border, g.refl_h) * g.lrs +
+                            pad_index(lx, g.Wl, g.border, g.refl_w));
+        }
     });
     lds_sync();
     for (int it = threadIdx.x; it < SH * (kTileW / kRun); it += kThreads) {
@@ -599,7 +640,7 @@ __device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__r
     lds_sync();
     const int col = lane, r0 = wave * LC;
     const int lx = tx0 + col;
-    const int nx = clip_len(lx, R, g.Wl);
+    const int nx = window_len<BD>(lx, R, g.Wl);
     float A = 0.f;
 #pragma unroll 8
     for (int k = 0; k <= 2 * R; ++k) A += rA[(r0 + k) * kRowW + col];
@@ -608,7 +649,7 @@ __device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__r
         if (t) A += rA[(r0 + t + 2 * R) * kRowW + col] - rA[(r0 + t - 1) * kRowW + col];
         const int ly = ty0 + r0 + t;
         if (ly < g.Hl && lx < g.Wl)
-            stp<COH>(D + (int64_t)ly * g.lrs + lx, A * rcp((float)(clip_len(ly, R, g.Hl) * nx)));
+            stp<COH>(D + (int64_t)ly * g.lrs + lx, A * rcp((float)(window_len<BD>(ly, R, g.Hl) * nx)));
     }
 }
 

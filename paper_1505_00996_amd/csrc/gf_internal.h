@@ -10,14 +10,19 @@
 namespace gf {
 
 // Geometry of one filtering problem.  Full-res H x W, low-res Hl x Wl
-// (ceil(H/s) x ceil(W/s)), low-res radius R, C channels of p.  The
+// (ceil(H/s) x ceil(W/s)), low-res radius R, C channels of p, subsampling
+// kind sub and border convention border (gf_subsample, gf_border).  The
 // low-resolution FP32 maps live in a workspace as planes of Hl rows with
 // row stride lrs (a multiple of 16 floats) and plane stride lps (a multiple
 // of 64 floats), so every plane and row start is 64-byte aligned.
+// refl_h, refl_w: reflections a reflect-101 border needs on each axis to
+// bring every position a window reaches back into the map (1 unless the
+// window is wider than the map; 0 for the other borders).
 struct Geo {
     int H, W;
     int Hl, Wl;
-    int s, R, C, sub;
+    int s, R, C, sub, border;
+    int refl_h, refl_w;
     float eps;
     int64_t lrs, lps;
 };
@@ -41,7 +46,9 @@ constexpr int kOutPx = 4;       // full-res pixels per lane in the output kernel
 constexpr int kOutTileW = 64 * kOutPx;  // full-res columns per output tile
 constexpr int kMaxRadius = 64;  // largest low-res radius the LDS tile buffers hold
 
-Geo make_geo(int H, int W, int C, int r, int s, double eps, int sub);
+Geo make_geo(int H, int W, int C, const gf_params &pr);
+// Area subsampling runs as a pass of its own (launch_area) into FP32 planes.
+inline bool area_pass(const Geo &g) { return g.sub == GF_SUB_AREA && g.s > 1; }
 constexpr size_t kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
 bool coeff_staged(const TileCfg &t, int R);
 size_t coeff_lds_bytes(const TileCfg &t, int R);
@@ -69,6 +76,22 @@ hipError_t launch_coeff(gf_dtype dt, const View &I, const View &P, float *coef,
                         bool p_low = false);
 hipError_t launch_box(const float *src, float *dst, const Geo &g, const TileCfg &t,
                       hipStream_t st, const Stamp &ts = Stamp{});
+// Area subsampling of I (plane 0 of dst) and of the C channels of P (planes
+// 1..C; with p_low, P is already low-res and is converted as it is), FP32
+// planes of stride g.lps.  The coefficients then come from launch_coeff_lowres.
+hipError_t launch_area(gf_dtype dt, const View &I, const View &P, bool p_low, float *dst, const Geo &g,
+                       hipStream_t st, const Stamp &ts = Stamp{});
+// Coefficients from low-res FP32 planes: guide Il, channels of p at Pl + c*g.lps.
+hipError_t launch_coeff_lowres(const float *Il, const float *Pl, float *coef, const Geo &g, const TileCfg &t,
+                               hipStream_t st, const Stamp &ts = Stamp{});
+// The same launchers for the padded borders (gf_kernels_padded.hip); the
+// launchers above forward to them when g.border is not GF_BORDER_CLIP.
+hipError_t launch_coeff_padded(gf_dtype dt, const View &I, const View &P, float *coef, const Geo &g,
+                               const TileCfg &t, hipStream_t st, const Stamp &ts, bool p_low);
+hipError_t launch_coeff_lowres_padded(const float *Il, const float *Pl, float *coef, const Geo &g,
+                                      const TileCfg &t, hipStream_t st, const Stamp &ts);
+hipError_t launch_box_padded(const float *src, float *dst, const Geo &g, const TileCfg &t, hipStream_t st,
+                             const Stamp &ts);
 hipError_t launch_output(gf_dtype dt, const View &I, const View &Q, const float *mean,
                          const Geo &g, const TileCfg &t, bool vec, hipStream_t st,
                          const Stamp &ts = Stamp{}, const Detail &detail = Detail{});

@@ -5,38 +5,16 @@
 //   k_box    (grid: low-res tiles x 2C maps)   step 5    -> mean_a, mean_b
 //   k_output (grid: full-res 256 x 32 blocks)  steps 6-7 -> q
 // Algorithm 1 is the same three launches at s = 1, where subsampling and
-// upsampling are identities.  The per-tile work lives in gf_device.h.
-#include <hip/hip_ext.h>
-#include <hip/hip_runtime.h>
-
-#include "gf_device.h"
-#include "gf_internal.h"
+// upsampling are identities.  Area subsampling adds a first launch,
+//   k_area   (grid: low-res 64 x 4 blocks x (1+C) planes)  step 1 -> I', p'
+// after which k_coeff reads the FP32 low-res planes as they are.  The
+// per-tile work lives in gf_device.h; the window-sum kernels and their
+// launchers in gf_window_kernels.h (this file instantiates the
+// clip-normalised ones, gf_kernels_padded.hip the padded-border ones).
+#include "gf_window_kernels.h"
 
 namespace gf {
 namespace {
-
-using namespace dev;
-
-template <typename T, int K, int KP, int TH, bool STAGE>
-__global__ __launch_bounds__(kThreads) void k_coeff(const T *__restrict__ I, int64_t Irs,
-                                                    const T *__restrict__ P, int64_t Prs, int64_t Pps,
-                                                    float *__restrict__ coef, Geo g, int ntx, int ntiles) {
-    extern __shared__ double lds_d[];
-    const int tile = xcd_tile(blockIdx.x);
-    if (tile >= ntiles) return;  // uniform per workgroup: no barrier is skipped by part of it
-    coeff_tile<T, K, TH, STAGE, false, KP>(I, Irs, P, Prs, Pps, coef, g, (tile / ntx) * TH, (tile % ntx) * kTileW,
-                                           lds_d);
-}
-
-template <int TH>
-__global__ __launch_bounds__(kThreads) void k_box(const float *__restrict__ src, float *__restrict__ dst,
-                                                  Geo g, int ntx, int ntiles) {
-    extern __shared__ double lds_d[];
-    const int tile = xcd_tile(blockIdx.x);
-    if (tile >= ntiles) return;
-    box_tile<TH>(src + (int64_t)blockIdx.y * g.lps, dst + (int64_t)blockIdx.y * g.lps, g,
-                 (tile / ntx) * TH, (tile % ntx) * kTileW, lds_d);
-}
 
 // One workgroup = 4 waves = a 256-column x 32-row block of q (EPI: of the
 // detail-enhanced e, reading the matching block of p).
@@ -53,63 +31,111 @@ __global__ __launch_bounds__(kThreads) void k_output(const T *__restrict__ I, in
                                (tile % ntx) * kOutTileW, vec != 0, P, Prs, Pps, gain);
 }
 
-int grid8(int n) { return ((n + 7) / 8) * 8; }
-
-// A launch that carries timing events in its dispatch when asked to.
-template <typename Kn, typename... A>
-void launch_k(Kn kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
-              A... args) {
-    if (e0 || e1) hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, st, e0, e1, 0u, args...);
-    else hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
-}
-
-// Dynamic LDS above 64 KB has to be allowed per kernel (gfx950 has 160 KB).
-template <typename Kn>
-void allow_lds(Kn kernel, size_t bytes) {
-    if (bytes > 65536)
-        (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)bytes);
-}
-
-template <typename T, int K, int KP>
-hipError_t coeff_tk(const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
-                    hipStream_t st, const Stamp &ts) {
-    const T *Ip = (const T *)I.data, *Pp = (const T *)P.data;
-    const bool staged = coeff_staged(t, g.R);
-    const int th = staged ? t.coeff_th : 8;  // the unstaged kernel works on 8-row tiles
-    const int ntx = (g.Wl + kTileW - 1) / kTileW, nty = (g.Hl + th - 1) / th;
-    const int ntiles = ntx * nty;
-    const size_t lds = coeff_lds_bytes(t, g.R);
-    const dim3 grid(grid8(ntiles)), block(kThreads);
-#define GF_COEFF(TH, STG)                                                                              \
-    {                                                                                                   \
-        allow_lds(k_coeff<T, K, KP, TH, STG>, lds);                                                     \
-        launch_k(k_coeff<T, K, KP, TH, STG>, grid, block, lds, st, ts.start, ts.stop, Ip, I.rs, Pp, P.rs, P.ps, \
-                 coef, g, ntx, ntiles);                                                                 \
+// Area subsampling (step 1 with the block mean): low-res pixel (ly, lx) of
+// plane k is the mean of the full-res block [s*ly, s*ly+s) x [s*lx, s*lx+s)
+// clipped to the image, summed in FP64 row by row and rounded once to FP32.
+// Plane 0 is the guide, planes 1..C the channels of p; with p_low those are
+// given at low resolution and are converted as they are.  A workgroup covers
+// 4 low-res rows (one per wave) x 64 columns (one per lane) of plane
+// blockIdx.y.  S: compile-time ratio for full blocks (0: g.s at run time);
+// with vec, every row of a full block is read with 2- or 4-wide loads (the
+// host checked that every row of I and p starts aligned for them).
+template <typename T, int S>
+__global__ __launch_bounds__(kThreads) void k_area(const T *__restrict__ I, int64_t Irs, const T *__restrict__ P,
+                                                   int64_t Prs, int64_t Pps, int p_low, float *__restrict__ dst,
+                                                   Geo g, int ntx, int vec) {
+    const int lane = threadIdx.x & 63;
+    const int ly = (blockIdx.x / ntx) * 4 + wave_id(), lx = (blockIdx.x % ntx) * 64 + lane;
+    if (ly >= g.Hl || lx >= g.Wl) return;  // no barriers in this kernel
+    const int k = blockIdx.y;
+    float *out = dst + (int64_t)k * g.lps + (int64_t)ly * g.lrs + lx;
+    if (k > 0 && p_low) {
+        *out = ld(P + (int64_t)(k - 1) * Pps + (int64_t)ly * Prs + lx);
+        return;
     }
-    if (!staged) {
-        GF_COEFF(8, false)  // large r': only the row sums live in LDS
+    const T *src = k == 0 ? I : P + (int64_t)(k - 1) * Pps;
+    const int64_t rs = k == 0 ? Irs : Prs;
+    const int s = S ? S : g.s, y0 = s * ly, x0 = s * lx;
+    const int ny = min(s, g.H - y0), nx = min(s, g.W - x0);  // >= 1: s*ly < H, s*lx < W
+    double acc = 0.0;
+    if (S && ny == S && nx == S) {
+        double ra[S > 0 ? S : 1];
+        if (vec) {
+            // all loads first, then the sums (in the same order as below)
+            float v[S > 0 ? S : 1][S > 0 ? S : 1];
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                const T *row = src + (int64_t)(y0 + i) * rs + x0;
+                if constexpr (S == 2) {
+                    const f32x2 a = ld2(row);
+                    v[i][0] = a[0];
+                    v[i][1] = a[1];
+                } else {
+#pragma unroll
+                    for (int j = 0; j < S; j += 4) {
+                        const f32x4 a = ld4(row + j);
+                        v[i][j] = a[0];
+                        v[i][j + 1] = a[1];
+                        v[i][j + 2] = a[2];
+                        v[i][j + 3] = a[3];
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                ra[i] = 0.0;
+#pragma unroll
+                for (int j = 0; j < S; ++j) ra[i] += (double)v[i][j];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                const T *row = src + (int64_t)(y0 + i) * rs + x0;
+                ra[i] = 0.0;
+#pragma unroll
+                for (int j = 0; j < S; ++j) ra[i] += (double)ld(row + j);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) acc += ra[i];
     } else {
-        switch (t.coeff_th) {
-            case 8: GF_COEFF(8, true) break;
-            case 16: GF_COEFF(16, true) break;
-            case 24: GF_COEFF(24, true) break;
-            default: GF_COEFF(32, true) break;
+        for (int i = 0; i < ny; ++i) {
+            const T *row = src + (int64_t)(y0 + i) * rs + x0;
+            double ra = 0.0;
+            for (int j = 0; j < nx; ++j) ra += (double)ld(row + j);
+            acc += ra;
         }
     }
-#undef GF_COEFF
-    return hipGetLastError();
+    *out = (float)(acc / (double)(ny * nx));
+}
+
+// Rows of a view start on a multiple of n elements (n-wide loads allowed).
+template <typename T>
+bool rows_aligned(const View &v, int n, bool planes) {
+    const int64_t b = (int64_t)(n * sizeof(T));
+    return (uintptr_t)v.data % (uintptr_t)b == 0 && (v.rs * (int64_t)sizeof(T)) % b == 0 &&
+           (!planes || (v.ps * (int64_t)sizeof(T)) % b == 0);
 }
 
 template <typename T>
-hipError_t coeff_t(const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
-                   hipStream_t st, const Stamp &ts, bool p_low) {
-    if (g.s == 1) return coeff_tk<T, kSubId, kSubId>(I, P, coef, g, t, st, ts);
-    if (g.sub == GF_SUB_NEAREST || (g.s & 1))
-        return p_low ? coeff_tk<T, kSubNear, kSubId>(I, P, coef, g, t, st, ts)
-                     : coeff_tk<T, kSubNear, kSubNear>(I, P, coef, g, t, st, ts);
-    return p_low ? coeff_tk<T, kSubLin, kSubId>(I, P, coef, g, t, st, ts)
-                 : coeff_tk<T, kSubLin, kSubLin>(I, P, coef, g, t, st, ts);
+hipError_t area_t(const View &I, const View &P, bool p_low, float *dst, const Geo &g, hipStream_t st,
+                  const Stamp &ts) {
+    const int ntx = (g.Wl + 63) / 64, nty = (g.Hl + 3) / 4;
+    const dim3 grid(ntx * nty, 1 + g.C), block(kThreads);
+    const T *Ip = (const T *)I.data, *Pp = (const T *)P.data;
+    const int n = g.s == 2 ? 2 : 4;  // load width of the S = 2, 4, 8 kernels
+    const int vec = rows_aligned<T>(I, n, false) && (p_low || rows_aligned<T>(P, n, g.C > 1));
+#define GF_AREA(SS)                                                                                  \
+    launch_k(k_area<T, SS>, grid, block, 0, st, ts.start, ts.stop, Ip, I.rs, Pp, P.rs, P.ps, (int)p_low, dst, g, \
+             ntx, vec)
+    switch (g.s) {
+        case 2: GF_AREA(2); break;
+        case 4: GF_AREA(4); break;
+        case 8: GF_AREA(8); break;
+        default: GF_AREA(0); break;
+    }
+#undef GF_AREA
+    return hipGetLastError();
 }
 
 template <typename T, int CC, bool EPI>
@@ -168,33 +194,30 @@ size_t box_lds_bytes(const TileCfg &t, int R) { return dev::box_tile_lds(t.box_t
 
 hipError_t launch_coeff(gf_dtype dt, const View &I, const View &P, float *coef, const Geo &g,
                         const TileCfg &t, hipStream_t st, const Stamp &ts, bool p_low) {
+    if (g.border != GF_BORDER_CLIP) return launch_coeff_padded(dt, I, P, coef, g, t, st, ts, p_low);
+    return coeff_dt<kClip>(dt, I, P, coef, g, t, st, ts, p_low);
+}
+
+hipError_t launch_area(gf_dtype dt, const View &I, const View &P, bool p_low, float *dst, const Geo &g,
+                       hipStream_t st, const Stamp &ts) {
     switch (dt) {
-        case GF_F32: return coeff_t<float>(I, P, coef, g, t, st, ts, p_low);
-        case GF_F16: return coeff_t<_Float16>(I, P, coef, g, t, st, ts, p_low);
-        case GF_BF16: return coeff_t<dev::bf16>(I, P, coef, g, t, st, ts, p_low);
+        case GF_F32: return area_t<float>(I, P, p_low, dst, g, st, ts);
+        case GF_F16: return area_t<_Float16>(I, P, p_low, dst, g, st, ts);
+        case GF_BF16: return area_t<dev::bf16>(I, P, p_low, dst, g, st, ts);
     }
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_coeff_lowres(const float *Il, const float *Pl, float *coef, const Geo &g, const TileCfg &t,
+                               hipStream_t st, const Stamp &ts) {
+    if (g.border != GF_BORDER_CLIP) return launch_coeff_lowres_padded(Il, Pl, coef, g, t, st, ts);
+    return coeff_lowres<kClip>(Il, Pl, coef, g, t, st, ts);
+}
+
 hipError_t launch_box(const float *src, float *dst, const Geo &g, const TileCfg &t, hipStream_t st,
                       const Stamp &ts) {
-    const int ntx = (g.Wl + kTileW - 1) / kTileW, nty = (g.Hl + t.box_th - 1) / t.box_th;
-    const int ntiles = ntx * nty;
-    const size_t lds = box_lds_bytes(t, g.R);
-    const dim3 grid(grid8(ntiles), 2 * g.C), block(kThreads);
-#define GF_BOX(TH)                                                                            \
-    {                                                                                         \
-        allow_lds(k_box<TH>, lds);                                                            \
-        launch_k(k_box<TH>, grid, block, lds, st, ts.start, ts.stop, src, dst, g, ntx, ntiles);  \
-    }
-    switch (t.box_th) {
-        case 8: GF_BOX(8) break;
-        case 16: GF_BOX(16) break;
-        case 24: GF_BOX(24) break;
-        default: GF_BOX(32) break;
-    }
-#undef GF_BOX
-    return hipGetLastError();
+    if (g.border != GF_BORDER_CLIP) return launch_box_padded(src, dst, g, t, st, ts);
+    return box_b<kClip>(src, dst, g, t, st, ts);
 }
 
 hipError_t launch_output(gf_dtype dt, const View &I, const View &Q, const float *mean, const Geo &g,

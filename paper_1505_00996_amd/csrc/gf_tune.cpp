@@ -45,7 +45,7 @@ gf_status gf_ctx_set_tiles(gf_ctx *ctx, gf_dtype dtype, int32_t h, int32_t w, in
         ctx->tuned.erase(key);
         return GF_OK;
     }
-    const Geo g = make_geo(h, w, c, pr->r, pr->s, pr->eps, (int)pr->sub);
+    const Geo g = make_geo(h, w, c, *pr);
     const TileCfg t = from_abi(*tiles);
     if (!tiles_fit(g, t)) return fail(GF_ENOTSUP, "tile shapes do not fit r'=%d", g.R);
     ctx->tuned[key] = t;
@@ -60,7 +60,7 @@ gf_status gf_tune(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q
     if (st != GF_OK) return st;
     if ((st = ctx_use_device(ctx)) != GF_OK) return st;
     if (reps < 1) reps = 1;
-    const Geo g = make_geo(I->h, I->w, p->c, pr->r, pr->s, pr->eps, (int)pr->sub);
+    const Geo g = make_geo(I->h, I->w, p->c, *pr);
     if (!ws) {
         ws_bytes = workspace_bytes(g);
         if ((st = ctx_workspace(ctx, ws_bytes, &ws)) != GF_OK) return st;
@@ -70,8 +70,15 @@ gf_status gf_tune(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q
     hipStream_t s = (hipStream_t)stream;
     float *coef = (float *)ws;
     float *mean = coef + (size_t)(2 * g.C) * g.lps;
+    float *lowres = mean + (size_t)(2 * g.C) * g.lps;
     const View vI{I->data, I->row_stride, I->plane_stride};
     const View vP{p->data, p->row_stride, p->plane_stride};
+    // area subsampling: the low-res planes are made once; the candidates of
+    // the coefficient kernel read them
+    if (area_pass(g)) {
+        const hipError_t e = launch_area(I->dtype, vI, vP, false, lowres, g, s);
+        if (e != hipSuccess) return fail(GF_EDEVICE, "area subsampling launch failed: %s", hipGetErrorString(e));
+    }
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -86,8 +93,9 @@ gf_status gf_tune(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q
         TileCfg best_cfg = chosen;
         for (const TileCfg &c : candidates(g, chosen, kernel)) {
             auto launch = [&]() -> hipError_t {
-                return kernel == GF_K_COEFF ? launch_coeff(I->dtype, vI, vP, coef, g, c, s)
-                                            : launch_box(coef, mean, g, c, s);
+                if (kernel != GF_K_COEFF) return launch_box(coef, mean, g, c, s);
+                return area_pass(g) ? launch_coeff_lowres(lowres, lowres + g.lps, coef, g, c, s)
+                                    : launch_coeff(I->dtype, vI, vP, coef, g, c, s);
             };
             hipError_t e = launch();  // warm-up (also leaves valid a, b for the box candidates)
             if (e == hipSuccess) e = hipEventRecord(e0, s);

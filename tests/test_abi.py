@@ -64,7 +64,7 @@ def good():
     ("q_aliases_p", gfp.GF_EINVAL),
     ("q_overlaps_I_tail", gfp.GF_EINVAL),
     ("empty_image", gfp.GF_EINVAL),
-    ("bad_border", gfp.GF_ENOTSUP),
+    ("bad_border", gfp.GF_EINVAL),
     ("bad_subsample", gfp.GF_EINVAL),
     ("radius_too_large", gfp.GF_ENOTSUP),
     ("misaligned_data", gfp.GF_EINVAL),
@@ -155,6 +155,13 @@ def test_workspace_bytes():
     assert L.gf_workspace_bytes(0, 4000, 3, ctypes.byref(pr)) == 0
     pr1 = gfp.params(16, 1, 1e-3)
     assert L.gf_workspace_bytes(10, 10, 1, ctypes.byref(pr1)) == 4 * 1 * 192 * 4
+    # area subsampling adds I' and the C channels of p' (1 + C planes); borders add nothing
+    pra = gfp.params(16, 4, 1e-3, "area")
+    assert L.gf_workspace_bytes(3000, 4000, 3, ctypes.byref(pra)) == (4 * 3 + 1 + 3) * lps * 4
+    prb = gfp.params(16, 4, 1e-3, "nearest", "reflect101")
+    assert L.gf_workspace_bytes(3000, 4000, 3, ctypes.byref(prb)) == 4 * 3 * lps * 4
+    pra1 = gfp.params(16, 1, 1e-3, "area")  # s = 1: the area mean of one pixel is that pixel, no pass
+    assert L.gf_workspace_bytes(10, 10, 1, ctypes.byref(pra1)) == 4 * 1 * 192 * 4
 
 
 def test_prepared_batch_rejected_on_host():
