@@ -180,10 +180,11 @@ gf_status validate(const gf_image *I, const gf_image *p, const gf_image *q,
     return GF_OK;
 }
 
-// 16-byte (fp32) or 8-byte (16-bit) accesses of 4 pixels need the row starts
-// of I and of every q plane aligned to that size.
-bool vector_ok(const gf_image *I, const gf_image *q) {
-    const size_t es = elem_size(I->dtype), vb = 4 * es;
+// Row accesses of `bytes` bytes need the row starts of I and of every q
+// plane aligned to that size (per-image output kernel: 16 bytes; batched
+// kernels: 4 pixels).
+bool vector_ok(const gf_image *I, const gf_image *q, size_t bytes) {
+    const size_t es = elem_size(I->dtype), vb = bytes;
     auto aligned = [&](const gf_image *im) {
         return (uintptr_t)im->data % vb == 0 && (im->row_stride * (int64_t)es) % (int64_t)vb == 0 &&
                (im->c == 1 || (im->plane_stride * (int64_t)es) % (int64_t)vb == 0);
@@ -233,8 +234,8 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
             dt.p = vP;
             dt.gain = *gain;
         }
-        e = launch_output(I->dtype, vI, vQ, mean, g, t, vector_ok(I, q) && (!gain || vector_ok(p, p)), st,
-                          ps.stamp(), dt);
+        e = launch_output(I->dtype, vI, vQ, mean, g, t, vector_ok(I, q, 16) && (!gain || vector_ok(p, p, 16)),
+                          st, ps.stamp(), dt);
         ps.commit(e == hipSuccess);
     }
     if (e != hipSuccess) return fail(GF_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));

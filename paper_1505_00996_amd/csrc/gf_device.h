@@ -61,12 +61,9 @@ __device__ __forceinline__ float to_f32(float v) { return v; }
 __device__ __forceinline__ float to_f32(_Float16 v) { return (float)v; }
 __device__ __forceinline__ float to_f32(bf16 v) { return __uint_as_float((unsigned)v.bits << 16); }
 
-// float -> bfloat16, round to nearest even (NaN kept quiet).
+// float -> bfloat16, round to nearest even (gfx950 converts in hardware).
 __device__ __forceinline__ unsigned short f32_to_bf16_bits(float f) {
-    unsigned u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+    return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
 
 template <typename T> __device__ __forceinline__ T from_f32(float v);
@@ -655,16 +652,18 @@ __device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__r
 
 // ---------------------------------------------------------------- output
 //
-// A wave covers 256 full-res columns (4 per lane) and kOutRows = 8 rows
-// starting at a multiple of 8.  A lane first loads its 8 x 4 guide pixels
-// (all loads in flight together); then, channel by channel, it loads the
-// low-res rows and columns of mean_a, mean_b its pixels interpolate from,
+// A wave covers kOutRows = 8 rows starting at a multiple of 8 and 64 PX
+// full-res columns, PX pixels per lane: 4 for fp32 and 8 for 16-bit storage
+// in the per-image kernel, so that every row access is 16 bytes (the
+// batched kernels use 4).  A lane first loads its 8 x PX guide pixels (all
+// loads in flight together); then, channel by channel, it loads the low-res
+// rows and columns of mean_a, mean_b its pixels interpolate from,
 // interpolates them horizontally once, and for every row finishes the
 // bilinear weights and writes q = a*I + b with non-temporal stores.
 //
 // Upsampling geometry (half-pixel centres): full-res x maps to low-res
 // u = (x + 0.5)/s - 0.5 = (2x + 1 - s) / (2s), taps floor(u), floor(u) + 1
-// clamped to the map.  For s in {2, 4, 8} lanes start at x0 = 0 mod 4 and
+// clamped to the map.  For s in {2, 4, 8} lanes start at x0 = 0 mod PX and
 // waves at y = 0 mod 8, so which low-res rows/columns each pixel uses,
 // relative to the first one, is known at compile time.
 
@@ -678,80 +677,157 @@ constexpr float cfrac_u(int x, int s) {
     return (float)((2 * x + 1 - s) - 2 * s * cfloor_u(x, s)) / (float)(2 * s);
 }
 
-// q for CC channels (planes Q + c*Qps) of the wave's 8 x 256 block at
-// (yb, xw); mean_a_c = M + (c0+c)*lps, mean_b_c = M + (C+c0+c)*lps.
-// S: compile-time ratio, 0 = read g.s at run time.
+// Rows of PX pixels per lane.  fp32 (PX = 4): FP32 values, one 16-byte
+// access.  16-bit (PX = 8): the 8 stored values kept in their storage width
+// (half the registers) and widened, exactly, when used; one 16-byte access.
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+template <typename T, int PX>
+struct PixRow {
+    float v[PX];
+    __device__ __forceinline__ float at(int j) const { return v[j]; }
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int j = 0; j < PX; ++j) v[j] = 0.f;
+    }
+};
+template <typename T>
+struct PixRow<T, 8> {
+    static_assert(sizeof(T) == 2, "8-wide rows are 16-bit rows");
+    u16x8 b;
+    __device__ __forceinline__ float at(int j) const {
+        if constexpr (std::is_same<T, bf16>::value) return __uint_as_float((unsigned)b[j] << 16);
+        else return (float)__builtin_bit_cast(_Float16, (unsigned short)b[j]);
+    }
+    __device__ __forceinline__ void zero() { b = u16x8{0, 0, 0, 0, 0, 0, 0, 0}; }
+};
+__device__ __forceinline__ unsigned short raw16(const _Float16 *p) {
+    return __builtin_bit_cast(unsigned short, *p);
+}
+__device__ __forceinline__ unsigned short raw16(const bf16 *p) { return p->bits; }
+// one row of PX consecutive elements at row + x0: 16-byte access (full),
+// 2-wide accesses (pairs), or one element at a time up to n (0 past it)
+template <typename T, int PX>
+__device__ __forceinline__ void ld_row(PixRow<T, PX> &r, const T *row, bool full, bool pairs, int n) {
+    if constexpr (PX == 4) {
+        if (full) {
+            const f32x4 a = ld4(row);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) r.v[j] = a[j];
+        } else if (pairs) {
+#pragma unroll
+            for (int j = 0; j < 4; j += 2) {
+                const f32x2 t = ld2(row + j);
+                r.v[j] = t.x;
+                r.v[j + 1] = t.y;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) r.v[j] = j < n ? ld(row + j) : 0.f;
+        }
+    } else {
+        if (full) {
+            r.b = *(const u16x8 *)row;
+        } else if (pairs) {
+#pragma unroll
+            for (int j = 0; j < 8; j += 2) {
+                const u16x2 t = *(const u16x2 *)(row + j);
+                r.b[j] = t.x;
+                r.b[j + 1] = t.y;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) r.b[j] = j < n ? raw16(row + j) : (unsigned short)0;
+        }
+    }
+}
+template <int PX, typename T>
+__device__ __forceinline__ void stv(T *p, const float *v) {
+    if constexpr (PX == 4) {
+        st4(p, f32x4{v[0], v[1], v[2], v[3]});
+    } else {
+        static_assert(PX == 8 && sizeof(T) == 2, "8-wide rows are 16-bit rows");
+        u16x8 b;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if constexpr (std::is_same<T, bf16>::value) b[j] = f32_to_bf16_bits(v[j]);
+            else b[j] = __builtin_bit_cast(unsigned short, from_f32<_Float16>(v[j]));
+        }
+        __builtin_nontemporal_store(b, (u16x8 *)p);
+    }
+}
+
+// q for CC channels (planes Q + c*Qps) of the wave's 8 x (64 PX) block at
+// (yb, xw), PX pixels per lane; mean_a_c = M + (c0+c)*lps,
+// mean_b_c = M + (C+c0+c)*lps.  S: compile-time ratio, 0 = read g.s at run
+// time.  Every pixel gets the same arithmetic whatever PX is.
 // EPI (detail enhancement): with P the c0-th plane of p (same layout as Q),
 // each output becomes e = q + gain (p - q), formed from the FP32 q before
 // the store's rounding.
-template <typename T, int CC, int S, bool EPI = false>
+template <typename T, int CC, int S, bool EPI = false, int PX = kOutPx>
 __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs, T *__restrict__ Q,
                                             int64_t Qrs, int64_t Qps, const float *__restrict__ M,
                                             const Geo &g, int c0, int yb, int xw, bool vec,
                                             const T *__restrict__ P = nullptr, int64_t Prs = 0,
                                             int64_t Pps = 0, float gain = 0.f) {
+    static_assert(PX == 4 || PX == 8, "4 or 8 pixels per lane");
     constexpr int ROWS = kOutRows;
     const int lane = threadIdx.x & 63;
-    const int x0 = xw + lane * kOutPx;
+    const int x0 = xw + lane * PX;
     const int nrows = min(ROWS, g.H - yb);
     if (x0 >= g.W || nrows <= 0) return;  // no barriers below
-    // Per row: four-wide accesses when every row allows them (vec), else
-    // two-wide ones on rows whose start is aligned for them (x0 is a
-    // multiple of 4), else one element at a time.
-    const bool in4 = x0 + 3 < g.W;
-    const bool full = vec && in4;
+    // Per row: 16-byte accesses when every row allows them (vec: row starts
+    // 16-byte aligned), else two-wide ones on rows whose start is aligned
+    // for them (x0 is a multiple of 4), else one element at a time.
+    const bool inpx = x0 + PX - 1 < g.W;
+    const bool full = vec && inpx;
 
-    auto load_row = [&](const T *plane, int64_t rs, int y) -> f32x4 {
-        f32x4 v = {0.f, 0.f, 0.f, 0.f};
-        const T *base = plane + (int64_t)y * rs, *row = base + x0;
-        if (full) {
-            v = ld4(row);
-        } else if (in4 && pair_aligned(base)) {
-            const f32x2 lo = ld2(row), hi = ld2(row + 2);
-            v = f32x4{lo.x, lo.y, hi.x, hi.y};
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (x0 + j < g.W) v[j] = ld(row + j);
-        }
-        return v;
+    typedef PixRow<T, PX> Row;
+    auto load_row = [&](const T *plane, int64_t rs, int y, Row &r) {
+        const T *base = plane + (int64_t)y * rs;
+        ld_row<T, PX>(r, base + x0, full, inpx && pair_aligned(base), g.W - x0);
     };
-    f32x4 iv[ROWS];
+    Row iv[ROWS];
 #pragma unroll
-    for (int i = 0; i < ROWS; ++i) iv[i] = i < nrows ? load_row(I, Irs, yb + i) : f32x4{0.f, 0.f, 0.f, 0.f};
-    auto store_q = [&](T *plane, int y, f32x4 v) {
+    for (int i = 0; i < ROWS; ++i) {
+        if (i < nrows) load_row(I, Irs, yb + i, iv[i]);
+        else iv[i].zero();
+    }
+    auto store_q = [&](T *plane, int y, const float *v) {
         T *base = plane + (int64_t)y * Qrs, *row = base + x0;
         if (full) {
-            st4(row, v);
-        } else if (in4 && pair_aligned(base)) {
-            st2(row, v[0], v[1]);
-            st2(row + 2, v[2], v[3]);
+            stv<PX>(row, v);
+        } else if (inpx && pair_aligned(base)) {
+#pragma unroll
+            for (int j = 0; j < PX; j += 2) st2(row + j, v[j], v[j + 1]);
         } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < PX; ++j)
                 if (x0 + j < g.W) st1(row + j, v[j]);
         }
     };
     // the rows of channel c of p, for the detail epilogue (loaded together)
-    f32x4 pv[EPI ? ROWS : 1] = {};
+    Row pv[EPI ? ROWS : 1];
+    pv[0].zero();
     auto load_p = [&](int c) {
         if constexpr (EPI) {
             const T *Pc = P + (int64_t)c * Pps;
 #pragma unroll
-            for (int i = 0; i < ROWS; ++i) pv[i] = i < nrows ? load_row(Pc, Prs, yb + i) : f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int i = 0; i < ROWS; ++i) {
+                if (i < nrows) load_row(Pc, Prs, yb + i, pv[i]);
+                else pv[i].zero();
+            }
         }
     };
-    auto finish = [&](f32x4 q, f32x4 pr) -> f32x4 {
+    auto finish = [&](float *q, const Row &pr) {
         if constexpr (EPI) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) q[j] = lerp(q[j], pr[j], gain);
+            for (int j = 0; j < PX; ++j) q[j] = lerp(q[j], pr.at(j), gain);
         }
-        return q;
     };
 
     if constexpr (S == 1) {
         // Algorithm 1: the maps are full resolution; rows are padded to a
-        // multiple of 16 floats, so the 16-byte read at x0 stays in the row.
+        // multiple of 16 floats, so the 16-byte reads at x0 stay in the row.
 #pragma unroll 1
         for (int c = 0; c < CC; ++c) {
             const float *Ma = M + (int64_t)(c0 + c) * g.lps;
@@ -762,19 +838,23 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
             for (int i = 0; i < ROWS; ++i) {
                 if (i < nrows) {
                     const int y = yb + i;
-                    const f32x4 a = ld4(Ma + (int64_t)y * g.lrs + x0);
-                    const f32x4 b = ld4(Mb + (int64_t)y * g.lrs + x0);
-                    f32x4 out;
+                    float out[PX];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) out[j] = madd(a[j], iv[i][j], b[j]);
-                    store_q(Qc, y, finish(out, pv[EPI ? i : 0]));
+                    for (int j = 0; j < PX; j += 4) {
+                        const f32x4 a = ld4(Ma + (int64_t)y * g.lrs + x0 + j);
+                        const f32x4 b = ld4(Mb + (int64_t)y * g.lrs + x0 + j);
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) out[j + k] = madd(a[k], iv[i].at(j + k), b[k]);
+                    }
+                    finish(out, pv[EPI ? i : 0]);
+                    store_q(Qc, y, out);
                 }
             }
         }
     } else if constexpr (S == 2 || S == 4 || S == 8) {
         // low-res rows base_y .. base_y + NL - 1 and columns base_x .. base_x + NC - 1
         constexpr int NL = cfloor_u(ROWS - 1, S) - cfloor_u(0, S) + 2;
-        constexpr int NC = cfloor_u(3, S) - cfloor_u(0, S) + 2;
+        constexpr int NC = cfloor_u(PX - 1, S) - cfloor_u(0, S) + 2;
         const int base_y = floordiv(2 * yb + 1 - S, 2 * S);
         const int base_x = floordiv(2 * x0 + 1 - S, 2 * S);
         int ry[NL], cx[NC];
@@ -782,35 +862,50 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
         for (int m = 0; m < NL; ++m) ry[m] = clampi(base_y + m, 0, g.Hl - 1);
 #pragma unroll
         for (int m = 0; m < NC; ++m) cx[m] = clampi(base_x + m, 0, g.Wl - 1);
-        // horizontal weights: compile time when s divides 4; for s = 8 they
-        // depend on whether the lane starts at 0 or 4 mod 8
-        float wx[4];
+        // horizontal weights and taps: compile time when s divides x0 (PX = 8,
+        // or s < 8); at s = 8 with four pixels per lane they depend on whether
+        // the lane starts at 0 or 4 mod 8, and the taps do not (offset 0)
+        constexpr bool XPHASE = S == 8 && PX == 4;
+        float wx[PX];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            wx[j] = (S == 8) ? (float)((2 * ((x0 & 7) + j) + 1 - 8) & 15) * (1.0f / 16.0f)
-                             : cfrac_u(j, S);
+        for (int j = 0; j < PX; ++j)
+            wx[j] = XPHASE ? (float)((2 * ((x0 & 7) + j) + 1 - 8) & 15) * (1.0f / 16.0f) : cfrac_u(j, S);
 #pragma unroll 1
         for (int c = 0; c < CC; ++c) {
             const float *Ma = M + (int64_t)(c0 + c) * g.lps;
             const float *Mb = M + (int64_t)(g.C + c0 + c) * g.lps;
             T *Qc = Q + (int64_t)c * Qps;
             load_p(c);
-            float ha[NL][4], hb[NL][4];
+            // the low-res values under the block, all loads in flight together
+            float va[NL][NC], vb[NL][NC];
 #pragma unroll
             for (int m = 0; m < NL; ++m) {
                 const float *ra = Ma + (int64_t)ry[m] * g.lrs;
                 const float *rb = Mb + (int64_t)ry[m] * g.lrs;
-                float va[NC], vb[NC];
 #pragma unroll
                 for (int k = 0; k < NC; ++k) {
-                    va[k] = ra[cx[k]];
-                    vb[k] = rb[cx[k]];
+                    va[m][k] = ra[cx[k]];
+                    vb[m][k] = rb[cx[k]];
                 }
+            }
+            // horizontal interpolation of low-res row m at pixel j
+            auto hlerp = [&](const float (&v)[NL][NC], int m, int j) -> float {
+                const int k0 = XPHASE ? 0 : cfloor_u(j, S) - cfloor_u(0, S);
+                return lerp(v[m][k0], v[m][k0 + 1], wx[j]);
+            };
+            // four pixels per lane: every row's horizontal values once, then
+            // the rows; eight: the two rows each output row needs, per row
+            // (same values, fewer live registers)
+            constexpr bool HOIST = PX == 4;
+            float ha[HOIST ? NL : 1][PX], hb[HOIST ? NL : 1][PX];
+            if constexpr (HOIST) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int k0 = cfloor_u(j, S) - cfloor_u(0, S);  // 0 for s = 8 as well
-                    ha[m][j] = lerp(va[k0], va[k0 + 1], wx[j]);
-                    hb[m][j] = lerp(vb[k0], vb[k0 + 1], wx[j]);
+                for (int m = 0; m < NL; ++m) {
+#pragma unroll
+                    for (int j = 0; j < PX; ++j) {
+                        ha[m][j] = hlerp(va, m, j);
+                        hb[m][j] = hlerp(vb, m, j);
+                    }
                 }
             }
 #pragma unroll
@@ -818,14 +913,17 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
                 if (i < nrows) {
                     const int m0 = cfloor_u(i, S) - cfloor_u(0, S);
                     const float wy = cfrac_u(i, S);
-                    f32x4 out;
+                    float out[PX];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const float a = lerp(ha[m0][j], ha[m0 + 1][j], wy);
-                        const float b = lerp(hb[m0][j], hb[m0 + 1][j], wy);
-                        out[j] = madd(a, iv[i][j], b);
+                    for (int j = 0; j < PX; ++j) {
+                        const float a0 = HOIST ? ha[m0][j] : hlerp(va, m0, j);
+                        const float a1 = HOIST ? ha[m0 + 1][j] : hlerp(va, m0 + 1, j);
+                        const float b0 = HOIST ? hb[m0][j] : hlerp(vb, m0, j);
+                        const float b1 = HOIST ? hb[m0 + 1][j] : hlerp(vb, m0 + 1, j);
+                        out[j] = madd(lerp(a0, a1, wy), iv[i].at(j), lerp(b0, b1, wy));
                     }
-                    store_q(Qc, yb + i, finish(out, pv[EPI ? i : 0]));
+                    finish(out, pv[EPI ? i : 0]);
+                    store_q(Qc, yb + i, out);
                 }
             }
         }
@@ -833,10 +931,10 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
         // any other ratio: taps computed per pixel and per row at run time
         const int s = g.s, s2 = 2 * s;
         const float inv2s = 1.0f / (float)s2;
-        int xa[4], xb[4];
-        float wx[4];
+        int xa[PX], xb[PX];
+        float wx[PX];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < PX; ++j) {
             const int num = 2 * (x0 + j) + 1 - s;
             const int l = floordiv(num, s2);
             wx[j] = (float)(num - s2 * l) * inv2s;
@@ -857,20 +955,29 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
                 const int k0 = clampi(l, 0, g.Hl - 1), k1 = clampi(l + 1, 0, g.Hl - 1);
                 const float *ra0 = Ma + (int64_t)k0 * g.lrs, *ra1 = Ma + (int64_t)k1 * g.lrs;
                 const float *rb0 = Mb + (int64_t)k0 * g.lrs, *rb1 = Mb + (int64_t)k1 * g.lrs;
-                f32x4 iy = {0.f, 0.f, 0.f, 0.f};
+                float iy[PX];
+#pragma unroll
+                for (int j = 0; j < PX; ++j) iy[j] = 0.f;
 #pragma unroll
                 for (int r = 0; r < ROWS; ++r)
-                    if (r == i) iy = iv[r];
-                f32x4 out;
+                    if (r == i) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                        for (int j = 0; j < PX; ++j) iy[j] = iv[r].at(j);
+                    }
+                float out[PX];
+#pragma unroll
+                for (int j = 0; j < PX; ++j) {
                     const float a0 = lerp(ra0[xa[j]], ra0[xb[j]], wx[j]);
                     const float a1 = lerp(ra1[xa[j]], ra1[xb[j]], wx[j]);
                     const float b0 = lerp(rb0[xa[j]], rb0[xb[j]], wx[j]);
                     const float b1 = lerp(rb1[xa[j]], rb1[xb[j]], wx[j]);
                     out[j] = madd(lerp(a0, a1, wy), iy[j], lerp(b0, b1, wy));
                 }
-                if constexpr (EPI) out = finish(out, load_row(P + (int64_t)c * Pps, Prs, y));
+                if constexpr (EPI) {
+                    Row pr;
+                    load_row(P + (int64_t)c * Pps, Prs, y, pr);
+                    finish(out, pr);
+                }
                 store_q(Qc, y, out);
             }
         }

@@ -16,19 +16,25 @@
 namespace gf {
 namespace {
 
-// One workgroup = 4 waves = a 256-column x 32-row block of q (EPI: of the
-// detail-enhanced e, reading the matching block of p).
+// Pixels per lane of the per-image output kernel: every row access is 16
+// bytes (4 fp32 or 8 16-bit values).
+template <typename T>
+constexpr int out_px() { return sizeof(T) == 2 ? 8 : 4; }
+
+// One workgroup = 4 waves = a (64 PX)-column x 32-row block of q (EPI: of
+// the detail-enhanced e, reading the matching block of p).
 template <typename T, int CC, int S, bool EPI>
 __global__ __launch_bounds__(kThreads) void k_output(const T *__restrict__ I, int64_t Irs,
                                                      T *__restrict__ Q, int64_t Qrs, int64_t Qps,
                                                      const float *__restrict__ M, Geo g, int c0,
                                                      int ntx, int ntiles, int vec, const T *__restrict__ P,
                                                      int64_t Prs, int64_t Pps, float gain) {
+    constexpr int PX = out_px<T>();
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;
-    output_rows<T, CC, S, EPI>(I, Irs, Q, Qrs, Qps, M, g, c0,
-                               (tile / ntx) * (4 * kOutRows) + wave_id() * kOutRows,
-                               (tile % ntx) * kOutTileW, vec != 0, P, Prs, Pps, gain);
+    output_rows<T, CC, S, EPI, PX>(I, Irs, Q, Qrs, Qps, M, g, c0,
+                                   (tile / ntx) * (4 * kOutRows) + wave_id() * kOutRows,
+                                   (tile % ntx) * (64 * PX), vec != 0, P, Prs, Pps, gain);
 }
 
 // Area subsampling (step 1 with the block mean): low-res pixel (ly, lx) of
@@ -141,7 +147,8 @@ hipError_t area_t(const View &I, const View &P, bool p_low, float *dst, const Ge
 template <typename T, int CC, bool EPI>
 hipError_t output_cc(const View &I, const View &Q, const float *mean, const Geo &g, int c0, bool vec,
                      hipStream_t st, hipEvent_t e0, hipEvent_t e1, const Detail &dt) {
-    const int ntx = (g.W + kOutTileW - 1) / kOutTileW;
+    const int tw = 64 * out_px<T>();
+    const int ntx = (g.W + tw - 1) / tw;
     const int nty = (g.H + 4 * kOutRows - 1) / (4 * kOutRows);
     const int ntiles = ntx * nty;
     const T *Ip = (const T *)I.data;
