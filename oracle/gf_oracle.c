@@ -41,7 +41,9 @@
  * upsampling against its assembly from library routines and against the fast
  * filter of a subsampled input; detail enhancement at its gain end points;
  * the padded borders against numpy's edge and reflect padding and scipy's
- * uniform filter, area subsampling against torch's average pooling).
+ * uniform filter, area subsampling against torch's average pooling; colour
+ * guidance against a least-squares solve of its windowed ridge regression,
+ * a library assembly, and the gray filter for a guide of three equal planes).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -464,6 +466,134 @@ int oracle_joint_upsample(const double *I, const double *p_lo, int c, int h, int
 {
     if (mode != ORACLE_NEAREST && mode != ORACLE_BILINEAR) return -1;
     return oracle_joint_upsample_ex(I, p_lo, c, h, w, r, s, eps, mode, ORACLE_CLIP, q);
+}
+
+/*
+ * Colour guidance (a three-channel guide I = (I0, I1, I2), planes of h*w).
+ * The paper names the number of channels as a cost factor and takes the
+ * colour form of the guided filter from its earlier definition: in every
+ * window the linear model is q = a^T I + b with a a 3-vector, fitted by
+ *   min  sum_{i in w_k} (a^T I_i + b - p_i)^2 + eps |a|^2
+ * (the same ridge regression as the gray Eqs. 1-3, one eps|a|^2 per pixel),
+ * whose solution is
+ *   a_k = (Sigma_k + eps U)^-1 (mean(I p) - mean(I) mean(p)),  b_k = mean(p) - a_k^T mean(I),
+ * with Sigma_k the 3x3 population covariance of I in the window and U the
+ * identity; q_i = mean_a(i)^T I_i + mean_b(i) with the box means of Eq. 4.
+ */
+
+/* x = M^-1 y for a 3x3 matrix M (row-major), by its adjugate and determinant. */
+static void solve3(const double M[9], const double y[3], double x[3])
+{
+    double adj[9];
+    adj[0] = M[4] * M[8] - M[5] * M[7];
+    adj[1] = M[2] * M[7] - M[1] * M[8];
+    adj[2] = M[1] * M[5] - M[2] * M[4];
+    adj[3] = M[5] * M[6] - M[3] * M[8];
+    adj[4] = M[0] * M[8] - M[2] * M[6];
+    adj[5] = M[2] * M[3] - M[0] * M[5];
+    adj[6] = M[3] * M[7] - M[4] * M[6];
+    adj[7] = M[1] * M[6] - M[0] * M[7];
+    adj[8] = M[0] * M[4] - M[1] * M[3];
+    double det = M[0] * adj[0] + M[1] * adj[3] + M[2] * adj[6];
+    for (int r = 0; r < 3; ++r)
+        x[r] = (adj[3 * r] * y[0] + adj[3 * r + 1] * y[1] + adj[3 * r + 2] * y[2]) / det;
+}
+
+/*
+ * Coefficients of the colour model for one channel of p: a (3 planes a0, a1,
+ * a2 of n = h*w) and b, every mean a box mean of radius r under `border`.
+ */
+static int coefficients_color(const double *I, const double *p, int h, int w, int r, double eps, int border,
+                              double *a, double *b)
+{
+    size_t n = (size_t)h * (size_t)w;
+    double *mI = (double *)malloc(sizeof(double) * 3 * n);    /* mean of I_j */
+    double *cII = (double *)malloc(sizeof(double) * 9 * n);   /* mean of I_j I_k */
+    double *cIp = (double *)malloc(sizeof(double) * 3 * n);   /* mean of I_j p */
+    double *mp = (double *)malloc(sizeof(double) * n);
+    double *tmp = (double *)malloc(sizeof(double) * n);
+    int rc = 0;
+    if (!mI || !cII || !cIp || !mp || !tmp) { rc = -2; goto done; }
+    if ((rc = oracle_box_mean_border(p, h, w, r, border, mp))) goto done;
+    for (int j = 0; j < 3; ++j) {
+        const double *Ij = I + (size_t)j * n;
+        if ((rc = oracle_box_mean_border(Ij, h, w, r, border, mI + (size_t)j * n))) goto done;
+        for (size_t i = 0; i < n; ++i) tmp[i] = Ij[i] * p[i];
+        if ((rc = oracle_box_mean_border(tmp, h, w, r, border, cIp + (size_t)j * n))) goto done;
+        for (int k = 0; k < 3; ++k) {
+            const double *Ik = I + (size_t)k * n;
+            for (size_t i = 0; i < n; ++i) tmp[i] = Ij[i] * Ik[i];
+            if ((rc = oracle_box_mean_border(tmp, h, w, r, border, cII + (size_t)(3 * j + k) * n))) goto done;
+        }
+    }
+    for (size_t i = 0; i < n; ++i) {
+        double M[9], cov[3], x[3];
+        for (int j = 0; j < 3; ++j) {
+            for (int k = 0; k < 3; ++k)
+                M[3 * j + k] = cII[(size_t)(3 * j + k) * n + i] - mI[(size_t)j * n + i] * mI[(size_t)k * n + i];
+            M[3 * j + j] += eps;
+            cov[j] = cIp[(size_t)j * n + i] - mI[(size_t)j * n + i] * mp[i];
+        }
+        solve3(M, cov, x);
+        double bi = mp[i];
+        for (int j = 0; j < 3; ++j) {
+            a[(size_t)j * n + i] = x[j];
+            bi -= x[j] * mI[(size_t)j * n + i];
+        }
+        b[i] = bi;
+    }
+done:
+    free(mI); free(cII); free(cIp); free(mp); free(tmp);
+    return rc;
+}
+
+/*
+ * The fast guided filter with a colour guide: I has 3 planes (h x w), p has c.
+ * Step 1 subsamples every plane of I and p (s = 1: the guided filter itself);
+ * a (3 per channel) and b at r' = r/s; their box means; bilinear upsampling;
+ * q = mean_a0 I0 + mean_a1 I1 + mean_a2 I2 + mean_b on the full-res guide.
+ * Optional outputs (may be NULL), low resolution: a_lo (c*3*hl*wl, channel k's
+ * three planes at 3k..3k+2), b_lo (c*hl*wl).
+ */
+int oracle_fast_guided_filter_color(const double *I, const double *p, int c, int h, int w, int r, int s,
+                                    double eps, int mode, int border, double *q, double *a_lo, double *b_lo)
+{
+    if (h <= 0 || w <= 0 || c <= 0 || r < 0 || s < 1 || !(eps > 0.0)) return -1;
+    if (mode != ORACLE_NEAREST && mode != ORACLE_BILINEAR && mode != ORACLE_AREA) return -1;
+    int hl = oracle_lowres_size(h, s), wl = oracle_lowres_size(w, s);
+    int rl = oracle_lowres_radius(r, s);
+    size_t n = (size_t)h * (size_t)w, nl = (size_t)hl * (size_t)wl;
+    double *Il = (double *)malloc(sizeof(double) * 3 * nl);
+    double *pl = (double *)malloc(sizeof(double) * nl);
+    double *ca = (double *)malloc(sizeof(double) * 3 * nl);
+    double *cb = (double *)malloc(sizeof(double) * nl);
+    double *mean_lo = (double *)malloc(sizeof(double) * nl);
+    double *up = (double *)malloc(sizeof(double) * n);
+    int rc = 0;
+    if (!Il || !pl || !ca || !cb || !mean_lo || !up) { rc = -2; goto done; }
+    for (int j = 0; j < 3; ++j)
+        if ((rc = oracle_subsample(I + (size_t)j * n, h, w, s, mode, Il + (size_t)j * nl))) goto done;
+    for (int k = 0; k < c; ++k) {
+        double *qk = q + (size_t)k * n;
+        if ((rc = oracle_subsample(p + (size_t)k * n, h, w, s, mode, pl))) goto done;
+        if ((rc = coefficients_color(Il, pl, hl, wl, rl, eps, border, ca, cb))) goto done;
+        if (a_lo) memcpy(a_lo + (size_t)3 * k * nl, ca, sizeof(double) * 3 * nl);
+        if (b_lo) memcpy(b_lo + (size_t)k * nl, cb, sizeof(double) * nl);
+        /* q = sum_j up(mean(a_j)) I_j + up(mean(b)), terms added in that order */
+        for (size_t i = 0; i < n; ++i) qk[i] = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            if ((rc = oracle_box_mean_border(ca + (size_t)j * nl, hl, wl, rl, border, mean_lo))) goto done;
+            if ((rc = oracle_upsample(mean_lo, hl, wl, s, h, w, up))) goto done;
+            const double *Ij = I + (size_t)j * n;
+            for (size_t i = 0; i < n; ++i) qk[i] += up[i] * Ij[i];
+        }
+        if ((rc = oracle_box_mean_border(cb, hl, wl, rl, border, mean_lo))) goto done;
+        if ((rc = oracle_upsample(mean_lo, hl, wl, s, h, w, up))) goto done;
+        for (size_t i = 0; i < n; ++i) qk[i] += up[i];
+    }
+done:
+    free(Il); free(pl); free(ca); free(cb); free(mean_lo); free(up);
+    return rc;
 }
 
 /*

@@ -78,6 +78,7 @@ class Oracle:
             "oracle_joint_upsample": [_DP, _DP, i, i, i, i, i, d, i, _DP],
             "oracle_joint_upsample_ex": [_DP, _DP, i, i, i, i, i, d, i, i, _DP],
             "oracle_detail_enhance": [_DP, _DP, ctypes.c_size_t, d, _DP],
+            "oracle_fast_guided_filter_color": [_DP, _DP, i, i, i, i, i, d, i, i, _DP, _DP, _DP],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -214,6 +215,29 @@ class Oracle:
                    "oracle_joint_upsample_ex")
         return q[0] if squeeze else q
 
+    def fast_guided_filter_color(self, I, p, r: int, s: int, eps: float, mode="nearest", border="clip",
+                                 intermediates: bool = False):
+        """Colour guidance: ``I`` is (3, h, w), ``p`` (h, w) or (c, h, w).
+        s = 1 is the guided filter itself.  Low-res intermediates: a
+        (c, 3, hl, wl) and b (c, hl, wl)."""
+        I = np.ascontiguousarray(_f64(I))
+        assert I.ndim == 3 and I.shape[0] == 3, I.shape
+        h, w = I.shape[1:]
+        p3, squeeze = self._as_chw(p, h, w)
+        c = p3.shape[0]
+        hl, wl = self.lowres_size(h, s), self.lowres_size(w, s)
+        q = np.empty_like(p3)
+        a = np.empty((c, 3, hl, wl)) if intermediates else None
+        b = np.empty((c, hl, wl)) if intermediates else None
+        _check(self.lib.oracle_fast_guided_filter_color(
+            _ptr(I), _ptr(p3), c, h, w, int(r), int(s), float(eps), _MODES[mode], _BORDERS[border], _ptr(q),
+            _ptr(a), _ptr(b)), "oracle_fast_guided_filter_color")
+        if squeeze:
+            q = q[0]
+            if intermediates:
+                a, b = a[0], b[0]
+        return (q, {"a": a, "b": b}) if intermediates else q
+
     def detail_enhance(self, p, q, gain: float):
         """e = q + gain (p - q), elementwise (p and q of one shape)."""
         p, q = _f64(p), _f64(q)
@@ -275,3 +299,11 @@ def joint_upsample(I, p_lo, r, s, eps, mode="nearest", border="clip"):
 
 def detail_enhance(p, q, gain):
     return default().detail_enhance(p, q, gain)
+
+
+def fast_guided_filter_color(I, p, r, s, eps, mode="nearest", border="clip", intermediates=False):
+    return default().fast_guided_filter_color(I, p, r, s, eps, mode, border, intermediates)
+
+
+def guided_filter_color(I, p, r, eps, border="clip"):
+    return default().fast_guided_filter_color(I, p, r, 1, eps, "nearest", border)

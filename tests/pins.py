@@ -576,4 +576,106 @@ def pin_border_constant(orc):
                f"constant guide {border}")
 
 
+# ---------------------------------------------------------------- colour guidance
+
+def _windows(n, i, r, border):
+    """Indices along an axis that the window of radius r at i reads."""
+    if border == "clip":
+        return list(range(max(0, i - r), min(n - 1, i + r) + 1))
+    idx = np.pad(np.arange(n), r, mode=_NP_PAD[border])
+    return list(idx[i:i + 2 * r + 1])
+
+
+def pin_color_coefficients_lstsq(orc):
+    """a_k (3-vector), b_k minimise sum_{i in w_k} (a.I_i + b - p_i)^2 + |w_k| eps |a|^2
+    over the window's samples (clip-normalised and padded windows)."""
+    g = _rng(51)
+    h, w = 7, 9
+    I = g.uniform(0, 1, size=(3, h, w))
+    p = 0.3 * I[0] - 0.2 * I[1] + 0.5 * I[2] + g.uniform(0, 0.3, size=(h, w))
+    for border in ("clip", "replicate", "reflect101"):
+        for r, eps in [(1, 1e-2), (2, 0.2), (4, 1e-3)]:
+            _, ex = orc.fast_guided_filter_color(I, p, r, 1, eps, border=border, intermediates=True)
+            for ky, kx in [(0, 0), (0, w - 1), (h - 1, 4), (3, 4), (h - 1, w - 1), (2, 0)]:
+                ys, xs = _windows(h, ky, r, border), _windows(w, kx, r, border)
+                Iw = np.stack([I[j][np.ix_(ys, xs)].ravel() for j in range(3)], 1)
+                pw = p[np.ix_(ys, xs)].ravel()
+                n = pw.size
+                A = np.vstack([np.hstack([Iw, np.ones((n, 1))]),
+                               np.hstack([math.sqrt(n * eps) * np.eye(3), np.zeros((3, 1))])])
+                sol = np.linalg.lstsq(A, np.concatenate([pw, np.zeros(3)]), rcond=None)[0]
+                assert np.allclose(ex["a"][:, ky, kx], sol[:3], atol=1e-9, rtol=0), (border, r, ky, kx)
+                assert abs(ex["b"][ky, kx] - sol[3]) < 1e-9, (border, r, ky, kx)
+
+
+def composed_color(I, p, r, s, eps, mode, border):
+    """Colour guidance from library routines: torch subsampling (or pooling),
+    scipy box means, numpy's batched 3x3 solve, torch upsampling."""
+    h, w = I.shape[1:]
+    rl = 0 if r == 0 else max(1, int(math.floor(r / s + 0.5)))
+    Il = np.stack([lib_sub(I[j], s, mode) if s > 1 else I[j] for j in range(3)])
+    pl = lib_sub(p, s, mode) if s > 1 else p
+    mI = np.stack([lib_box(Il[j], rl, border) for j in range(3)])
+    mp = lib_box(pl, rl, border)
+    S = np.empty(Il.shape[1:] + (3, 3))
+    for j in range(3):
+        for k in range(3):
+            S[..., j, k] = lib_box(Il[j] * Il[k], rl, border) - mI[j] * mI[k]
+    S += eps * np.eye(3)
+    cov = np.stack([lib_box(Il[j] * pl, rl, border) - mI[j] * mp for j in range(3)], -1)
+    a = np.linalg.solve(S, cov[..., None])[..., 0]
+    b = mp - np.einsum("...j,j...->...", a, mI)
+    up = (lambda x: x) if s == 1 else (lambda x: torch_upsample(x, s, h, w))
+    q = up(lib_box(b, rl, border))
+    for j in range(3):
+        q = q + up(lib_box(a[..., j], rl, border)) * I[j]
+    return q
+
+
+def pin_color_composition(orc):
+    """The colour filter (plain and fast, every border and subsampling)
+    equals its assembly from library routines."""
+    g = _rng(52)
+    for (h, w), r, s, eps, mode, border in [((23, 31), 4, 1, 1e-2, "nearest", "clip"),
+                                            ((37, 45), 8, 4, 1e-2, "nearest", "clip"),
+                                            ((30, 21), 5, 2, 1e-3, "bilinear", "reflect101"),
+                                            ((29, 33), 6, 3, 1e-1, "area", "replicate"),
+                                            ((12, 40), 12, 4, 1e-3, "nearest", "reflect101")]:
+        I = g.uniform(0, 1, size=(3, h, w))
+        p = np.clip(0.5 * I[0] + 0.3 * I[2] + g.normal(0, 0.1, size=(h, w)), 0, 1)
+        _close(orc.fast_guided_filter_color(I, p, r, s, eps, mode, border), composed_color(I, p, r, s, eps, mode, border),
+               1e-10, f"colour {h}x{w} r={r} s={s} {mode} {border}")
+
+
+def pin_color_gray_guide(orc):
+    """A guide of three equal planes G: the colour filter is the gray filter
+    of G with eps/3 (Sigma = var 11^T, whose eigenvalue along (1,1,1) is
+    3 var, so a = cov / (3 var + eps) (1,1,1))."""
+    g = _rng(53)
+    G = g.uniform(0, 1, size=(26, 34))
+    p = g.uniform(0, 1, size=(2, 26, 34))
+    for s, mode, border in [(1, "nearest", "clip"), (4, "nearest", "clip"), (2, "bilinear", "reflect101")]:
+        _close(orc.fast_guided_filter_color(np.stack([G, G, G]), p, 6, s, 3e-2, mode, border),
+               orc.fast_guided_filter(G, p, 6, s, 1e-2, mode, border=border), 1e-10, f"equal planes s={s}")
+
+
+def pin_color_invariants(orc):
+    """Constant p returns p; adding a constant to a guide plane changes
+    nothing; a p that is an affine function of the guide comes back as
+    itself as eps -> 0; channels of p are independent."""
+    g = _rng(54)
+    I = g.uniform(0, 1, size=(3, 19, 23))
+    _close(orc.fast_guided_filter_color(I, np.full((19, 23), 0.25), 5, 2, 1e-2), np.full((19, 23), 0.25), 1e-13,
+           "constant p")
+    p = g.uniform(0, 1, size=(19, 23))
+    q = orc.fast_guided_filter_color(I, p, 5, 2, 1e-2)
+    _close(orc.fast_guided_filter_color(I + np.array([0.3, -0.2, 0.1])[:, None, None], p, 5, 2, 1e-2),
+           q, 1e-9, "guide offset")
+    lin = 0.4 * I[0] - 0.7 * I[1] + 0.2 * I[2] + 0.1
+    _close(orc.fast_guided_filter_color(I, lin, 3, 1, 1e-12), lin, 1e-7, "affine p")
+    pp = g.uniform(0, 1, size=(2, 19, 23))
+    both = orc.fast_guided_filter_color(I, pp, 4, 2, 1e-2)
+    _close(both[1], orc.fast_guided_filter_color(I, pp[1], 4, 2, 1e-2), 0.0, "channel independence")
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -60,6 +60,19 @@ MUTANTS = {
                             "if ((rc = coefficients(Il, pl, hl, wl, rl, eps, ORACLE_CLIP, a, b))) goto done;"),
     "area_divides_by_full_block": ("acc / ((double)(y1 - y0) * (double)(x1 - x0))", "acc / ((double)s * (double)s)"),
     "area_block_shifted": ("int x0 = s * xx, x1 = imin(w, s * xx + s);", "int x0 = s * xx + s / 2, x1 = imin(w, s * xx + s);"),
+    "color_eps_off_diagonal": ("M[3 * j + j] += eps;", "M[3 * j + ((j + 1) % 3)] += eps;"),
+    "color_cov_wrong_mean": ("cov[j] = cIp[(size_t)j * n + i] - mI[(size_t)j * n + i] * mp[i];",
+                             "cov[j] = cIp[(size_t)j * n + i] - mI[(size_t)j * n + i] * mI[(size_t)j * n + i];"),
+    "color_adjugate_sign": ("adj[1] = M[2] * M[7] - M[1] * M[8];", "adj[1] = M[1] * M[8] - M[2] * M[7];"),
+    "color_determinant_sign": ("double det = M[0] * adj[0] + M[1] * adj[3] + M[2] * adj[6];",
+                               "double det = M[0] * adj[0] + M[1] * adj[3] - M[2] * adj[6];"),
+    "color_b_one_channel_mean": ("bi -= x[j] * mI[(size_t)j * n + i];", "bi -= x[j] * mI[i];"),
+    "color_cross_terms_dropped": ("for (size_t i = 0; i < n; ++i) tmp[i] = Ij[i] * Ik[i];",
+                                  "for (size_t i = 0; i < n; ++i) tmp[i] = Ij[i] * Ij[i];"),
+    "color_output_skips_plane": ("        for (int j = 0; j < 3; ++j) {\n            if ((rc = oracle_box_mean_border(ca",
+                                 "        for (int j = 0; j < 2; ++j) {\n            if ((rc = oracle_box_mean_border(ca"),
+    "color_output_planes_swapped": ("const double *Ij = I + (size_t)j * n;\n            for (size_t i = 0; i < n; ++i) qk[i] += up[i] * Ij[i];",
+                                    "const double *Ij = I + (size_t)(2 - j) * n;\n            for (size_t i = 0; i < n; ++i) qk[i] += up[i] * Ij[i];"),
 }
 
 
