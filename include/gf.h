@@ -29,6 +29,17 @@
  *     taps clamped to the low-res map;
  *   - a multi-channel p is filtered channel by channel with the same gray I.
  *
+ * Colour guide (I with 3 channels; the paper counts channels as a cost
+ * factor and takes the colour form of the guided filter from its earlier
+ * definition): per window q = a.I + b with a a 3-vector,
+ * a = (Sigma + eps U)^-1 (mean(I p) - mean(I) mean(p)), b = mean(p) - a.mean(I),
+ * Sigma the 3x3 population covariance of I in the window (sums in FP64, the
+ * 3x3 solve in FP64), and q = mean_a.I + mean_b.  gf_plain, gf_fast and the
+ * batched and prepared-batch calls take it (a batch holding one runs image
+ * by image); gf_joint_upsample, gf_detail_enhance, gf_tune and gf_submit
+ * refuse it (GF_ENOTSUP), as they do a low-res radius whose colour tiles do
+ * not fit in LDS (above about 24).
+ *
  * Options for the conventions of other image libraries (gf_params):
  *   - GF_BORDER_REPLICATE / GF_BORDER_REFLECT101: every box mean (of the
  *     statistics and of a, b) reads the map extended past its edges, by
@@ -98,7 +109,8 @@ typedef enum { GF_SUB_NEAREST = 0, GF_SUB_BILINEAR = 1, GF_SUB_AREA = 2 } gf_sub
  * A c x h x w image in device memory.  Element (k, y, x) is at
  * data + k*plane_stride + y*row_stride + x, strides counted in ELEMENTS.
  * Requirements: c >= 1, h >= 1, w >= 1, row_stride >= w,
- * plane_stride >= h*row_stride when c > 1.  For I, c must be 1.
+ * plane_stride >= h*row_stride when c > 1.  For I, c is 1 (gray) or 3
+ * (colour guide).
  */
 typedef struct {
     void *data;
@@ -141,13 +153,19 @@ void gf_ctx_destroy(gf_ctx *ctx);
 const char *gf_last_error(const gf_ctx *ctx);
 
 /* Device workspace (bytes) gf_fast needs for an h x w image with c channels
- * of p: 4c low-resolution FP32 maps (a, b and their box means).  Returns 0
- * for invalid arguments. */
+ * of p and a gray guide: 4c low-resolution FP32 maps (a, b and their box
+ * means), plus 1 + c with area subsampling.  Returns 0 for invalid
+ * arguments. */
 size_t gf_workspace_bytes(int32_t h, int32_t w, int32_t c, const gf_params *params);
+
+/* The same for a guide of guide_c channels (1 or 3): a colour guide needs 8c
+ * maps (a_0, a_1, a_2, b and their box means), plus 3 + c with area
+ * subsampling. */
+size_t gf_workspace_bytes_guide(int32_t h, int32_t w, int32_t guide_c, int32_t c, const gf_params *params);
 
 /*
  * Algorithm 1 (guided filter) at full resolution: q = mean_a .* I + mean_b.
- * I: 1 x h x w; p, q: c x h x w; all three of one dtype; q must not overlap
+ * I: 1 x h x w (or 3 x h x w, colour guide); p, q: c x h x w; all three of one dtype; q must not overlap
  * I or p.  Enqueued on `hip_stream` (a hipStream_t; NULL = default stream);
  * returns after enqueue.  workspace: device memory of at least
  * gf_workspace_bytes(h, w, c, {r, 1, eps}) bytes, or NULL for the context's.

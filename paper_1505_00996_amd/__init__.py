@@ -35,7 +35,7 @@ EXPORTS = ("gf_ctx_create", "gf_ctx_destroy", "gf_last_error", "gf_workspace_byt
            "gf_ctx_profile", "gf_ctx_profile_read", "gf_ctx_set_tiles", "gf_tune",
            "gf_ctx_save_tuning", "gf_ctx_load_tuning", "gf_batch_create", "gf_batch_launch",
            "gf_batch_destroy", "gf_ctx_set_batch_cfg", "gf_tune_batched", "gf_footprint_bytes", "gf_joint_upsample",
-           "gf_detail_enhance")
+           "gf_detail_enhance", "gf_workspace_bytes_guide")
 KERNELS = ("coeff", "box", "output", "batched", "area")
 
 
@@ -116,6 +116,7 @@ def lib() -> ctypes.CDLL:
             "gf_ctx_destroy": (None, [VP]),
             "gf_last_error": (ctypes.c_char_p, [VP]),
             "gf_workspace_bytes": (SZ, [I32, I32, I32, par_p]),
+            "gf_workspace_bytes_guide": (SZ, [I32, I32, I32, I32, par_p]),
             "gf_plain": (ctypes.c_int, [VP, img_p, img_p, img_p, I32, D, ctypes.c_int, VP, SZ, VP]),
             "gf_fast": (ctypes.c_int, [VP, img_p, img_p, img_p, par_p, VP, SZ, VP]),
             "gf_joint_upsample": (ctypes.c_int, [VP, img_p, img_p, img_p, par_p, VP, SZ, VP]),
@@ -199,8 +200,13 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def workspace_bytes(h: int, w: int, c: int, r: int, s: int, eps: float, sub="nearest", border="clip") -> int:
-    return int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(params(r, s, eps, sub, border))))
+def workspace_bytes(h: int, w: int, c: int, r: int, s: int, eps: float, sub="nearest", border="clip",
+                    guide_c: int = 1) -> int:
+    return int(lib().gf_workspace_bytes_guide(h, w, guide_c, c, ctypes.byref(params(r, s, eps, sub, border))))
+
+
+def _guide_c(I) -> int:
+    return 1 if I.dim() == 2 else int(I.shape[0])
 
 
 def _workspace(nbytes: int, device):
@@ -220,13 +226,14 @@ def _out_like(p, q):
 
 def gf_fast(I, p, r: int, s: int, eps: float, sub: str = "nearest", q=None, ctx=None,
             workspace=None, stream=None, border: str = "clip"):
-    """Algorithm 2 on the GPU: returns q (shape of p).  ``I`` is (H, W);
-    ``p`` is (H, W) or (C, H, W); same dtype (float32 / float16 / bfloat16)."""
+    """Algorithm 2 on the GPU: returns q (shape of p).  ``I`` is (H, W), or
+    (3, H, W) for a colour guide; ``p`` is (H, W) or (C, H, W); same dtype
+    (float32 / float16 / bfloat16)."""
     q = _out_like(p, q)
     pr = params(r, s, eps, sub, border)
     h, w = I.shape[-2:]
     c = 1 if p.dim() == 2 else p.shape[0]
-    need = int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(pr)))
+    need = int(lib().gf_workspace_bytes_guide(h, w, _guide_c(I), c, ctypes.byref(pr)))
     if workspace is None:
         workspace = _workspace(need, p.device)
     _check(lib().gf_fast(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p)),
@@ -271,12 +278,13 @@ def gf_detail_enhance(I, p, r: int, s: int, eps: float, gain: float, sub: str = 
 
 
 def gf_plain(I, p, r: int, eps: float, q=None, ctx=None, workspace=None, stream=None, border: str = "clip"):
-    """Algorithm 1 on the GPU (full resolution): returns q (shape of p)."""
+    """Algorithm 1 on the GPU (full resolution): returns q (shape of p).
+    ``I`` is (H, W), or (3, H, W) for a colour guide."""
     q = _out_like(p, q)
     pr = params(r, 1, eps, "nearest", border)
     h, w = I.shape[-2:]
     c = 1 if p.dim() == 2 else p.shape[0]
-    need = int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(pr)))
+    need = int(lib().gf_workspace_bytes_guide(h, w, _guide_c(I), c, ctypes.byref(pr)))
     if workspace is None:
         workspace = _workspace(need, p.device)
     _check(lib().gf_plain(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p)),

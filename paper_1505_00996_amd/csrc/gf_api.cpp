@@ -54,8 +54,9 @@ static int reflections(int n, int R) {
     return most;
 }
 
-Geo make_geo(int H, int W, int C, const gf_params &pr) {
+Geo make_geo(int H, int W, int C, const gf_params &pr, int G) {
     Geo g;
+    g.G = G;
     const int s = pr.s;
     g.H = H;
     g.W = W;
@@ -107,9 +108,11 @@ bool tiles_fit(const Geo &g, const TileCfg &t) {
 }
 
 size_t workspace_bytes(const Geo &g) {
-    // a, b (2C planes) and their box means (2C planes), FP32; with area
-    // subsampling also I' and the C channels of p' (1 + C planes)
-    return sizeof(float) * (size_t)(4 * g.C + (area_pass(g) ? 1 + g.C : 0)) * (size_t)g.lps;
+    // a, b (2C planes, or 4C with a colour guide: a_0..a_2, b) and their box
+    // means, FP32; with area subsampling also the G channels of I' and the C
+    // channels of p'
+    const int maps = (g.G == 3 ? 4 : 2) * g.C;
+    return sizeof(float) * (size_t)(2 * maps + (area_pass(g) ? g.G + g.C : 0)) * (size_t)g.lps;
 }
 
 static size_t elem_size(gf_dtype d) { return d == GF_F32 ? 4 : 2; }
@@ -154,7 +157,7 @@ gf_status validate(const gf_image *I, const gf_image *p, const gf_image *q,
     if ((st = check_image(p, "p")) != GF_OK) return st;
     if ((st = check_image(q, "q")) != GF_OK) return st;
     if (!pr) return fail(GF_EINVAL, "params: null");
-    if (I->c != 1) return fail(GF_ENOTSUP, "I: colour guidance (c=%d) is not supported; I must be gray", I->c);
+    if (I->c != 1 && I->c != 3) return fail(GF_ENOTSUP, "I: a guide has 1 (gray) or 3 (colour) channels, not %d", I->c);
     if (pr->s < 1) return fail(GF_EINVAL, "s = %d < 1", pr->s);
     // p is full resolution, or (joint upsampling) ceil(h/s) x ceil(w/s)
     const int ph = p_low ? (I->h + pr->s - 1) / pr->s : I->h, pw = p_low ? (I->w + pr->s - 1) / pr->s : I->w;
@@ -177,6 +180,12 @@ gf_status validate(const gf_image *I, const gf_image *p, const gf_image *q,
     if (I->h > (1 << 24) || I->w > (1 << 24)) return fail(GF_ENOTSUP, "image side above 2^24");
     if (lowres_radius(pr->r, pr->s) > kMaxRadius)
         return fail(GF_ENOTSUP, "low-res radius %d above %d", lowres_radius(pr->r, pr->s), kMaxRadius);
+    if (I->c == 3) {
+        if (p_low) return fail(GF_ENOTSUP, "joint upsampling with a colour guide is not supported");
+        if (!color_tile_h(TileCfg{8, 8}, lowres_radius(pr->r, pr->s)))
+            return fail(GF_ENOTSUP, "colour guide: low-res radius %d too large for the LDS tiles",
+                        lowres_radius(pr->r, pr->s));
+    }
     return GF_OK;
 }
 
@@ -195,7 +204,7 @@ bool vector_ok(const gf_image *I, const gf_image *q, size_t bytes) {
 gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
                    const gf_params *pr, void *ws, size_t ws_bytes, hipStream_t st,
                    const TileCfg *tiles, bool p_low, const float *gain) {
-    const Geo g = make_geo(I->h, I->w, p->c, *pr);
+    const Geo g = make_geo(I->h, I->w, p->c, *pr, I->c);
     // pinned or tuned shapes that do not fit this radius fall back to the built-in choice
     const TileCfg t = (tiles && tiles_fit(g, *tiles)) ? *tiles : default_tiles(g);
     if (!tiles_fit(g, t)) return fail(GF_ENOTSUP, "tile shapes do not fit in LDS for r'=%d", g.R);
@@ -204,9 +213,11 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
     if (ws_bytes < need)
         return fail(GF_ENOMEM, "workspace of %zu bytes < %zu needed", ws_bytes, need);
     if ((uintptr_t)ws % 256) return fail(GF_EINVAL, "workspace not 256-byte aligned");
+    const bool color = g.G == 3;
+    const int maps = (color ? 4 : 2) * g.C;
     float *coef = (float *)ws;
-    float *mean = coef + (size_t)(2 * g.C) * g.lps;
-    float *lowres = mean + (size_t)(2 * g.C) * g.lps;  // area subsampling: I', then p'
+    float *mean = coef + (size_t)maps * g.lps;
+    float *lowres = mean + (size_t)maps * g.lps;  // area subsampling: I' (G planes), then p'
     const View vI{I->data, I->row_stride, I->plane_stride};
     const View vP{p->data, p->row_stride, p->plane_stride};
     const View vQ{q->data, q->row_stride, q->plane_stride};
@@ -218,16 +229,29 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
     }
     if (e == hipSuccess) {
         ProfScope ps(ctx, GF_K_COEFF, st, true);
-        e = area_pass(g) ? launch_coeff_lowres(lowres, lowres + g.lps, coef, g, t, st, ps.stamp())
-                         : launch_coeff(I->dtype, vI, vP, coef, g, t, st, ps.stamp(), p_low);
+        const float *pl = lowres + (size_t)g.G * g.lps;
+        if (color)
+            e = area_pass(g) ? launch_coeff_color_lowres(lowres, pl, coef, g, t, st, ps.stamp())
+                             : launch_coeff_color(I->dtype, vI, vP, coef, g, t, st, ps.stamp());
+        else
+            e = area_pass(g) ? launch_coeff_lowres(lowres, pl, coef, g, t, st, ps.stamp())
+                             : launch_coeff(I->dtype, vI, vP, coef, g, t, st, ps.stamp(), p_low);
         ps.commit(e == hipSuccess);
     }
     if (e == hipSuccess) {
+        // the box tiles run over maps = 2 * gb.C planes
+        Geo gb = g;
+        gb.C = maps / 2;
         ProfScope ps(ctx, GF_K_BOX, st, true);
-        e = launch_box(coef, mean, g, t, st, ps.stamp());
+        e = launch_box(coef, mean, gb, t, st, ps.stamp());
         ps.commit(e == hipSuccess);
     }
-    if (e == hipSuccess) {
+    if (e == hipSuccess && color) {
+        ProfScope ps(ctx, GF_K_OUTPUT, st, true);
+        const size_t es = I->dtype == GF_F32 ? 4 : 2;
+        e = launch_output_color(I->dtype, vI, vQ, mean, g, vector_ok(I, q, 4 * es), st, ps.stamp());
+        ps.commit(e == hipSuccess);
+    } else if (e == hipSuccess) {
         ProfScope ps(ctx, GF_K_OUTPUT, st, true);
         Detail dt;
         if (gain) {
@@ -273,8 +297,12 @@ extern "C" {
 const char *gf_last_error(const gf_ctx *) { return gf::last_error(); }
 
 size_t gf_workspace_bytes(int32_t h, int32_t w, int32_t c, const gf_params *pr) {
-    if (!pr || h < 1 || w < 1 || c < 1 || pr->s < 1 || pr->r < 0) return 0;
-    return workspace_bytes(make_geo(h, w, c, *pr));
+    return gf_workspace_bytes_guide(h, w, 1, c, pr);
+}
+
+size_t gf_workspace_bytes_guide(int32_t h, int32_t w, int32_t guide_c, int32_t c, const gf_params *pr) {
+    if (!pr || h < 1 || w < 1 || c < 1 || pr->s < 1 || pr->r < 0 || (guide_c != 1 && guide_c != 3)) return 0;
+    return workspace_bytes(make_geo(h, w, c, *pr, guide_c));
 }
 
 static gf_status fast_entry(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q, const gf_params *pr,
@@ -283,7 +311,7 @@ static gf_status fast_entry(gf_ctx *ctx, const gf_image *I, const gf_image *p, g
     if (st != GF_OK) return st;
     if (!ws) {
         if (!ctx) return fail(GF_EINVAL, "workspace is NULL and there is no context");
-        const Geo g = make_geo(I->h, I->w, p->c, *pr);
+        const Geo g = make_geo(I->h, I->w, p->c, *pr, I->c);
         if ((st = ctx_use_device(ctx)) != GF_OK) return st;
         ws_bytes = workspace_bytes(g);
         if ((st = ctx_workspace(ctx, ws_bytes, &ws)) != GF_OK) return st;
@@ -309,6 +337,7 @@ gf_status gf_detail_enhance(gf_ctx *ctx, const gf_image *I, const gf_image *p, g
                             const gf_params *pr, double gain, void *ws, size_t ws_bytes, void *stream) {
     const float g = (float)gain;
     if (!isfinite(gain) || !isfinite(g)) return fail(GF_EINVAL, "gain = %g must be finite (in FP32)", gain);
+    if (I && I->c == 3) return fail(GF_ENOTSUP, "detail enhancement with a colour guide is not supported");
     return fast_entry(ctx, I, p, e, pr, ws, ws_bytes, stream, false, &g);
 }
 

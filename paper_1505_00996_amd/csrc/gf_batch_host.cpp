@@ -67,20 +67,21 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
     if (!I || !p || !q || !pr) return fail(GF_EINVAL, "batch: null array");
     gf_status st;
     int maxR = 0;
-    bool area = false;
+    bool per_image = false;
     for (int i = 0; i < n; ++i) {
         if ((st = validate(&I[i], &p[i], &q[i], &pr[i])) != GF_OK)
             return fail(st, "image %d: %s", i, last_error());
         if (I[i].dtype != I[0].dtype) return fail(GF_EINVAL, "image %d: dtype differs from image 0", i);
         maxR = std::max(maxR, lowres_radius(pr[i].r, pr[i].s));
-        area = area || (pr[i].sub == GF_SUB_AREA && pr[i].s > 1);
+        per_image = per_image || (pr[i].sub == GF_SUB_AREA && pr[i].s > 1) || I[i].c == 3;
     }
     plan->n = n;
     plan->dtype = I[0].dtype;
     plan->sched = cfg.schedule;
-    // area subsampling has a pass of its own that the batched kernels do not
-    // run: such a batch goes image by image
-    plan->th = area ? 0 : batch_th(cfg.schedule, cfg.tile_h, maxR, plan);
+    // area subsampling has a pass of its own and a colour guide kernels of
+    // its own that the batched kernels do not run: such a batch goes image
+    // by image
+    plan->th = per_image ? 0 : batch_th(cfg.schedule, cfg.tile_h, maxR, plan);
     plan->desc.assign(n, BDesc{});
     // plan order: by ratio class (stable), so each class's output blocks are contiguous
     plan->order.resize(n);
@@ -96,7 +97,7 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
     for (int k = 0; k < n; ++k) {
         const int i = plan->order[k];
         BDesc &d = plan->desc[k];
-        const Geo g = make_geo(I[i].h, I[i].w, p[i].c, pr[i]);
+        const Geo g = make_geo(I[i].h, I[i].w, p[i].c, pr[i], I[i].c);
         d.I = I[i].data;
         d.P = p[i].data;
         d.Q = q[i].data;
@@ -116,12 +117,12 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
         d.ntiles[0] = (unsigned)(d.ntx_l * d.nty_l);  // a coefficient task covers every channel
         d.ntiles[1] = (unsigned)(d.ntx_l * d.nty_l * 2 * g.C);
         d.ntiles[2] = (unsigned)(d.ntx_o * d.nty_o * ((g.C + 2) / 3));
-        const size_t planes = sizeof(float) * (size_t)g.lps * 2 * g.C;
+        // the image's workspace as gf_fast lays it out: a, b planes, their box
+        // means right after them (the batched kernels' layout), then any
+        // area-subsampled planes
         d.coef = (float *)(ws_base + off);
-        off += round256(planes);
-        d.mean = (float *)(ws_base + off);
-        off += round256(planes);
-        if (area_pass(g)) off += round256(sizeof(float) * (size_t)g.lps * (1 + g.C));
+        d.mean = d.coef + (size_t)g.lps * 2 * g.C;
+        off += round256(workspace_bytes(g));
         for (int ph = 0; ph < 3; ++ph) {
             d.base[ph] = base[ph];
             base[ph] += d.ntiles[ph];
@@ -226,9 +227,8 @@ size_t gf_batched_workspace_bytes(int32_t n, const gf_image *I, const gf_image *
     size_t planes = 0;
     for (int i = 0; i < n; ++i) {
         if (I[i].h < 1 || I[i].w < 1 || p[i].c < 1 || pr[i].s < 1 || pr[i].r < 0) return 0;
-        const Geo g = make_geo(I[i].h, I[i].w, p[i].c, pr[i]);
-        planes += 2 * round256(sizeof(float) * (size_t)g.lps * 2 * g.C);
-        if (area_pass(g)) planes += round256(sizeof(float) * (size_t)g.lps * (1 + g.C));
+        if (I[i].c != 1 && I[i].c != 3) return 0;
+        planes += round256(workspace_bytes(make_geo(I[i].h, I[i].w, p[i].c, pr[i], I[i].c)));
     }
     return round256(sizeof(unsigned) * batch_ctl_words(n)) + round256(sizeof(BDesc) * n) + planes;
 }
@@ -257,8 +257,9 @@ gf_status gf_fast_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_im
     if ((uintptr_t)ws % 256) return fail(GF_EINVAL, "workspace not 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     if (plan.th == 0) {
-        // radius too large for the persistent kernel's staged tiles, or area
-        // subsampling: one gf_fast per image on the same stream (same results)
+        // radius too large for the persistent kernel's staged tiles, area
+        // subsampling or a colour guide: one gf_fast per image on the same
+        // stream (same results)
         for (int k = 0; k < n; ++k) {
             const BDesc &d = plan.desc[k];
             const int i = plan.order[k];

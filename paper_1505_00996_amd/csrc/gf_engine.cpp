@@ -122,7 +122,7 @@ class Engine {
         if ((st = plan_batch(1, I, p, q, pr, nullptr, ctx_batch_cfg(ctx_), &one)) != GF_OK) return st;
         if (one.th == 0)
             return fail(GF_ENOTSUP, "the request needs per-image launches (low-res radius above the batched "
-                                    "kernel's limit, or area subsampling)");
+                                    "kernel's limit, area subsampling or a colour guide)");
         if (one.ws_bytes > bytes_)
             return fail(GF_ENOMEM, "request needs %zu bytes of arena, the arena holds %zu", one.ws_bytes,
                         bytes_);

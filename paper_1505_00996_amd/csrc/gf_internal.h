@@ -10,8 +10,9 @@
 namespace gf {
 
 // Geometry of one filtering problem.  Full-res H x W, low-res Hl x Wl
-// (ceil(H/s) x ceil(W/s)), low-res radius R, C channels of p, subsampling
-// kind sub and border convention border (gf_subsample, gf_border).  The
+// (ceil(H/s) x ceil(W/s)), low-res radius R, G channels of the guide (1
+// gray, 3 colour), C channels of p, subsampling kind sub and border
+// convention border (gf_subsample, gf_border).  The
 // low-resolution FP32 maps live in a workspace as planes of Hl rows with
 // row stride lrs (a multiple of 16 floats) and plane stride lps (a multiple
 // of 64 floats), so every plane and row start is 64-byte aligned.
@@ -21,7 +22,7 @@ namespace gf {
 struct Geo {
     int H, W;
     int Hl, Wl;
-    int s, R, C, sub, border;
+    int s, R, G, C, sub, border;
     int refl_h, refl_w;
     float eps;
     int64_t lrs, lps;
@@ -46,7 +47,7 @@ constexpr int kOutPx = 4;       // full-res pixels per lane in the output kernel
 constexpr int kOutTileW = 64 * kOutPx;  // full-res columns per output tile
 constexpr int kMaxRadius = 64;  // largest low-res radius the LDS tile buffers hold
 
-Geo make_geo(int H, int W, int C, const gf_params &pr);
+Geo make_geo(int H, int W, int C, const gf_params &pr, int G = 1);
 // Area subsampling runs as a pass of its own (launch_area) into FP32 planes.
 inline bool area_pass(const Geo &g) { return g.sub == GF_SUB_AREA && g.s > 1; }
 constexpr size_t kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
@@ -76,9 +77,10 @@ hipError_t launch_coeff(gf_dtype dt, const View &I, const View &P, float *coef,
                         bool p_low = false);
 hipError_t launch_box(const float *src, float *dst, const Geo &g, const TileCfg &t,
                       hipStream_t st, const Stamp &ts = Stamp{});
-// Area subsampling of I (plane 0 of dst) and of the C channels of P (planes
-// 1..C; with p_low, P is already low-res and is converted as it is), FP32
-// planes of stride g.lps.  The coefficients then come from launch_coeff_lowres.
+// Area subsampling of the G channels of I (planes 0..G-1 of dst) and of the
+// C channels of P (planes G..G+C-1; with p_low, P is already low-res and is
+// converted as it is), FP32 planes of stride g.lps.  The coefficients then
+// come from launch_coeff_lowres (or its colour form).
 hipError_t launch_area(gf_dtype dt, const View &I, const View &P, bool p_low, float *dst, const Geo &g,
                        hipStream_t st, const Stamp &ts = Stamp{});
 // Coefficients from low-res FP32 planes: guide Il, channels of p at Pl + c*g.lps.
@@ -95,5 +97,19 @@ hipError_t launch_box_padded(const float *src, float *dst, const Geo &g, const T
 hipError_t launch_output(gf_dtype dt, const View &I, const View &Q, const float *mean,
                          const Geo &g, const TileCfg &t, bool vec, hipStream_t st,
                          const Stamp &ts = Stamp{}, const Detail &detail = Detail{});
+
+// Colour guide (gf_kernels_color.hip): coefficients a_0..a_2, b per channel
+// (4C planes at coef, layout in gf_color.h), from the images or from the
+// low-res FP32 planes of area subsampling (guide Il: 3 planes; p: Pl + c*lps);
+// output q from the box means of those 4C planes (vec: 4-wide row accesses).
+// color_tile_h: the coefficient tile height used for tiles t at radius R
+// (16 or 8; 0 when even 8 rows do not fit in LDS).
+int color_tile_h(const TileCfg &t, int R);
+hipError_t launch_coeff_color(gf_dtype dt, const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
+                              hipStream_t st, const Stamp &ts = Stamp{});
+hipError_t launch_coeff_color_lowres(const float *Il, const float *Pl, float *coef, const Geo &g, const TileCfg &t,
+                                     hipStream_t st, const Stamp &ts = Stamp{});
+hipError_t launch_output_color(gf_dtype dt, const View &I, const View &Q, const float *mean, const Geo &g, bool vec,
+                               hipStream_t st, const Stamp &ts = Stamp{});
 
 }  // namespace gf

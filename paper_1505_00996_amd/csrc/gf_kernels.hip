@@ -6,7 +6,7 @@
 //   k_output (grid: full-res 256 x 32 blocks)  steps 6-7 -> q
 // Algorithm 1 is the same three launches at s = 1, where subsampling and
 // upsampling are identities.  Area subsampling adds a first launch,
-//   k_area   (grid: low-res 64 x 4 blocks x (1+C) planes)  step 1 -> I', p'
+//   k_area   (grid: low-res 64 x 4 blocks x (G+C) planes)  step 1 -> I', p'
 // after which k_coeff reads the FP32 low-res planes as they are.  The
 // per-tile work lives in gf_device.h; the window-sum kernels and their
 // launchers in gf_window_kernels.h (this file instantiates the
@@ -40,27 +40,28 @@ __global__ __launch_bounds__(kThreads) void k_output(const T *__restrict__ I, in
 // Area subsampling (step 1 with the block mean): low-res pixel (ly, lx) of
 // plane k is the mean of the full-res block [s*ly, s*ly+s) x [s*lx, s*lx+s)
 // clipped to the image, summed in FP64 row by row and rounded once to FP32.
-// Plane 0 is the guide, planes 1..C the channels of p; with p_low those are
-// given at low resolution and are converted as they are.  A workgroup covers
+// Planes 0..G-1 are the guide's channels (1 gray, 3 colour), planes
+// G..G+C-1 the channels of p; with p_low those are given at low resolution
+// and are converted as they are.  A workgroup covers
 // 4 low-res rows (one per wave) x 64 columns (one per lane) of plane
 // blockIdx.y.  S: compile-time ratio for full blocks (0: g.s at run time);
 // with vec, every row of a full block is read with 2- or 4-wide loads (the
 // host checked that every row of I and p starts aligned for them).
 template <typename T, int S>
-__global__ __launch_bounds__(kThreads) void k_area(const T *__restrict__ I, int64_t Irs, const T *__restrict__ P,
-                                                   int64_t Prs, int64_t Pps, int p_low, float *__restrict__ dst,
-                                                   Geo g, int ntx, int vec) {
+__global__ __launch_bounds__(kThreads) void k_area(const T *__restrict__ I, int64_t Irs, int64_t Ips,
+                                                   const T *__restrict__ P, int64_t Prs, int64_t Pps, int p_low,
+                                                   float *__restrict__ dst, Geo g, int ntx, int vec) {
     const int lane = threadIdx.x & 63;
     const int ly = (blockIdx.x / ntx) * 4 + wave_id(), lx = (blockIdx.x % ntx) * 64 + lane;
     if (ly >= g.Hl || lx >= g.Wl) return;  // no barriers in this kernel
     const int k = blockIdx.y;
     float *out = dst + (int64_t)k * g.lps + (int64_t)ly * g.lrs + lx;
-    if (k > 0 && p_low) {
-        *out = ld(P + (int64_t)(k - 1) * Pps + (int64_t)ly * Prs + lx);
+    if (k >= g.G && p_low) {
+        *out = ld(P + (int64_t)(k - g.G) * Pps + (int64_t)ly * Prs + lx);
         return;
     }
-    const T *src = k == 0 ? I : P + (int64_t)(k - 1) * Pps;
-    const int64_t rs = k == 0 ? Irs : Prs;
+    const T *src = k < g.G ? I + (int64_t)k * Ips : P + (int64_t)(k - g.G) * Pps;
+    const int64_t rs = k < g.G ? Irs : Prs;
     const int s = S ? S : g.s, y0 = s * ly, x0 = s * lx;
     const int ny = min(s, g.H - y0), nx = min(s, g.W - x0);  // >= 1: s*ly < H, s*lx < W
     double acc = 0.0;
@@ -127,13 +128,13 @@ template <typename T>
 hipError_t area_t(const View &I, const View &P, bool p_low, float *dst, const Geo &g, hipStream_t st,
                   const Stamp &ts) {
     const int ntx = (g.Wl + 63) / 64, nty = (g.Hl + 3) / 4;
-    const dim3 grid(ntx * nty, 1 + g.C), block(kThreads);
+    const dim3 grid(ntx * nty, g.G + g.C), block(kThreads);
     const T *Ip = (const T *)I.data, *Pp = (const T *)P.data;
     const int n = g.s == 2 ? 2 : 4;  // load width of the S = 2, 4, 8 kernels
-    const int vec = rows_aligned<T>(I, n, false) && (p_low || rows_aligned<T>(P, n, g.C > 1));
+    const int vec = rows_aligned<T>(I, n, g.G > 1) && (p_low || rows_aligned<T>(P, n, g.C > 1));
 #define GF_AREA(SS)                                                                                  \
-    launch_k(k_area<T, SS>, grid, block, 0, st, ts.start, ts.stop, Ip, I.rs, Pp, P.rs, P.ps, (int)p_low, dst, g, \
-             ntx, vec)
+    launch_k(k_area<T, SS>, grid, block, 0, st, ts.start, ts.stop, Ip, I.rs, I.ps, Pp, P.rs, P.ps, (int)p_low, dst, \
+             g, ntx, vec)
     switch (g.s) {
         case 2: GF_AREA(2); break;
         case 4: GF_AREA(4); break;

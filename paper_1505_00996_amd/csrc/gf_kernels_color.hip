@@ -1,0 +1,134 @@
+// Per-image kernels of the guided filter with a colour (three-channel)
+// guide, and their host launchers:
+//   k_coeff_color  (grid: low-res tiles)            steps 1-4 -> a_0, a_1, a_2, b per channel
+//   k_box          (grid: low-res tiles x 4C maps)  step 5 (the gray path's box tiles)
+//   k_output_color (grid: full-res 256 x 16 blocks) steps 6-7 -> q
+// The tile code lives in gf_color.h.
+#include "gf_color.h"
+#include "gf_window_kernels.h"
+
+namespace gf {
+namespace {
+
+template <typename T, int K, int TH, int BD>
+__global__ __launch_bounds__(kThreads) void k_coeff_color(const T *__restrict__ I, int64_t Irs, int64_t Ips,
+                                                          const T *__restrict__ P, int64_t Prs, int64_t Pps,
+                                                          float *__restrict__ coef, Geo g, int ntx, int ntiles) {
+    extern __shared__ double lds_d[];
+    const int tile = xcd_tile(blockIdx.x);
+    if (tile >= ntiles) return;  // uniform per workgroup: no barrier is skipped by part of it
+    coeff_tile_color<T, K, TH, BD>(I, Irs, Ips, P, Prs, Pps, coef, g, (tile / ntx) * TH, (tile % ntx) * kTileW,
+                                   lds_d);
+}
+
+// One workgroup = 4 waves = a 256-column x 16-row block of q.
+template <typename T, int S>
+__global__ __launch_bounds__(kThreads) void k_output_color(const T *__restrict__ I, int64_t Irs, int64_t Ips,
+                                                           T *__restrict__ Q, int64_t Qrs, int64_t Qps,
+                                                           const float *__restrict__ M, Geo g, int ntx, int ntiles,
+                                                           int vec) {
+    const int tile = xcd_tile(blockIdx.x);
+    if (tile >= ntiles) return;
+    output_rows_color<T, S>(I, Irs, Ips, Q, Qrs, Qps, M, g,
+                            (tile / ntx) * (4 * kColorRows) + wave_id() * kColorRows, (tile % ntx) * 256,
+                            vec != 0);
+}
+
+template <typename T, int K, int BD>
+hipError_t coeff_color_tk(const View &I, const View &P, float *coef, const Geo &g, int th, hipStream_t st,
+                          const Stamp &ts) {
+    const T *Ip = (const T *)I.data, *Pp = (const T *)P.data;
+    const int ntx = (g.Wl + kTileW - 1) / kTileW, nty = (g.Hl + th - 1) / th;
+    const int ntiles = ntx * nty;
+    const size_t lds = color_tile_lds(th, g.R);
+    const dim3 grid(grid8(ntiles)), block(kThreads);
+#define GF_CC(TH)                                                                                           \
+    {                                                                                                        \
+        allow_lds(k_coeff_color<T, K, TH, BD>, lds);                                                         \
+        launch_k(k_coeff_color<T, K, TH, BD>, grid, block, lds, st, ts.start, ts.stop, Ip, I.rs, I.ps, Pp, P.rs, \
+                 P.ps, coef, g, ntx, ntiles);                                                                \
+    }
+    if (th == 16) GF_CC(16)
+    else GF_CC(8)
+#undef GF_CC
+    return hipGetLastError();
+}
+
+template <typename T, int K>
+hipError_t coeff_color_k(const View &I, const View &P, float *coef, const Geo &g, int th, hipStream_t st,
+                         const Stamp &ts) {
+    return g.border == GF_BORDER_CLIP ? coeff_color_tk<T, K, kClip>(I, P, coef, g, th, st, ts)
+                                      : coeff_color_tk<T, K, kPadded>(I, P, coef, g, th, st, ts);
+}
+
+template <typename T>
+hipError_t coeff_color_t(const View &I, const View &P, float *coef, const Geo &g, int th, hipStream_t st,
+                         const Stamp &ts) {
+    if (g.s == 1) return coeff_color_k<T, kSubId>(I, P, coef, g, th, st, ts);
+    if (g.sub == GF_SUB_AREA) return hipErrorInvalidValue;  // area: launch_area, then the low-res form
+    if (g.sub == GF_SUB_NEAREST || (g.s & 1)) return coeff_color_k<T, kSubNear>(I, P, coef, g, th, st, ts);
+    return coeff_color_k<T, kSubLin>(I, P, coef, g, th, st, ts);
+}
+
+template <typename T>
+hipError_t output_color_t(const View &I, const View &Q, const float *mean, const Geo &g, bool vec, hipStream_t st,
+                          const Stamp &ts) {
+    const int ntx = (g.W + 255) / 256, nty = (g.H + 4 * kColorRows - 1) / (4 * kColorRows);
+    const int ntiles = ntx * nty;
+    const T *Ip = (const T *)I.data;
+    T *Qp = (T *)Q.data;
+    const dim3 grid(grid8(ntiles)), block(kThreads);
+#define GF_OC(SS)                                                                                           \
+    launch_k(k_output_color<T, SS>, grid, block, 0, st, ts.start, ts.stop, Ip, I.rs, I.ps, Qp, Q.rs, Q.ps, mean, g, \
+             ntx, ntiles, (int)vec)
+    switch (g.s) {
+        case 1: GF_OC(1); break;
+        case 2: GF_OC(2); break;
+        case 4: GF_OC(4); break;
+        case 8: GF_OC(8); break;
+        default: GF_OC(0); break;
+    }
+#undef GF_OC
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// 8-row tiles (the 16-row form needs about 250 VGPRs, one wave per SIMD),
+// or 16 when pinned and they fit; 0 when none fits.
+int color_tile_h(const TileCfg &t, int R) {
+    if (t.coeff_th == 16 && dev::color_tile_lds(16, R) <= kLdsLimit) return 16;
+    return dev::color_tile_lds(8, R) <= kLdsLimit ? 8 : 0;
+}
+
+hipError_t launch_coeff_color(gf_dtype dt, const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
+                              hipStream_t st, const Stamp &ts) {
+    const int th = color_tile_h(t, g.R);
+    if (!th) return hipErrorInvalidValue;
+    switch (dt) {
+        case GF_F32: return coeff_color_t<float>(I, P, coef, g, th, st, ts);
+        case GF_F16: return coeff_color_t<_Float16>(I, P, coef, g, th, st, ts);
+        case GF_BF16: return coeff_color_t<dev::bf16>(I, P, coef, g, th, st, ts);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_coeff_color_lowres(const float *Il, const float *Pl, float *coef, const Geo &g, const TileCfg &t,
+                                     hipStream_t st, const Stamp &ts) {
+    const int th = color_tile_h(t, g.R);
+    if (!th) return hipErrorInvalidValue;
+    const View vI{(void *)Il, g.lrs, g.lps}, vP{(void *)Pl, g.lrs, g.lps};
+    return coeff_color_k<float, kSubId>(vI, vP, coef, g, th, st, ts);
+}
+
+hipError_t launch_output_color(gf_dtype dt, const View &I, const View &Q, const float *mean, const Geo &g, bool vec,
+                               hipStream_t st, const Stamp &ts) {
+    switch (dt) {
+        case GF_F32: return output_color_t<float>(I, Q, mean, g, vec, st, ts);
+        case GF_F16: return output_color_t<_Float16>(I, Q, mean, g, vec, st, ts);
+        case GF_BF16: return output_color_t<dev::bf16>(I, Q, mean, g, vec, st, ts);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace gf

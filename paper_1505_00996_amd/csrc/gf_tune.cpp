@@ -60,6 +60,7 @@ gf_status gf_tune(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q
     if (st != GF_OK) return st;
     if ((st = ctx_use_device(ctx)) != GF_OK) return st;
     if (reps < 1) reps = 1;
+    if (I->c != 1) return fail(GF_ENOTSUP, "gf_tune covers the gray-guide kernels");
     const Geo g = make_geo(I->h, I->w, p->c, *pr);
     if (!ws) {
         ws_bytes = workspace_bytes(g);

@@ -102,6 +102,22 @@ def colour_input(I: np.ndarray, c: int, seed: int, noise: float = 0.05) -> np.nd
     return out
 
 
+def colour_guide(h: int, w: int, seed: int, noise: float = 0.02) -> np.ndarray:
+    """Three-channel guide (3, h, w): a shared photo-like luminance G with,
+    per channel, gain in [0.7, 1.1], offset in [-0.1, 0.1], a smooth tint
+    field and N(0, noise^2), clipped to [0, 1]."""
+    g = _rng(seed)
+    G = photo_guide(h, w, seed + 1000, noise)
+    out = np.empty((3, h, w), dtype=np.float32)
+    for k in range(3):
+        gain = np.float32(g.uniform(0.7, 1.1))
+        off = np.float32(g.uniform(-0.1, 0.1))
+        ck = gain * G + off + _smooth_field(g, h, w, 3, 0.1)
+        ck += g.standard_normal(size=(h, w), dtype=np.float32) * np.float32(noise)
+        out[k] = np.clip(ck, 0.0, 1.0)
+    return out
+
+
 def flat_blocks_guide(h: int, w: int, seed: int, block: int = 500) -> np.ndarray:
     """Guide whose blocks are, with probability 1/2, near-constant in
     [0.49, 0.51] (0.5 + 0.01 * smooth field); the rest is photo content."""
@@ -128,6 +144,12 @@ def workload_12mp(h: int = 3000, w: int = 4000, c: int = 3, seed_I: int = 2, see
     """4000x3000 gray guide, RGB input; r=16, s=4 (and s=1), eps=1e-3."""
     I = photo_guide(h, w, seed_I)
     return I, colour_input(I, c, seed_p)
+
+
+def workload_12mp_colour(h: int = 3000, w: int = 4000, c: int = 3, seed_I: int = 6, seed_p: int = 7):
+    """4000x3000 RGB guide, RGB input (p from the guide's mean luminance)."""
+    I = colour_guide(h, w, seed_I)
+    return I, colour_input(I.mean(axis=0, dtype=np.float32), c, seed_p)
 
 
 def workload_24mp(h: int = 4000, w: int = 6000, c: int = 3, seed_I: int = 4, seed_p: int = 5):

@@ -58,7 +58,8 @@ def good():
     ("channel_mismatch", gfp.GF_EINVAL),
     ("dtype_mismatch", gfp.GF_EINVAL),
     ("bad_dtype", gfp.GF_EINVAL),
-    ("colour_guide", gfp.GF_ENOTSUP),
+    ("two_channel_guide", gfp.GF_ENOTSUP),
+    ("colour_guide_radius_too_large", gfp.GF_ENOTSUP),
     ("row_stride_short", gfp.GF_EINVAL),
     ("plane_stride_short", gfp.GF_EINVAL),
     ("q_aliases_p", gfp.GF_EINVAL),
@@ -96,8 +97,11 @@ def test_invalid_call_rejected_on_host(case, status):
         p = img(A_P, 3, 64, 80, gfp.GF_F16)
     elif case == "bad_dtype":
         I.dtype = 7
-    elif case == "colour_guide":
+    elif case == "two_channel_guide":
+        I = img(A_I, 2, 64, 80)
+    elif case == "colour_guide_radius_too_large":
         I = img(A_I, 3, 64, 80)
+        pr.r, pr.s = 120, 4  # r' = 30: the colour coefficient tiles do not fit in LDS
     elif case == "row_stride_short":
         p = img(A_P, 3, 64, 80, rs=79)
     elif case == "plane_stride_short":
@@ -162,6 +166,11 @@ def test_workspace_bytes():
     assert L.gf_workspace_bytes(3000, 4000, 3, ctypes.byref(prb)) == 4 * 3 * lps * 4
     pra1 = gfp.params(16, 1, 1e-3, "area")  # s = 1: the area mean of one pixel is that pixel, no pass
     assert L.gf_workspace_bytes(10, 10, 1, ctypes.byref(pra1)) == 4 * 1 * 192 * 4
+    # a colour guide: a_0, a_1, a_2, b and their box means (8C planes), plus 3 + C with area subsampling
+    assert L.gf_workspace_bytes_guide(3000, 4000, 3, 3, ctypes.byref(pr)) == 8 * 3 * lps * 4
+    assert L.gf_workspace_bytes_guide(3000, 4000, 3, 3, ctypes.byref(pra)) == (8 * 3 + 3 + 3) * lps * 4
+    assert L.gf_workspace_bytes_guide(3000, 4000, 1, 3, ctypes.byref(pr)) == L.gf_workspace_bytes(3000, 4000, 3, ctypes.byref(pr))
+    assert L.gf_workspace_bytes_guide(3000, 4000, 2, 3, ctypes.byref(pr)) == 0
 
 
 def test_prepared_batch_rejected_on_host():
