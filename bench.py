@@ -196,6 +196,63 @@ def measure_16bit(gfp, torch, dev, steps=50, with_oracle=True):
     return out
 
 
+def measure_colour(gfp, torch, dev, steps=50, with_oracle=True):
+    """Colour guide: 4000x3000 RGB guide, RGB input, fp32, r = 16, eps = 1e-3,
+    s = 4 (fast) and s = 1 (plain), four rotated input sets.  MPix/s,
+    per-kernel HIP event times, the output pass against its algorithmic bytes
+    (3 guide planes read, C planes written, 4C low-res maps read), and
+    max |q - oracle| of the fast filter."""
+    import numpy as np
+    import synth
+    h, w, c, r, s, eps = 3000, 4000, 3, 16, 4, 1e-3
+    I_np, p_np = synth.workload_12mp_colour(h, w, c)
+    sets = [(torch.from_numpy(I_np).to(dev), torch.from_numpy(p_np).to(dev),
+             torch.empty((c, h, w), dtype=torch.float32, device=dev)) for _ in range(4)]
+    out = {"workload": "4000x3000 RGB guide + RGB input, fp32, r=16, eps=1e-3, nearest; gf_fast (s=4) and "
+                       "gf_plain (s=1) per step", "h": h, "w": w, "channels": c}
+    for name, ss, n_steps in (("fast", s, steps), ("plain", 1, max(steps // 5, 5))):
+        ctx = gfp.Context(0)
+        ws = torch.empty(gfp.workspace_bytes(h, w, c, r, ss, eps, guide_c=3), dtype=torch.uint8, device=dev)
+
+        def step(i):
+            dI, dp, q = sets[i % len(sets)]
+            gfp.gf_fast(dI, dp, r, ss, eps, q=q, ctx=ctx, workspace=ws)
+        for i in range(3):
+            step(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n_steps):
+            step(i)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / n_steps
+        ctx.profile(True)
+        ctx.profile_read()
+        for i in range(n_steps):
+            step(i)
+        kt = ctx.profile_read()
+        ctx.profile(False)
+        hl, wl = lowres(h, ss), lowres(w, ss)
+        ob = h * w * 4 * (3 + c) + 4 * c * hl * wl * 4
+        out_ms = kt["output"][0] / max(kt["output"][1], 1)
+        res = {"value": round(h * w / 1e6 / (ms * 1e-3), 1), "unit": "MPix/s", "ms_per_step": round(ms, 5), "s": ss,
+               "kernels": {k: round(v[0] / v[1], 5) for k, v in kt.items() if v[1]},
+               "output_pass": {"achieved_GBs": round(ob / (out_ms * 1e-3) / 1e9, 1),
+                               "frac": round(ob / (out_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "algorithmic_bytes_per_launch": ob}}
+        if with_oracle and name == "fast":
+            from oracle import oracle
+            dI, dp, q = sets[0]
+            step(0)
+            torch.cuda.synchronize()
+            exp = oracle.fast_guided_filter_color(I_np.astype(np.float64), p_np.astype(np.float64), r, s, eps)
+            res["max_abs_err"] = float(np.max(np.abs(q.double().cpu().numpy() - exp)))
+        out[name] = res
+        ctx.close()
+    out["speedup_fast_vs_plain"] = round(out["plain"]["ms_per_step"] / out["fast"]["ms_per_step"], 3)
+    del sets
+    return out
+
+
 def measure_apps(gfp, torch, dev, I_np, p_np, steps=50, with_oracle=True):
     """The paper's applications and joint upsampling on the 4000x3000 workload
     (fp32, nearest, s = 4, four rotated input sets): MPix/s, per-kernel HIP
@@ -510,8 +567,11 @@ def main():
     kt_plain = ctx.profile_read()
     ctx.profile(False)
 
-    batched = served = sixteen = apps = None
+    batched = served = sixteen = apps = colour = None
     if not args.no_extra:
+        colour = measure_colour(gfp, torch, dev, with_oracle=not args.no_cpu)
+        print(f"# colour guide: fast {colour['fast']['value']} plain {colour['plain']['value']} MPix/s "
+              f"({colour['speedup_fast_vs_plain']}x)", file=sys.stderr, flush=True)
         apps = measure_apps(gfp, torch, dev, I_np, p_np, with_oracle=not args.no_cpu)
         print("# apps: " + ", ".join(f"{k} {v['value']}" for k, v in apps.items() if isinstance(v, dict)),
               file=sys.stderr, flush=True)
@@ -553,6 +613,7 @@ def main():
                   "ms_per_step": round(ms_plain, 5), "steps": plain_steps,
                   "kernels": {k: round(v[0] / v[1], 5) for k, v in kt_plain.items() if v[1]}},
         "storage_16bit": sixteen,
+        "colour_guide": colour,
         "applications": apps,
         "speedup_vs_plain": round(ms_plain / ms_fast, 3),
         "step_events": step_events,
