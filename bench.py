@@ -196,6 +196,48 @@ def measure_16bit(gfp, torch, dev, steps=50, with_oracle=True):
     return out
 
 
+def measure_small(gfp, torch, dev, calls=300, with_oracle=True):
+    """The 512x512 workload (gray guide and input, r = 8, s = 4, eps = 0.01):
+    a cache-resident image, so latency rather than bandwidth.  Per-call GPU
+    time from HIP events around each call (median, p99) and host time per
+    call for back-to-back calls."""
+    import numpy as np
+    import synth
+    I_np, p_np = synth.workload_small()
+    dI, dp = torch.from_numpy(I_np).to(dev), torch.from_numpy(p_np).to(dev)
+    q = torch.empty_like(dp)
+    ctx = gfp.Context(0)
+    ws = torch.empty(gfp.workspace_bytes(512, 512, 1, 8, 4, 0.01), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def call():
+        gfp.gf_fast(dI, dp, 8, 4, 0.01, q=q, ctx=ctx, workspace=ws)
+    for _ in range(20):
+        call()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        call()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    t = sorted(e0.elapsed_time(e1) * 1e3 for e0, e1 in evs)
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        call()
+    torch.cuda.synchronize()
+    host_us = (time.perf_counter() - t0) * 1e6 / calls
+    out = {"workload": "512x512 gray guide and input (rectangles + noise), r=8, s=4, eps=0.01, fp32, nearest",
+           "gpu_us_median": round(t[len(t) // 2], 2), "gpu_us_p99": round(t[int(0.99 * (len(t) - 1))], 2),
+           "us_per_call_back_to_back": round(host_us, 2), "calls": calls}
+    if with_oracle:
+        from oracle import oracle
+        exp = oracle.fast_guided_filter(I_np.astype(np.float64), p_np.astype(np.float64), 8, 4, 0.01)
+        out["max_abs_err"] = float(np.max(np.abs(q.double().cpu().numpy() - exp)))
+    ctx.close()
+    return out
+
+
 def measure_colour(gfp, torch, dev, steps=50, with_oracle=True):
     """Colour guide: 4000x3000 RGB guide, RGB input, fp32, r = 16, eps = 1e-3,
     s = 4 (fast) and s = 1 (plain), four rotated input sets.  MPix/s,
@@ -567,8 +609,11 @@ def main():
     kt_plain = ctx.profile_read()
     ctx.profile(False)
 
-    batched = served = sixteen = apps = colour = None
+    batched = served = sixteen = apps = colour = small = None
     if not args.no_extra:
+        small = measure_small(gfp, torch, dev, with_oracle=not args.no_cpu)
+        print(f"# 512x512: {small['gpu_us_median']} us per call (GPU), {small['us_per_call_back_to_back']} us "
+              f"back to back", file=sys.stderr, flush=True)
         colour = measure_colour(gfp, torch, dev, with_oracle=not args.no_cpu)
         print(f"# colour guide: fast {colour['fast']['value']} plain {colour['plain']['value']} MPix/s "
               f"({colour['speedup_fast_vs_plain']}x)", file=sys.stderr, flush=True)
@@ -613,6 +658,7 @@ def main():
                   "ms_per_step": round(ms_plain, 5), "steps": plain_steps,
                   "kernels": {k: round(v[0] / v[1], 5) for k, v in kt_plain.items() if v[1]}},
         "storage_16bit": sixteen,
+        "small_image": small,
         "colour_guide": colour,
         "applications": apps,
         "speedup_vs_plain": round(ms_plain / ms_fast, 3),
@@ -625,7 +671,8 @@ def main():
         "roofline": {"kernel": "k_output (bilinear upsample + q = mean_a*I + mean_b)",
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes_per_launch": out_bytes},
+                     "traffic": traffic, "algorithmic_bytes_per_launch": out_bytes,
+                     "frac_of_copy": round(achieved / ceilings["copy_torch_GBs"], 4)},
     }
 
     if not args.no_cpu:
