@@ -34,11 +34,11 @@
  * definition): per window q = a.I + b with a a 3-vector,
  * a = (Sigma + eps U)^-1 (mean(I p) - mean(I) mean(p)), b = mean(p) - a.mean(I),
  * Sigma the 3x3 population covariance of I in the window (sums in FP64, the
- * 3x3 solve in FP64), and q = mean_a.I + mean_b.  gf_plain, gf_fast and the
- * batched and prepared-batch calls take it (a batch holding one runs image
- * by image); gf_joint_upsample, gf_detail_enhance, gf_tune and gf_submit
- * refuse it (GF_ENOTSUP), as they do a low-res radius whose colour tiles do
- * not fit in LDS (above about 24).
+ * 3x3 solve in FP64), and q = mean_a.I + mean_b.  gf_plain, gf_fast,
+ * gf_joint_upsample, gf_detail_enhance and the batched and prepared-batch
+ * calls take it (a batch holding one runs image by image); gf_tune and
+ * gf_submit refuse it (GF_ENOTSUP), as every call does a low-res radius whose
+ * colour tiles do not fit in LDS (above about 24).
  *
  * Options for the conventions of other image libraries (gf_params):
  *   - GF_BORDER_REPLICATE / GF_BORDER_REFLECT101: every box mean (of the

@@ -597,6 +597,47 @@ done:
 }
 
 /*
+ * Joint upsampling with a colour guide: p_lo (c planes of ceil(h/s) x
+ * ceil(w/s)) is given at low resolution, only the three guide planes are
+ * subsampled, and the colour filter's remaining steps run as in
+ * oracle_fast_guided_filter_color.
+ */
+int oracle_joint_upsample_color(const double *I, const double *p_lo, int c, int h, int w, int r, int s,
+                                double eps, int mode, int border, double *q)
+{
+    if (h <= 0 || w <= 0 || c <= 0 || r < 0 || s < 1 || !(eps > 0.0)) return -1;
+    if (mode != ORACLE_NEAREST && mode != ORACLE_BILINEAR && mode != ORACLE_AREA) return -1;
+    int hl = oracle_lowres_size(h, s), wl = oracle_lowres_size(w, s);
+    int rl = oracle_lowres_radius(r, s);
+    size_t n = (size_t)h * (size_t)w, nl = (size_t)hl * (size_t)wl;
+    double *Il = (double *)malloc(sizeof(double) * 3 * nl);
+    double *ca = (double *)malloc(sizeof(double) * 3 * nl);
+    double *cb = (double *)malloc(sizeof(double) * nl);
+    double *mean_lo = (double *)malloc(sizeof(double) * nl);
+    double *up = (double *)malloc(sizeof(double) * n);
+    int rc = 0;
+    if (!Il || !ca || !cb || !mean_lo || !up) { rc = -2; goto done; }
+    for (int j = 0; j < 3; ++j)
+        if ((rc = oracle_subsample(I + (size_t)j * n, h, w, s, mode, Il + (size_t)j * nl))) goto done;
+    for (int k = 0; k < c; ++k) {
+        double *qk = q + (size_t)k * n;
+        if ((rc = coefficients_color(Il, p_lo + (size_t)k * nl, hl, wl, rl, eps, border, ca, cb))) goto done;
+        for (size_t i = 0; i < n; ++i) qk[i] = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            if ((rc = oracle_box_mean_border(ca + (size_t)j * nl, hl, wl, rl, border, mean_lo))) goto done;
+            if ((rc = oracle_upsample(mean_lo, hl, wl, s, h, w, up))) goto done;
+            for (size_t i = 0; i < n; ++i) qk[i] += up[i] * I[(size_t)j * n + i];
+        }
+        if ((rc = oracle_box_mean_border(cb, hl, wl, rl, border, mean_lo))) goto done;
+        if ((rc = oracle_upsample(mean_lo, hl, wl, s, h, w, up))) goto done;
+        for (size_t i = 0; i < n; ++i) qk[i] += up[i];
+    }
+done:
+    free(Il); free(ca); free(cb); free(mean_lo); free(up);
+    return rc;
+}
+
+/*
  * Detail enhancement, the paper's first application: the filtered image q is
  * the base layer, p - q the detail layer, and the enhanced image carries the
  * detail `gain` times over (its example shows x5 detail):

@@ -79,6 +79,7 @@ class Oracle:
             "oracle_joint_upsample_ex": [_DP, _DP, i, i, i, i, i, d, i, i, _DP],
             "oracle_detail_enhance": [_DP, _DP, ctypes.c_size_t, d, _DP],
             "oracle_fast_guided_filter_color": [_DP, _DP, i, i, i, i, i, d, i, i, _DP, _DP, _DP],
+            "oracle_joint_upsample_color": [_DP, _DP, i, i, i, i, i, d, i, i, _DP],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -238,6 +239,24 @@ class Oracle:
                 a, b = a[0], b[0]
         return (q, {"a": a, "b": b}) if intermediates else q
 
+    def joint_upsample_color(self, I, p_lo, r: int, s: int, eps: float, mode="nearest", border="clip"):
+        """Joint upsampling with a colour guide ``I`` (3, h, w); ``p_lo`` (c,
+        ceil(h/s), ceil(w/s)) or 2-D.  Returns q at full resolution."""
+        I = np.ascontiguousarray(_f64(I))
+        assert I.ndim == 3 and I.shape[0] == 3, I.shape
+        h, w = I.shape[1:]
+        hl, wl = self.lowres_size(h, s), self.lowres_size(w, s)
+        p_lo = _f64(p_lo)
+        squeeze = p_lo.ndim == 2
+        p3 = np.ascontiguousarray(p_lo.reshape(1, hl, wl)) if squeeze else p_lo
+        assert p3.shape[1:] == (hl, wl), (p3.shape, hl, wl)
+        c = p3.shape[0]
+        q = np.empty((c, h, w))
+        _check(self.lib.oracle_joint_upsample_color(_ptr(I), _ptr(p3), c, h, w, int(r), int(s), float(eps),
+                                                    _MODES[mode], _BORDERS[border], _ptr(q)),
+               "oracle_joint_upsample_color")
+        return q[0] if squeeze else q
+
     def detail_enhance(self, p, q, gain: float):
         """e = q + gain (p - q), elementwise (p and q of one shape)."""
         p, q = _f64(p), _f64(q)
@@ -303,6 +322,10 @@ def detail_enhance(p, q, gain):
 
 def fast_guided_filter_color(I, p, r, s, eps, mode="nearest", border="clip", intermediates=False):
     return default().fast_guided_filter_color(I, p, r, s, eps, mode, border, intermediates)
+
+
+def joint_upsample_color(I, p_lo, r, s, eps, mode="nearest", border="clip"):
+    return default().joint_upsample_color(I, p_lo, r, s, eps, mode, border)
 
 
 def guided_filter_color(I, p, r, eps, border="clip"):

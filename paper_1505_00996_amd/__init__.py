@@ -253,7 +253,7 @@ def gf_joint_upsample(I, p_low, r: int, s: int, eps: float, sub: str = "nearest"
     pr = params(r, s, eps, sub, border)
     c = 1 if p_low.dim() == 2 else p_low.shape[0]
     if workspace is None:
-        workspace = _workspace(int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(pr))), I.device)
+        workspace = _workspace(int(lib().gf_workspace_bytes_guide(h, w, _guide_c(I), c, ctypes.byref(pr))), I.device)
     _check(lib().gf_joint_upsample(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p_low)),
                                    ctypes.byref(image(q)), ctypes.byref(pr), ctypes.c_void_p(workspace.data_ptr()),
                                    workspace.numel() * workspace.element_size(), _stream(stream)), ctx)
@@ -269,7 +269,7 @@ def gf_detail_enhance(I, p, r: int, s: int, eps: float, gain: float, sub: str = 
     h, w = I.shape[-2:]
     c = 1 if p.dim() == 2 else p.shape[0]
     if workspace is None:
-        workspace = _workspace(int(lib().gf_workspace_bytes(h, w, c, ctypes.byref(pr))), p.device)
+        workspace = _workspace(int(lib().gf_workspace_bytes_guide(h, w, _guide_c(I), c, ctypes.byref(pr))), p.device)
     _check(lib().gf_detail_enhance(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p)),
                                    ctypes.byref(image(e)), ctypes.byref(pr), float(gain),
                                    ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),

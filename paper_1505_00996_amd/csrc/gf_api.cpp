@@ -181,7 +181,6 @@ gf_status validate(const gf_image *I, const gf_image *p, const gf_image *q,
     if (lowres_radius(pr->r, pr->s) > kMaxRadius)
         return fail(GF_ENOTSUP, "low-res radius %d above %d", lowres_radius(pr->r, pr->s), kMaxRadius);
     if (I->c == 3) {
-        if (p_low) return fail(GF_ENOTSUP, "joint upsampling with a colour guide is not supported");
         if (!color_tile_h(TileCfg{8, 8}, lowres_radius(pr->r, pr->s)))
             return fail(GF_ENOTSUP, "colour guide: low-res radius %d too large for the LDS tiles",
                         lowres_radius(pr->r, pr->s));
@@ -232,7 +231,7 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
         const float *pl = lowres + (size_t)g.G * g.lps;
         if (color)
             e = area_pass(g) ? launch_coeff_color_lowres(lowres, pl, coef, g, t, st, ps.stamp())
-                             : launch_coeff_color(I->dtype, vI, vP, coef, g, t, st, ps.stamp());
+                             : launch_coeff_color(I->dtype, vI, vP, coef, g, t, st, ps.stamp(), p_low);
         else
             e = area_pass(g) ? launch_coeff_lowres(lowres, pl, coef, g, t, st, ps.stamp())
                              : launch_coeff(I->dtype, vI, vP, coef, g, t, st, ps.stamp(), p_low);
@@ -249,7 +248,13 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
     if (e == hipSuccess && color) {
         ProfScope ps(ctx, GF_K_OUTPUT, st, true);
         const size_t es = I->dtype == GF_F32 ? 4 : 2;
-        e = launch_output_color(I->dtype, vI, vQ, mean, g, vector_ok(I, q, 4 * es), st, ps.stamp());
+        Detail dt;
+        if (gain) {
+            dt.p = vP;
+            dt.gain = *gain;
+        }
+        e = launch_output_color(I->dtype, vI, vQ, mean, g, vector_ok(I, q, 4 * es) && (!gain || vector_ok(p, p, 4 * es)),
+                                st, ps.stamp(), dt);
         ps.commit(e == hipSuccess);
     } else if (e == hipSuccess) {
         ProfScope ps(ctx, GF_K_OUTPUT, st, true);
@@ -337,7 +342,6 @@ gf_status gf_detail_enhance(gf_ctx *ctx, const gf_image *I, const gf_image *p, g
                             const gf_params *pr, double gain, void *ws, size_t ws_bytes, void *stream) {
     const float g = (float)gain;
     if (!isfinite(gain) || !isfinite(g)) return fail(GF_EINVAL, "gain = %g must be finite (in FP32)", gain);
-    if (I && I->c == 3) return fail(GF_ENOTSUP, "detail enhancement with a colour guide is not supported");
     return fast_entry(ctx, I, p, e, pr, ws, ws_bytes, stream, false, &g);
 }
 

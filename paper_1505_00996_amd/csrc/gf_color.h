@@ -47,7 +47,9 @@ __device__ __forceinline__ void solve3_sym(double m00, double m01, double m02, d
 // S_v and S_jv (channel 0's S_1v rides in the fifth).  Then per pixel, with n the window's sample count,
 // n^2 Sigma_jk = n S_jk - S_j S_k and n^2 cov_j = n S_jv - S_j S_v, and
 // a = (n^2 Sigma + n^2 eps U)^-1 (n^2 cov), solved in FP64.
-template <typename T, int K, int TH, int BD>
+// KP: how p is sampled -- like I, or kSubId when p is given at low
+// resolution (joint upsampling).
+template <typename T, int K, int TH, int BD, int KP = K>
 __device__ __forceinline__ void coeff_tile_color(const T *__restrict__ I, int64_t Irs, int64_t Ips,
                                                  const T *__restrict__ P, int64_t Prs, int64_t Pps,
                                                  float *__restrict__ coef, const Geo &g, int ty0, int tx0,
@@ -63,27 +65,30 @@ __device__ __forceinline__ void coeff_tile_color(const T *__restrict__ I, int64_
     // the shifted sample of an image at region position (ry, rx); outside
     // the map 0 (kClip, a product rather than a select: see coeff_tile) or
     // the border extension's sample (kPadded)
-    auto gsample = [&](const T *img, int64_t rs, float c, int ry, int rx) -> float {
+    auto gsample = [&](auto kind, const T *img, int64_t rs, float c, int ry, int rx) -> float {
+        constexpr int KK = decltype(kind)::value;
         const int ly = oy + ry, lx = ox + rx;
         if constexpr (BD == kClip) {
             const bool in = ly >= 0 && ly < g.Hl && lx >= 0 && lx < g.Wl;
-            const float v = sample_rc<K>(img, rs, taps<K>(clampi(ly, 0, g.Hl - 1), g.s, g.H),
-                                         taps<K>(clampi(lx, 0, g.Wl - 1), g.s, g.W));
+            const float v = sample_rc<KK>(img, rs, taps<KK>(clampi(ly, 0, g.Hl - 1), g.s, g.H),
+                                          taps<KK>(clampi(lx, 0, g.Wl - 1), g.s, g.W));
             return (v - c) * (in ? 1.f : 0.f);
         } else {
-            const float v = sample_rc<K>(img, rs, taps<K>(pad_index(ly, g.Hl, g.border, g.refl_h), g.s, g.H),
-                                         taps<K>(pad_index(lx, g.Wl, g.border, g.refl_w), g.s, g.W));
+            const float v = sample_rc<KK>(img, rs, taps<KK>(pad_index(ly, g.Hl, g.border, g.refl_h), g.s, g.H),
+                                          taps<KK>(pad_index(lx, g.Wl, g.border, g.refl_w), g.s, g.W));
             return v - c;
         }
     };
+    using KI = std::integral_constant<int, K>;
+    using KQ = std::integral_constant<int, KP>;
     const T *I0 = I, *I1 = I + Ips, *I2 = I + 2 * Ips;
     const float c0 = sample<K>(I0, Irs, ty0, tx0, g), c1 = sample<K>(I1, Irs, ty0, tx0, g),
                 c2 = sample<K>(I2, Irs, ty0, tx0, g);
-    fill_tile2(sU0, sU1, SH, SW, SWp, [&](int ry, int rx) { return gsample(I0, Irs, c0, ry, rx); },
-               [&](int ry, int rx) { return gsample(I1, Irs, c1, ry, rx); });
-    float cP = sample<K>(P, Prs, ty0, tx0, g);
-    fill_tile2(sU2, sV, SH, SW, SWp, [&](int ry, int rx) { return gsample(I2, Irs, c2, ry, rx); },
-               [&](int ry, int rx) { return gsample(P, Prs, cP, ry, rx); });
+    fill_tile2(sU0, sU1, SH, SW, SWp, [&](int ry, int rx) { return gsample(KI{}, I0, Irs, c0, ry, rx); },
+               [&](int ry, int rx) { return gsample(KI{}, I1, Irs, c1, ry, rx); });
+    float cP = sample<KP>(P, Prs, ty0, tx0, g);
+    fill_tile2(sU2, sV, SH, SW, SWp, [&](int ry, int rx) { return gsample(KI{}, I2, Irs, c2, ry, rx); },
+               [&](int ry, int rx) { return gsample(KQ{}, P, Prs, cP, ry, rx); });
     lds_sync();
 
     // Row pass: rA = sum X*Y and rB = sum X*Z over each window of a run of
@@ -173,8 +178,8 @@ __device__ __forceinline__ void coeff_tile_color(const T *__restrict__ I, int64_
         if (c) {
             // sV is free: the last row pass that read it ended at a barrier
             const T *Pc = P + (int64_t)c * Pps;
-            cP = sample<K>(Pc, Prs, ty0, tx0, g);
-            fill_tile(sV, SH, SW, SWp, [&](int ry, int rx) { return gsample(Pc, Prs, cP, ry, rx); });
+            cP = sample<KP>(Pc, Prs, ty0, tx0, g);
+            fill_tile(sV, SH, SW, SWp, [&](int ry, int rx) { return gsample(KQ{}, Pc, Prs, cP, ry, rx); });
             lds_sync();
             pass(one{}, sV, nullptr, sU0, Sv, S0v);
             pass(prod{}, sV, sU1, sU2, S1v, S2v);
@@ -220,13 +225,16 @@ __device__ __forceinline__ void coeff_tile_color(const T *__restrict__ I, int64_
 // from the low-res maps M (layout above).  S: compile-time ratio (0: g.s at
 // run time).  The lane first loads its 3 x 4 x 4 guide values; then per
 // channel the low-res values its pixels interpolate from, and per row the
-// bilinear weights and the stores.
+// bilinear weights and the stores.  EPI (detail enhancement): with P the
+// input p (layout of Q), each output is e = q + gain (p - q), formed from the
+// FP32 q before the store's rounding.
 constexpr int kColorRows = 4;
-template <typename T, int S>
+template <typename T, int S, bool EPI = false>
 __device__ __forceinline__ void output_rows_color(const T *__restrict__ I, int64_t Irs, int64_t Ips,
                                                   T *__restrict__ Q, int64_t Qrs, int64_t Qps,
                                                   const float *__restrict__ M, const Geo &g, int yb, int xw,
-                                                  bool vec) {
+                                                  bool vec, const T *__restrict__ P = nullptr, int64_t Prs = 0,
+                                                  int64_t Pps = 0, float gain = 0.f) {
     constexpr int ROWS = kColorRows, PX = 4;
     const int lane = threadIdx.x & 63;
     const int x0 = xw + lane * PX;
@@ -248,7 +256,7 @@ __device__ __forceinline__ void output_rows_color(const T *__restrict__ I, int64
             }
         }
     }
-    auto store_q = [&](T *plane, int y, const float *v) {
+    auto store_q0 = [&](T *plane, int y, const float *v) {
         T *base = plane + (int64_t)y * Qrs, *row = base + x0;
         if (full) {
             stv<PX>(row, v);
@@ -260,6 +268,17 @@ __device__ __forceinline__ void output_rows_color(const T *__restrict__ I, int64
             for (int j = 0; j < PX; ++j)
                 if (x0 + j < g.W) st1(row + j, v[j]);
         }
+    };
+    // with EPI, e = q + gain (p - q) from channel c's row of p, then the store
+    auto store_q = [&](int c, int y, float *v) {
+        if constexpr (EPI) {
+            const T *base = P + (int64_t)c * Pps + (int64_t)y * Prs;
+            Row pr;
+            ld_row<T, PX>(pr, base + x0, full, inpx && pair_aligned(base), g.W - x0);
+#pragma unroll
+            for (int j = 0; j < PX; ++j) v[j] = lerp(v[j], pr.at(j), gain);
+        }
+        store_q0(Q + (int64_t)c * Qps, y, v);
     };
     // q = ((mean_b + a_0 I_0) + a_1 I_1) + a_2 I_2, one rounding per term
     auto combine = [&](const float *a, float b, int i, int j) -> float {
@@ -273,7 +292,6 @@ __device__ __forceinline__ void output_rows_color(const T *__restrict__ I, int64
 #pragma unroll 1
         for (int c = 0; c < g.C; ++c) {
             const float *Ma = M + (int64_t)(3 * c) * g.lps, *Mb = M + (int64_t)(3 * g.C + c) * g.lps;
-            T *Qc = Q + (int64_t)c * Qps;
 #pragma unroll
             for (int i = 0; i < ROWS; ++i) {
                 if (i < nrows) {
@@ -286,7 +304,7 @@ __device__ __forceinline__ void output_rows_color(const T *__restrict__ I, int64
                         const float a[3] = {a0[j], a1[j], a2[j]};
                         out[j] = combine(a, b[j], i, j);
                     }
-                    store_q(Qc, yb + i, out);
+                    store_q(c, yb + i, out);
                 }
             }
         }
@@ -312,7 +330,6 @@ __device__ __forceinline__ void output_rows_color(const T *__restrict__ I, int64
             wy[i] = PHASE ? (float)((2 * ((yb & 7) + i) + 1 - 8) & 15) * (1.0f / 16.0f) : cfrac_u(i, S);
 #pragma unroll 1
         for (int c = 0; c < g.C; ++c) {
-            T *Qc = Q + (int64_t)c * Qps;
             // low-res values of the four maps (a_0, a_1, a_2, b) under the block
             float v[4][NL][NC];
 #pragma unroll
@@ -341,7 +358,7 @@ __device__ __forceinline__ void output_rows_color(const T *__restrict__ I, int64
                         }
                         out[j] = combine(u, u[3], i, j);
                     }
-                    store_q(Qc, yb + i, out);
+                    store_q(c, yb + i, out);
                 }
             }
         }
@@ -361,7 +378,6 @@ __device__ __forceinline__ void output_rows_color(const T *__restrict__ I, int64
         }
 #pragma unroll 1
         for (int c = 0; c < g.C; ++c) {
-            T *Qc = Q + (int64_t)c * Qps;
 #pragma unroll
             for (int i = 0; i < ROWS; ++i) {
                 if (i < nrows) {
@@ -383,7 +399,7 @@ __device__ __forceinline__ void output_rows_color(const T *__restrict__ I, int64
                         }
                         out[j] = combine(u, u[3], i, j);
                     }
-                    store_q(Qc, y, out);
+                    store_q(c, y, out);
                 }
             }
         }

@@ -8,7 +8,7 @@
 //                 (step 2); var, cov (step 3) and a, b of Eqs. 2-3 (step 4).
 //   box_tile    : box mean of one coefficient map (step 5), clip-normalised
 //                 or over the map padded by replication / reflect-101.
-//   output_tile : bilinear upsampling of mean_a, mean_b fused with
+//   output_rows : bilinear upsampling of mean_a, mean_b fused with
 //                 q = mean_a * I + mean_b against the full-resolution I
 //                 (steps 6-7); the HBM-bound pass.
 //

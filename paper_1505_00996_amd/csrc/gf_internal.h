@@ -100,16 +100,18 @@ hipError_t launch_output(gf_dtype dt, const View &I, const View &Q, const float 
 
 // Colour guide (gf_kernels_color.hip): coefficients a_0..a_2, b per channel
 // (4C planes at coef, layout in gf_color.h), from the images or from the
-// low-res FP32 planes of area subsampling (guide Il: 3 planes; p: Pl + c*lps);
-// output q from the box means of those 4C planes (vec: 4-wide row accesses).
+// low-res FP32 planes of area subsampling (guide Il: 3 planes; p: Pl + c*lps;
+// p_low: p given at low resolution, joint upsampling); output q (or, with a
+// detail epilogue, e) from the box means of those 4C planes (vec: 4-wide
+// row accesses).
 // color_tile_h: the coefficient tile height used for tiles t at radius R
 // (16 or 8; 0 when even 8 rows do not fit in LDS).
 int color_tile_h(const TileCfg &t, int R);
 hipError_t launch_coeff_color(gf_dtype dt, const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
-                              hipStream_t st, const Stamp &ts = Stamp{});
+                              hipStream_t st, const Stamp &ts = Stamp{}, bool p_low = false);
 hipError_t launch_coeff_color_lowres(const float *Il, const float *Pl, float *coef, const Geo &g, const TileCfg &t,
                                      hipStream_t st, const Stamp &ts = Stamp{});
 hipError_t launch_output_color(gf_dtype dt, const View &I, const View &Q, const float *mean, const Geo &g, bool vec,
-                               hipStream_t st, const Stamp &ts = Stamp{});
+                               hipStream_t st, const Stamp &ts = Stamp{}, const Detail &detail = Detail{});
 
 }  // namespace gf

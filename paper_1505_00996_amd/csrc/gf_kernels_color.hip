@@ -10,31 +10,33 @@
 namespace gf {
 namespace {
 
-template <typename T, int K, int TH, int BD>
+template <typename T, int K, int KP, int TH, int BD>
 __global__ __launch_bounds__(kThreads) void k_coeff_color(const T *__restrict__ I, int64_t Irs, int64_t Ips,
                                                           const T *__restrict__ P, int64_t Prs, int64_t Pps,
                                                           float *__restrict__ coef, Geo g, int ntx, int ntiles) {
     extern __shared__ double lds_d[];
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;  // uniform per workgroup: no barrier is skipped by part of it
-    coeff_tile_color<T, K, TH, BD>(I, Irs, Ips, P, Prs, Pps, coef, g, (tile / ntx) * TH, (tile % ntx) * kTileW,
-                                   lds_d);
+    coeff_tile_color<T, K, TH, BD, KP>(I, Irs, Ips, P, Prs, Pps, coef, g, (tile / ntx) * TH,
+                                       (tile % ntx) * kTileW, lds_d);
 }
 
-// One workgroup = 4 waves = a 256-column x 16-row block of q.
-template <typename T, int S>
+// One workgroup = 4 waves = a 256-column x 16-row block of q (EPI: of the
+// detail-enhanced e, reading the matching block of p).
+template <typename T, int S, bool EPI>
 __global__ __launch_bounds__(kThreads) void k_output_color(const T *__restrict__ I, int64_t Irs, int64_t Ips,
                                                            T *__restrict__ Q, int64_t Qrs, int64_t Qps,
                                                            const float *__restrict__ M, Geo g, int ntx, int ntiles,
-                                                           int vec) {
+                                                           int vec, const T *__restrict__ P, int64_t Prs,
+                                                           int64_t Pps, float gain) {
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;
-    output_rows_color<T, S>(I, Irs, Ips, Q, Qrs, Qps, M, g,
-                            (tile / ntx) * (4 * kColorRows) + wave_id() * kColorRows, (tile % ntx) * 256,
-                            vec != 0);
+    output_rows_color<T, S, EPI>(I, Irs, Ips, Q, Qrs, Qps, M, g,
+                                 (tile / ntx) * (4 * kColorRows) + wave_id() * kColorRows, (tile % ntx) * 256,
+                                 vec != 0, P, Prs, Pps, gain);
 }
 
-template <typename T, int K, int BD>
+template <typename T, int K, int KP, int BD>
 hipError_t coeff_color_tk(const View &I, const View &P, float *coef, const Geo &g, int th, hipStream_t st,
                           const Stamp &ts) {
     const T *Ip = (const T *)I.data, *Pp = (const T *)P.data;
@@ -44,9 +46,9 @@ hipError_t coeff_color_tk(const View &I, const View &P, float *coef, const Geo &
     const dim3 grid(grid8(ntiles)), block(kThreads);
 #define GF_CC(TH)                                                                                           \
     {                                                                                                        \
-        allow_lds(k_coeff_color<T, K, TH, BD>, lds);                                                         \
-        launch_k(k_coeff_color<T, K, TH, BD>, grid, block, lds, st, ts.start, ts.stop, Ip, I.rs, I.ps, Pp, P.rs, \
-                 P.ps, coef, g, ntx, ntiles);                                                                \
+        allow_lds(k_coeff_color<T, K, KP, TH, BD>, lds);                                                     \
+        launch_k(k_coeff_color<T, K, KP, TH, BD>, grid, block, lds, st, ts.start, ts.stop, Ip, I.rs, I.ps, Pp,  \
+                 P.rs, P.ps, coef, g, ntx, ntiles);                                                          \
     }
     if (th == 16) GF_CC(16)
     else GF_CC(8)
@@ -54,33 +56,37 @@ hipError_t coeff_color_tk(const View &I, const View &P, float *coef, const Geo &
     return hipGetLastError();
 }
 
-template <typename T, int K>
+template <typename T, int K, int KP>
 hipError_t coeff_color_k(const View &I, const View &P, float *coef, const Geo &g, int th, hipStream_t st,
                          const Stamp &ts) {
-    return g.border == GF_BORDER_CLIP ? coeff_color_tk<T, K, kClip>(I, P, coef, g, th, st, ts)
-                                      : coeff_color_tk<T, K, kPadded>(I, P, coef, g, th, st, ts);
+    return g.border == GF_BORDER_CLIP ? coeff_color_tk<T, K, KP, kClip>(I, P, coef, g, th, st, ts)
+                                      : coeff_color_tk<T, K, KP, kPadded>(I, P, coef, g, th, st, ts);
 }
 
 template <typename T>
 hipError_t coeff_color_t(const View &I, const View &P, float *coef, const Geo &g, int th, hipStream_t st,
-                         const Stamp &ts) {
-    if (g.s == 1) return coeff_color_k<T, kSubId>(I, P, coef, g, th, st, ts);
+                         const Stamp &ts, bool p_low) {
+    if (g.s == 1) return coeff_color_k<T, kSubId, kSubId>(I, P, coef, g, th, st, ts);
     if (g.sub == GF_SUB_AREA) return hipErrorInvalidValue;  // area: launch_area, then the low-res form
-    if (g.sub == GF_SUB_NEAREST || (g.s & 1)) return coeff_color_k<T, kSubNear>(I, P, coef, g, th, st, ts);
-    return coeff_color_k<T, kSubLin>(I, P, coef, g, th, st, ts);
+    if (g.sub == GF_SUB_NEAREST || (g.s & 1))
+        return p_low ? coeff_color_k<T, kSubNear, kSubId>(I, P, coef, g, th, st, ts)
+                     : coeff_color_k<T, kSubNear, kSubNear>(I, P, coef, g, th, st, ts);
+    return p_low ? coeff_color_k<T, kSubLin, kSubId>(I, P, coef, g, th, st, ts)
+                 : coeff_color_k<T, kSubLin, kSubLin>(I, P, coef, g, th, st, ts);
 }
 
-template <typename T>
+template <typename T, bool EPI>
 hipError_t output_color_t(const View &I, const View &Q, const float *mean, const Geo &g, bool vec, hipStream_t st,
-                          const Stamp &ts) {
+                          const Stamp &ts, const Detail &dt) {
     const int ntx = (g.W + 255) / 256, nty = (g.H + 4 * kColorRows - 1) / (4 * kColorRows);
     const int ntiles = ntx * nty;
     const T *Ip = (const T *)I.data;
     T *Qp = (T *)Q.data;
     const dim3 grid(grid8(ntiles)), block(kThreads);
-#define GF_OC(SS)                                                                                           \
-    launch_k(k_output_color<T, SS>, grid, block, 0, st, ts.start, ts.stop, Ip, I.rs, I.ps, Qp, Q.rs, Q.ps, mean, g, \
-             ntx, ntiles, (int)vec)
+    const T *Pp = (const T *)dt.p.data;
+#define GF_OC(SS)                                                                                             \
+    launch_k(k_output_color<T, SS, EPI>, grid, block, 0, st, ts.start, ts.stop, Ip, I.rs, I.ps, Qp, Q.rs, Q.ps, mean, \
+             g, ntx, ntiles, (int)vec, Pp, dt.p.rs, dt.p.ps, dt.gain)
     switch (g.s) {
         case 1: GF_OC(1); break;
         case 2: GF_OC(2); break;
@@ -102,13 +108,13 @@ int color_tile_h(const TileCfg &t, int R) {
 }
 
 hipError_t launch_coeff_color(gf_dtype dt, const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
-                              hipStream_t st, const Stamp &ts) {
+                              hipStream_t st, const Stamp &ts, bool p_low) {
     const int th = color_tile_h(t, g.R);
     if (!th) return hipErrorInvalidValue;
     switch (dt) {
-        case GF_F32: return coeff_color_t<float>(I, P, coef, g, th, st, ts);
-        case GF_F16: return coeff_color_t<_Float16>(I, P, coef, g, th, st, ts);
-        case GF_BF16: return coeff_color_t<dev::bf16>(I, P, coef, g, th, st, ts);
+        case GF_F32: return coeff_color_t<float>(I, P, coef, g, th, st, ts, p_low);
+        case GF_F16: return coeff_color_t<_Float16>(I, P, coef, g, th, st, ts, p_low);
+        case GF_BF16: return coeff_color_t<dev::bf16>(I, P, coef, g, th, st, ts, p_low);
     }
     return hipErrorInvalidValue;
 }
@@ -118,15 +124,22 @@ hipError_t launch_coeff_color_lowres(const float *Il, const float *Pl, float *co
     const int th = color_tile_h(t, g.R);
     if (!th) return hipErrorInvalidValue;
     const View vI{(void *)Il, g.lrs, g.lps}, vP{(void *)Pl, g.lrs, g.lps};
-    return coeff_color_k<float, kSubId>(vI, vP, coef, g, th, st, ts);
+    return coeff_color_k<float, kSubId, kSubId>(vI, vP, coef, g, th, st, ts);
+}
+
+template <typename T>
+hipError_t output_color_e(const View &I, const View &Q, const float *mean, const Geo &g, bool vec, hipStream_t st,
+                          const Stamp &ts, const Detail &dt) {
+    return dt.p.data ? output_color_t<T, true>(I, Q, mean, g, vec, st, ts, dt)
+                     : output_color_t<T, false>(I, Q, mean, g, vec, st, ts, dt);
 }
 
 hipError_t launch_output_color(gf_dtype dt, const View &I, const View &Q, const float *mean, const Geo &g, bool vec,
-                               hipStream_t st, const Stamp &ts) {
+                               hipStream_t st, const Stamp &ts, const Detail &detail) {
     switch (dt) {
-        case GF_F32: return output_color_t<float>(I, Q, mean, g, vec, st, ts);
-        case GF_F16: return output_color_t<_Float16>(I, Q, mean, g, vec, st, ts);
-        case GF_BF16: return output_color_t<dev::bf16>(I, Q, mean, g, vec, st, ts);
+        case GF_F32: return output_color_e<float>(I, Q, mean, g, vec, st, ts, detail);
+        case GF_F16: return output_color_e<_Float16>(I, Q, mean, g, vec, st, ts, detail);
+        case GF_BF16: return output_color_e<dev::bf16>(I, Q, mean, g, vec, st, ts, detail);
     }
     return hipErrorInvalidValue;
 }

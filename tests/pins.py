@@ -608,13 +608,14 @@ def pin_color_coefficients_lstsq(orc):
                 assert abs(ex["b"][ky, kx] - sol[3]) < 1e-9, (border, r, ky, kx)
 
 
-def composed_color(I, p, r, s, eps, mode, border):
+def composed_color(I, p, r, s, eps, mode, border, joint=False):
     """Colour guidance from library routines: torch subsampling (or pooling),
-    scipy box means, numpy's batched 3x3 solve, torch upsampling."""
+    scipy box means, numpy's batched 3x3 solve, torch upsampling.  With
+    joint, p is the low-res input and only the guide is subsampled."""
     h, w = I.shape[1:]
     rl = 0 if r == 0 else max(1, int(math.floor(r / s + 0.5)))
     Il = np.stack([lib_sub(I[j], s, mode) if s > 1 else I[j] for j in range(3)])
-    pl = lib_sub(p, s, mode) if s > 1 else p
+    pl = p if (joint or s == 1) else lib_sub(p, s, mode)
     mI = np.stack([lib_box(Il[j], rl, border) for j in range(3)])
     mp = lib_box(pl, rl, border)
     S = np.empty(Il.shape[1:] + (3, 3))
@@ -657,6 +658,25 @@ def pin_color_gray_guide(orc):
     for s, mode, border in [(1, "nearest", "clip"), (4, "nearest", "clip"), (2, "bilinear", "reflect101")]:
         _close(orc.fast_guided_filter_color(np.stack([G, G, G]), p, 6, s, 3e-2, mode, border),
                orc.fast_guided_filter(G, p, 6, s, 1e-2, mode, border=border), 1e-10, f"equal planes s={s}")
+
+
+def pin_color_joint(orc):
+    """Colour joint upsampling equals its library assembly for a low-res
+    input that is not a subsample, and the colour fast filter when p_lo is
+    p subsampled by the library routine."""
+    g = _rng(55)
+    for (h, w), r, s, mode, border in [((33, 40), 8, 4, "nearest", "clip"), ((26, 31), 4, 2, "bilinear", "reflect101"),
+                                       ((30, 27), 6, 3, "area", "replicate")]:
+        I = g.uniform(0, 1, size=(3, h, w))
+        p_lo = g.uniform(0, 1, size=(-(-h // s), -(-w // s)))
+        got = orc.joint_upsample_color(I, p_lo, r, s, 1e-2, mode, border)
+        _close(got, composed_color(I, p_lo, r, s, 1e-2, mode, border, joint=True), 1e-10,
+               f"colour joint {h}x{w} s={s} {mode} {border}")
+        p = g.uniform(0, 1, size=(2, h, w))
+        p_sub = np.stack([lib_sub(p[k], s, mode) for k in range(2)])
+        _close(orc.joint_upsample_color(I, p_sub, r, s, 1e-2, mode, border),
+               orc.fast_guided_filter_color(I, p, r, s, 1e-2, mode, border), 1e-13,
+               f"colour joint of subsampled p s={s} {mode}")
 
 
 def pin_color_invariants(orc):

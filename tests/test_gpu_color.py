@@ -99,16 +99,52 @@ def test_color_batched_runs_per_image():
         assert torch.equal(qs[k], solo), specs[k]
 
 
+@pytest.mark.parametrize("s,sub,border,dt", [(4, "nearest", "clip", "f32"), (2, "bilinear", "reflect101", "f32"),
+                                              (3, "area", "replicate", "f32"), (4, "nearest", "clip", "f16")])
+def test_color_joint_upsample(s, sub, border, dt):
+    """A low-res RGB input guided by a full-res RGB guide, against the oracle."""
+    import torch
+    h, w, c, r = 301, 405, 3, 16
+    I = synth.colour_guide(h, w, seed=41)
+    g = np.random.Generator(np.random.PCG64(42))
+    p_lo = g.uniform(0, 1, size=(c, -(-h // s), -(-w // s))).astype(np.float32)
+    dI, dp = gpuutil.to_device(I, dt), gpuutil.to_device(p_lo, dt)
+    q = gfp.gf_joint_upsample(dI, dp, r, s, 1e-3, sub, border=border)
+    torch.cuda.synchronize()
+    exp = oracle.joint_upsample_color(gpuutil.stored_f64(dI), gpuutil.stored_f64(dp), r, s, 1e-3, sub, border)
+    got = gpuutil.stored_f64(q)
+    assert np.all(np.abs(got - exp) <= gpuutil.tolerance(dt, exp)), gpuutil.max_err(got, exp)
+
+
+@pytest.mark.parametrize("s,dt", [(4, "f32"), (1, "f32"), (8, "bf16")])
+def test_color_detail_enhance(s, dt):
+    """e = q + 5 (p - q) with q the colour-guided filter; tolerance as for
+    the gray guide's detail test: |1 - gain| times q's bound plus one rounding
+    of e."""
+    import torch
+    h, w, c, gain = 250, 330, 3, 5.0
+    I = synth.colour_guide(h, w, seed=51)
+    p = synth.colour_input(I.mean(axis=0, dtype=np.float32), c, seed=52)
+    dI, dp = gpuutil.to_device(I, dt), gpuutil.to_device(p, dt)
+    e = gfp.gf_detail_enhance(dI, dp, 16, s, 1e-2, gain)
+    torch.cuda.synchronize()
+    I64, p64 = gpuutil.stored_f64(dI), gpuutil.stored_f64(dp)
+    exp = oracle.detail_enhance(p64, oracle.fast_guided_filter_color(I64, p64, 16, s, 1e-2), gain)
+    got = gpuutil.stored_f64(e)
+    tq = {"f32": 1e-5, "f16": 2e-3, "bf16": 4e-3}[dt]
+    bits = {"f32": 24, "f16": 11, "bf16": 8}[dt]
+    half_ulp = np.exp2(np.floor(np.log2(np.maximum(np.abs(exp), 1e-30))) - bits)
+    assert np.all(np.abs(got - exp) <= abs(1 - gain) * tq + half_ulp + 1e-7), gpuutil.max_err(got, exp)
+
+
 def test_color_refused_where_unsupported():
     import torch
     I = gpuutil.to_device(synth.colour_guide(64, 64, seed=1))
     p = gpuutil.to_device(synth.photo_guide(64, 64, seed=2))[None]
-    with pytest.raises(gfp.GfError) as ei:
-        gfp.gf_detail_enhance(I, p, 8, 4, 1e-2, 5.0)
-    assert ei.value.status == gfp.GF_ENOTSUP
-    with pytest.raises(gfp.GfError) as ei:
-        gfp.gf_joint_upsample(I, p[:, ::4, ::4].contiguous(), 8, 4, 1e-2)
-    assert ei.value.status == gfp.GF_ENOTSUP
+    with gfp.Context(0) as ctx:
+        with pytest.raises(gfp.GfError) as ei:
+            ctx.tune(I, p, 8, 4, 1e-2)
+        assert ei.value.status == gfp.GF_ENOTSUP
     with gfp.Context(0, arena_bytes=1 << 26, max_inflight=4) as ctx:
         with pytest.raises(gfp.GfError) as ei:
             ctx.gf_submit(I, p, torch.empty_like(p), 8, 4, 1e-2)

@@ -69,8 +69,12 @@ MUTANTS = {
     "color_b_one_channel_mean": ("bi -= x[j] * mI[(size_t)j * n + i];", "bi -= x[j] * mI[i];"),
     "color_cross_terms_dropped": ("for (size_t i = 0; i < n; ++i) tmp[i] = Ij[i] * Ik[i];",
                                   "for (size_t i = 0; i < n; ++i) tmp[i] = Ij[i] * Ij[i];"),
-    "color_output_skips_plane": ("        for (int j = 0; j < 3; ++j) {\n            if ((rc = oracle_box_mean_border(ca",
-                                 "        for (int j = 0; j < 2; ++j) {\n            if ((rc = oracle_box_mean_border(ca"),
+    "color_output_skips_plane": ("        for (int j = 0; j < 3; ++j) {\n            if ((rc = oracle_box_mean_border(ca + (size_t)j * nl, hl, wl, rl, border, mean_lo))) goto done;\n            if ((rc = oracle_upsample(mean_lo, hl, wl, s, h, w, up))) goto done;\n            const double *Ij",
+                                 "        for (int j = 0; j < 2; ++j) {\n            if ((rc = oracle_box_mean_border(ca + (size_t)j * nl, hl, wl, rl, border, mean_lo))) goto done;\n            if ((rc = oracle_upsample(mean_lo, hl, wl, s, h, w, up))) goto done;\n            const double *Ij"),
+    "color_joint_full_radius": ("if ((rc = coefficients_color(Il, p_lo + (size_t)k * nl, hl, wl, rl, eps, border, ca, cb))) goto done;",
+                                "if ((rc = coefficients_color(Il, p_lo + (size_t)k * nl, hl, wl, r, eps, border, ca, cb))) goto done;"),
+    "color_joint_guide_unsubsampled_plane": ("            for (size_t i = 0; i < n; ++i) qk[i] += up[i] * I[(size_t)j * n + i];",
+                                             "            for (size_t i = 0; i < n; ++i) qk[i] += up[i] * I[i];"),
     "color_output_planes_swapped": ("const double *Ij = I + (size_t)j * n;\n            for (size_t i = 0; i < n; ++i) qk[i] += up[i] * Ij[i];",
                                     "const double *Ij = I + (size_t)(2 - j) * n;\n            for (size_t i = 0; i < n; ++i) qk[i] += up[i] * Ij[i];"),
 }
