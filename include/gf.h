@@ -36,9 +36,10 @@
  * Sigma the 3x3 population covariance of I in the window (sums in FP64, the
  * 3x3 solve in FP64), and q = mean_a.I + mean_b.  gf_plain, gf_fast,
  * gf_joint_upsample, gf_detail_enhance and the batched and prepared-batch
- * calls take it (a batch holding one runs image by image); gf_tune and
- * gf_submit refuse it (GF_ENOTSUP), as every call does a low-res radius whose
- * colour tiles do not fit in LDS (above about 24).
+ * calls take it (a batch holding one runs image by image, and gf_submit
+ * runs such a request in a batch of its own); gf_tune refuses it
+ * (GF_ENOTSUP), as every call does a low-res radius whose colour tiles do
+ * not fit in LDS (above about 24).
  *
  * Options for the conventions of other image libraries (gf_params):
  *   - GF_BORDER_REPLICATE / GF_BORDER_REFLECT101: every box mean (of the
@@ -50,7 +51,7 @@
  *     block [s*y, s*y+s) x [s*x, s*x+s) clipped to the image.  It reads all
  *     of I and p, in a pass of its own (FP64 block sums, the mean stored as
  *     FP32 in the workspace); batched launches of a batch that holds such an
- *     image run image by image, and gf_submit refuses it.
+ *     image run image by image, and gf_submit runs such a request alone.
  *
  * Arithmetic: all window sums, coefficients and interpolation in FP32
  * (window sums of mean-shifted values, tile by tile); images may be stored as
@@ -190,7 +191,8 @@ gf_status gf_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q
  * one request of this shape occupies while it is in flight (its low-res maps
  * and its share of the batch's control words and descriptor table).
  * gf_submit refuses a request whose footprint exceeds the arena (GF_ENOMEM).
- * The dtype does not change it (all maps are FP32).  0 for invalid sizes.
+ * The dtype does not change it (all maps are FP32).  Gray guide (a colour
+ * guide needs twice the maps).  0 for invalid sizes.
  */
 size_t gf_footprint_bytes(int32_t h, int32_t w, int32_t c, gf_dtype dtype, const gf_params *params);
 
@@ -320,7 +322,10 @@ void gf_batch_destroy(gf_batch *batch);
 /*
  * Asynchronous request: filter (I, p) into q like gf_fast.  The request is
  * admitted when the context's arena has room for its workspace, batched with
- * the other requests in flight, and run on the context's own streams.
+ * the other requests in flight, and run on the context's own streams.  A
+ * request the batched kernels do not run (a colour guide, area subsampling,
+ * a low-res radius above their limit) is admitted alone and runs the
+ * per-image kernels; its q equals gf_fast's with the built-in tile shapes.
  * Returns GF_OK with *ticket set, GF_ENOMEM if it can never fit the arena,
  * GF_EBUSY if `max_inflight` requests are held, GF_EINVAL for bad arguments.
  * I, p, q must stay valid until gf_poll returns a terminal status.

@@ -12,6 +12,9 @@
 //   * launches each admitted group as one persistent batched kernel on the
 //     next of its streams, so requests that arrive while earlier batches run
 //     are admitted as memory frees up and their work overlaps on the device.
+//     A request the batched kernels do not run (a low-res radius above their
+//     limit, area subsampling, a colour guide) is admitted alone and runs
+//     the per-image kernels.
 // A request's result is exactly what the batched launch computes for it,
 // whatever else shares its batch (tile shapes depend only on the radius).
 #include <hip/hip_runtime_api.h>
@@ -44,6 +47,7 @@ struct Request {
     gf_params pr;
     size_t footprint;  // workspace bytes of this request alone
     int R;             // low-res radius (decides the request's tile height)
+    bool solo;         // runs the per-image kernels, in a batch of its own
     gf_req_stats st{};
     gf_status status = GF_PENDING;
 };
@@ -120,9 +124,6 @@ class Engine {
         if (st != GF_OK) return st;
         BatchPlan one;
         if ((st = plan_batch(1, I, p, q, pr, nullptr, ctx_batch_cfg(ctx_), &one)) != GF_OK) return st;
-        if (one.th == 0)
-            return fail(GF_ENOTSUP, "the request needs per-image launches (low-res radius above the batched "
-                                    "kernel's limit, area subsampling or a colour guide)");
         if (one.ws_bytes > bytes_)
             return fail(GF_ENOMEM, "request needs %zu bytes of arena, the arena holds %zu", one.ws_bytes,
                         bytes_);
@@ -138,6 +139,7 @@ class Engine {
         r.pr = *pr;
         r.footprint = one.ws_bytes;
         r.R = lowres_radius(pr->r, pr->s);
+        r.solo = one.th == 0;
         r.st.t_submit = now_s();
         queue_.push_back(t);
         *ticket = t;
@@ -230,7 +232,9 @@ class Engine {
             int th = -1;
             for (uint64_t tk : queue_) {
                 const Request &r = reqs_.at(tk);
-                const int rth = batch_tile_h(cfg, r.R);
+                // a request for the per-image kernels goes alone (tile height "-2")
+                const int rth = r.solo ? -2 : batch_tile_h(cfg, r.R);
+                if (th == -2 || (rth == -2 && th != -1)) break;
                 if (th < 0) th = rth;
                 // the batch's own workspace grows by this request's planes and descriptor
                 const size_t grow = r.footprint;
@@ -259,9 +263,19 @@ class Engine {
             err_slots_[b.slot] = 0;
             const double t = now_s();
             for (uint64_t tk : take) reqs_.at(tk).st.t_admit = t;
-            gf_status st = launch_plan(ctx_, plan, ws, s);
+            gf_status st;
+            if (plan.th == 0) {
+                // per-image kernels on the request's share of the workspace; no error word
+                const BDesc &d = plan.desc[0];
+                st = run_fast(ctx_, &I[0], &p[0], &q[0], &pr[0], d.coef, workspace_bytes(d.g), s, nullptr);
+            } else {
+                st = launch_plan(ctx_, plan, ws, s);
+            }
             hipError_t e = hipSuccess;
-            if (st == GF_OK) {
+            if (st == GF_OK && plan.th == 0) {
+                e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+                if (e == hipSuccess) e = hipEventRecord(b.done, s);
+            } else if (st == GF_OK) {
                 // the kernel's error word (control word 1) comes back with the batch
                 e = hipMemcpyAsync(&err_slots_[b.slot], ws + sizeof(unsigned), sizeof(unsigned),
                                    hipMemcpyDeviceToHost, s);

@@ -188,20 +188,24 @@ def test_batched_with_area_runs_per_image():
 
 
 def test_served_border_and_area():
-    """gf_submit runs a padded-border request like gf_fast and refuses area
-    subsampling (its pass is not part of the batched kernels)."""
+    """gf_submit runs a padded-border request (batched kernels) and an
+    area-subsampled one (per-image kernels, admitted alone) like gf_fast,
+    interleaved with plain requests."""
     import torch
     I = synth.photo_guide(200, 260, seed=71)
     p = synth.colour_input(I, 3, seed=72)
     dI, dp = gpuutil.to_device(I), gpuutil.to_device(p)
+    kinds = [("nearest", "reflect101"), ("area", "clip"), ("nearest", "clip"), ("area", "replicate"),
+             ("bilinear", "replicate")]
     with gfp.Context(0, arena_bytes=1 << 28, max_inflight=8) as ctx:
-        q = torch.empty_like(dp)
-        t = ctx.gf_submit(dI, dp, q, 12, 4, 1e-3, "nearest", "reflect101")
-        st, _ = ctx.gf_poll(t, 10000)
-        assert st == gfp.GF_OK
-        solo = gfp.gf_fast(dI, dp, 12, 4, 1e-3, "nearest", border="reflect101")
-        torch.cuda.synchronize()
-        assert torch.equal(q, solo)
-        with pytest.raises(gfp.GfError) as ei:
-            ctx.gf_submit(dI, dp, torch.empty_like(dp), 12, 4, 1e-3, "area")
-        assert ei.value.status == gfp.GF_ENOTSUP
+        qs, tickets = [], []
+        for sub, border in kinds:
+            qs.append(torch.empty_like(dp))
+            tickets.append(ctx.gf_submit(dI, dp, qs[-1], 12, 4, 1e-3, sub, border))
+        for t in tickets:
+            st, _ = ctx.gf_poll(t, 10000)
+            assert st == gfp.GF_OK
+        for q, (sub, border) in zip(qs, kinds):
+            solo = gfp.gf_fast(dI, dp, 12, 4, 1e-3, sub, border=border)
+            torch.cuda.synchronize()
+            assert torch.equal(q, solo), (sub, border)

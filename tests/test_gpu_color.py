@@ -137,15 +137,30 @@ def test_color_detail_enhance(s, dt):
     assert np.all(np.abs(got - exp) <= abs(1 - gain) * tq + half_ulp + 1e-7), gpuutil.max_err(got, exp)
 
 
-def test_color_refused_where_unsupported():
-    import torch
+def test_color_tuner_refused():
     I = gpuutil.to_device(synth.colour_guide(64, 64, seed=1))
     p = gpuutil.to_device(synth.photo_guide(64, 64, seed=2))[None]
     with gfp.Context(0) as ctx:
         with pytest.raises(gfp.GfError) as ei:
             ctx.tune(I, p, 8, 4, 1e-2)
         assert ei.value.status == gfp.GF_ENOTSUP
-    with gfp.Context(0, arena_bytes=1 << 26, max_inflight=4) as ctx:
-        with pytest.raises(gfp.GfError) as ei:
-            ctx.gf_submit(I, p, torch.empty_like(p), 8, 4, 1e-2)
-        assert ei.value.status == gfp.GF_ENOTSUP
+
+
+def test_color_served_like_solo():
+    """gf_submit admits a colour-guided request alone (per-image kernels):
+    the result equals gf_fast, also with gray requests queued around it."""
+    import torch
+    Ic = gpuutil.to_device(synth.colour_guide(180, 240, seed=61))
+    Ig = gpuutil.to_device(synth.photo_guide(180, 240, seed=62))
+    p = gpuutil.to_device(synth.colour_input(synth.photo_guide(180, 240, seed=62), 3, seed=63))
+    with gfp.Context(0, arena_bytes=1 << 27, max_inflight=8) as ctx:
+        guides = [Ig, Ic, Ig, Ic]
+        qs = [torch.empty_like(p) for _ in guides]
+        tickets = [ctx.gf_submit(I, p, q, 8, 4, 1e-2) for I, q in zip(guides, qs)]
+        for t in tickets:
+            st, _ = ctx.gf_poll(t, 10000)
+            assert st == gfp.GF_OK
+        for I, q in zip(guides, qs):
+            solo = gfp.gf_fast(I, p, 8, 4, 1e-2)
+            torch.cuda.synchronize()
+            assert torch.equal(q, solo)
