@@ -26,11 +26,12 @@ def content(spec, seed, dtype):
     return gpuutil.to_device(I, dtype), gpuutil.to_device(p, dtype)
 
 
-def run_graph_case(specs, dtype, schedule="phases", replays=3):
+def run_graph_case(specs, dtype, schedule="phases", replays=3, borders=None):
     import torch
     print(f"graph case: {len(specs)} images, {dtype}, {schedule}", flush=True)
     Is, ps = map(list, zip(*[content(sp, 10 + k, dtype) for k, sp in enumerate(specs)]))
-    prs = [gfp.params(r, s, 1e-3, sub) for (_, _, _, r, s, sub) in specs]
+    borders = borders or ["clip"] * len(specs)
+    prs = [gfp.params(r, s, 1e-3, sub, bd) for (_, _, _, r, s, sub), bd in zip(specs, borders)]
     bctx = gfp.Context(0)
     bctx.set_batch_cfg(schedule, 16)
     b = gfp.Batch(Is, ps, prs, ctx=bctx)
@@ -54,7 +55,7 @@ def run_graph_case(specs, dtype, schedule="phases", replays=3):
             q.fill_(float("nan"))  # a replay that writes nothing cannot pass
         # unrelated eager work through the library between replays
         h, w, c, r, s, sub = specs[0]
-        gfp.gf_fast(Is[0], ps[0], r, s, 1e-3, sub, ctx=ctx)
+        gfp.gf_fast(Is[0], ps[0], r, s, 1e-3, sub, ctx=ctx, border=borders[0])
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
@@ -65,7 +66,8 @@ def run_graph_case(specs, dtype, schedule="phases", replays=3):
         # one image per replay against the oracle
         k = rep % len(specs)
         h, w, c, r, s, sub = specs[k]
-        exp = oracle.fast_guided_filter(gpuutil.stored_f64(Is[k]), gpuutil.stored_f64(ps[k]), r, s, 1e-3, sub)
+        exp = oracle.fast_guided_filter(gpuutil.stored_f64(Is[k]), gpuutil.stored_f64(ps[k]), r, s, 1e-3, sub,
+                                        border=borders[k])
         got = gpuutil.stored_f64(b.qs[k])
         assert np.all(np.abs(got - exp) <= gpuutil.tolerance(dtype, exp)), (rep, k, gpuutil.max_err(got, exp))
     del g
@@ -82,3 +84,17 @@ def test_graph_replays_batch(dtype, schedule):
 
 def test_graph_replays_per_image_batch():
     run_graph_case(PER_IMAGE, "f32")
+
+
+@pytest.mark.parametrize("schedule", ["phases", "queue"])
+def test_graph_replays_padded_border_batch(schedule):
+    """Batched kernels choose the border's tile code per task."""
+    run_graph_case(BATCH, "f32", schedule,
+                   borders=["reflect101", "replicate", "clip", "reflect101", "replicate", "clip"])
+
+
+def test_graph_replays_area_batch():
+    """Area subsampling: the batch runs image by image (area pass, then the
+    per-image kernels), all captured in the graph."""
+    specs = [(300, 400, 3, 8, 4, "area"), (257, 129, 1, 5, 2, "area"), (150, 151, 2, 6, 3, "nearest")]
+    run_graph_case(specs, "f32", borders=["clip", "reflect101", "clip"])
