@@ -44,9 +44,10 @@ __device__ __forceinline__ void solve3_sym(double m00, double m01, double m02, d
 // exact in FP64): each pass is a row pass writing two row-sum planes, then a
 // column pass summing them into registers.  Five passes give the guide's
 // nine sums (S_j, S_jk) once for all channels; two more per channel give
-// S_v and S_jv (channel 0's S_1v rides in the fifth).  Then per pixel, with n the window's sample count,
-// n^2 Sigma_jk = n S_jk - S_j S_k and n^2 cov_j = n S_jv - S_j S_v, and
-// a = (n^2 Sigma + n^2 eps U)^-1 (n^2 cov), solved in FP64.
+// S_v and S_jv (channel 0's S_1v rides in the fifth).  Then per pixel, with
+// n the window's sample count, n^2 Sigma_jk = n S_jk - S_j S_k and
+// n^2 cov_j = n S_jv - S_j S_v, and a = (n^2 Sigma + n^2 eps U)^-1 (n^2 cov),
+// solved in FP64.
 // KP: how p is sampled -- like I, or kSubId when p is given at low
 // resolution (joint upsampling).
 template <typename T, int K, int TH, int BD, int KP = K>
