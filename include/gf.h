@@ -371,7 +371,7 @@ gf_status gf_ctx_profile_read(gf_ctx *ctx, gf_kernel_time *out);
 /*
  * Tile shapes of the window-sum kernels (Algorithm 2 steps 2-5).  Both the
  * coefficient kernel and the box-mean kernel work on tiles of 64 low-res
- * columns by *_th rows (8, 16, 24 or 32) plus an r' halo staged in LDS.
+ * columns by *_th rows (8, 16, 24, 32, 48 or 64) plus an r' halo staged in LDS.
  * Tall tiles amortise the halo; short ones need less LDS per workgroup.
  */
 typedef struct {

@@ -78,21 +78,32 @@ Geo make_geo(int H, int W, int C, const gf_params &pr, int G) {
 
 static const size_t kLdsMax = kLdsLimit;
 
-static bool th_ok(int th) { return th == 8 || th == 16 || th == 24 || th == 32; }
+static bool th_ok(int th) { return th == 8 || th == 16 || th == 24 || th == 32 || th == 48 || th == 64; }
 
-// Tile height: tall tiles amortise the 2r' halo rows.  Prefer 24 rows when
-// the footprint leaves room for two workgroups per CU (measured best at
-// r' <= 8); at larger radii the halo dominates, so take the tallest tile
-// that fits at all.
+// Tile height: tall tiles amortise the 2r' halo rows, short ones leave room
+// for more workgroups per CU.  The choices follow a sweep of both kernels at
+// r' = 2..32 on a 12 MP image.  At r' <= 4, 24 rows for both (the batched
+// kernels use the same tiles there, so gf_fast and the batch give the same
+// bits).  Coefficients: 32 rows up to r' = 10, then the tallest tile whose
+// region still fits in LDS.  Box means: 48 rows up to r' = 16, then the
+// tallest tile that leaves room for two workgroups per CU.
 static int pick_th(int R, bool coeff) {
-    auto bytes = [&](int th) {
+    auto fits = [&](int th, size_t room) {
         const TileCfg t{th, th};
-        return coeff ? coeff_lds_bytes(t, R) : box_lds_bytes(t, R);
+        return coeff ? coeff_staged(t, R) && coeff_lds_bytes(t, R) <= room : box_lds_bytes(t, R) <= room;
     };
-    if (bytes(24) <= 64 * 1024 && (!coeff || coeff_staged(TileCfg{24, 24}, R))) return 24;
-    for (int th : {32, 24, 16})
-        if (bytes(th) <= kLdsMax && (!coeff || coeff_staged(TileCfg{th, th}, R))) return th;
-    return 8;  // coefficient tiles fall back to unstaged 8-row tiles
+    if (R <= 4 && fits(24, kLdsMax)) return 24;
+    if (coeff) {
+        if (R <= 10 && fits(32, kLdsMax)) return 32;
+        for (int th : {64, 48, 32, 24, 16})
+            if (fits(th, kLdsMax)) return th;
+        return 8;  // unstaged 8-row tiles
+    }
+    if (R <= 16 && fits(48, kLdsMax)) return 48;
+    for (size_t room : {(size_t)80 * 1024, kLdsMax})
+        for (int th : {64, 48, 32, 24, 16})
+            if (fits(th, room)) return th;
+    return 8;
 }
 
 TileCfg default_tiles(const Geo &g) {

@@ -36,8 +36,8 @@ struct View {
 
 // Tile shapes for one call (picked by the host heuristic or the tuner).
 struct TileCfg {
-    int coeff_th;  // rows of a coefficient tile (8, 16, 24 or 32); tiles are 64 columns wide
-    int box_th;    // rows of a box-mean tile (8, 16, 24 or 32)
+    int coeff_th;  // rows of a coefficient tile (8, 16, 24, 32, 48 or 64); tiles are 64 columns wide
+    int box_th;    // rows of a box-mean tile (8, 16, 24, 32, 48 or 64)
 };
 
 constexpr int kThreads = 256;   // threads per workgroup for every kernel

@@ -20,7 +20,7 @@ static gf_tiles to_abi(const TileCfg &c) { return gf_tiles{c.coeff_th, c.box_th}
 // Candidates of one kernel; the other kernel's field is taken from `base`.
 static std::vector<TileCfg> candidates(const Geo &g, const TileCfg &base, int kernel) {
     std::vector<TileCfg> out;
-    for (int th : {8, 16, 24, 32}) {
+    for (int th : {8, 16, 24, 32, 48, 64}) {
         TileCfg c = base;
         (kernel == GF_K_COEFF ? c.coeff_th : c.box_th) = th;
         if (tiles_fit(g, c)) out.push_back(c);

@@ -79,7 +79,9 @@ hipError_t coeff_tk(const View &I, const View &P, float *coef, const Geo &g, con
             case 8: GF_COEFF(8, true) break;
             case 16: GF_COEFF(16, true) break;
             case 24: GF_COEFF(24, true) break;
-            default: GF_COEFF(32, true) break;
+            case 32: GF_COEFF(32, true) break;
+            case 48: GF_COEFF(48, true) break;
+            default: GF_COEFF(64, true) break;
         }
     }
 #undef GF_COEFF
@@ -132,7 +134,9 @@ hipError_t box_b(const float *src, float *dst, const Geo &g, const TileCfg &t, h
         case 8: GF_BOX(8) break;
         case 16: GF_BOX(16) break;
         case 24: GF_BOX(24) break;
-        default: GF_BOX(32) break;
+        case 32: GF_BOX(32) break;
+        case 48: GF_BOX(48) break;
+        default: GF_BOX(64) break;
     }
 #undef GF_BOX
     return hipGetLastError();

@@ -23,7 +23,7 @@ def test_every_tile_shape_matches_oracle(h, w, c, r, s, sub):
     exp = oracle.fast_guided_filter(I.astype(np.float64), p.astype(np.float64), r, s, 1e-3, sub)
     dI, dp = gpuutil.to_device(I), gpuutil.to_device(p)
     ctx = gfp.Context(0)
-    for cth, bth in itertools.product((8, 16, 24, 32), (8, 16, 24, 32)):
+    for cth, bth in itertools.product((8, 16, 24, 32, 48, 64), repeat=2):
         ctx.set_tiles(dI, dp, r, s, 1e-3, dict(coeff_th=cth, box_th=bth), sub)
         q = gfp.gf_fast(dI, dp, r, s, 1e-3, sub, ctx=ctx)
         torch.cuda.synchronize()
