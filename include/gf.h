@@ -253,8 +253,10 @@ gf_status gf_fast_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_im
  *   GF_BATCH_QUEUE: one persistent kernel; workgroups take tiles from a
  *     queue ordered phase by phase and wait on per-image phase counters, so
  *     the phases of different images overlap.
- * tile_h: rows of the low-res window-sum tiles (8, 16 or 24); 0 picks the
- * tallest of 24, 16, 8 whose tiles fit in LDS at the batch's largest r'.
+ * tile_h: rows of the low-res window-sum tiles: 8, 16, 24, or 32 and 48
+ * with GF_BATCH_PHASES.  A batch takes the tallest height up to tile_h
+ * whose tiles fit in LDS at its largest r' (at most 24 under
+ * GF_BATCH_QUEUE); 0 means up to 24.
  */
 typedef enum { GF_BATCH_PHASES = 0, GF_BATCH_QUEUE = 1 } gf_batch_schedule;
 

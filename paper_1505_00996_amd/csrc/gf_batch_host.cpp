@@ -23,8 +23,11 @@ static size_t round256(size_t v) { return (v + 255) / 256 * 256; }
 // radius, so an image gives the same bits alone and in any batch, and the
 // same bits as gf_fast with tiles {th, th}.
 static int batch_th(int sched, int want, int maxR, BatchPlan *plan) {
-    for (int th : {24, 16, 8}) {
-        if (want && th > want) continue;
+    // 32 and 48 rows only when asked for, and for the phase schedule only
+    // (the queue kernel carries every phase's LDS and registers at once)
+    const int cap = std::min(want ? want : 24, sched == GF_BATCH_QUEUE ? 24 : 48);
+    for (int th : {48, 32, 24, 16, 8}) {
+        if (th > cap) continue;
         const TileCfg t{th, th};
         if (!coeff_staged(t, maxR)) continue;
         const size_t c = coeff_lds_bytes(t, maxR), b = box_lds_bytes(t, maxR);
@@ -49,7 +52,8 @@ int batch_tile_h(const gf_batch_cfg &cfg, int maxR) {
 
 static bool cfg_ok(const gf_batch_cfg &c) {
     return (c.schedule == GF_BATCH_PHASES || c.schedule == GF_BATCH_QUEUE) &&
-           (c.tile_h == 0 || c.tile_h == 8 || c.tile_h == 16 || c.tile_h == 24);
+           (c.tile_h == 0 || c.tile_h == 8 || c.tile_h == 16 || c.tile_h == 24 || c.tile_h == 32 ||
+            c.tile_h == 48);
 }
 
 gf_batch_cfg ctx_batch_cfg(gf_ctx *ctx) {

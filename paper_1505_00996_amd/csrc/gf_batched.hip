@@ -444,9 +444,14 @@ hipError_t launch_phases(gf_dtype dt, int th, const BDesc *D, int n, unsigned *c
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
 #define GF_P(TT)                                                                                    \
-    return th == 8 ? phases_t<TT, 8>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st)            \
-         : th == 16 ? phases_t<TT, 16>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st)          \
-                    : phases_t<TT, 24>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st)
+    switch (th) {                                                                                   \
+        case 8: return phases_t<TT, 8>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);         \
+        case 16: return phases_t<TT, 16>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);       \
+        case 24: return phases_t<TT, 24>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);       \
+        case 32: return phases_t<TT, 32>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);       \
+        case 48: return phases_t<TT, 48>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);       \
+    }                                                                                               \
+    return hipErrorInvalidValue
     switch (dt) {
         case GF_F32: GF_P(float);
         case GF_F16: GF_P(_Float16);
@@ -457,9 +462,15 @@ hipError_t launch_phases(gf_dtype dt, int th, const BDesc *D, int n, unsigned *c
 }
 
 hipError_t phases_allow_lds(gf_dtype dt, int th, size_t lds_coeff, size_t lds_box) {
-#define GF_PA(TT)                                                                 \
-    return th == 8 ? phases_allow_t<TT, 8>(lds_coeff, lds_box)                    \
-         : th == 16 ? phases_allow_t<TT, 16>(lds_coeff, lds_box) : phases_allow_t<TT, 24>(lds_coeff, lds_box)
+#define GF_PA(TT)                                                    \
+    switch (th) {                                                    \
+        case 8: return phases_allow_t<TT, 8>(lds_coeff, lds_box);    \
+        case 16: return phases_allow_t<TT, 16>(lds_coeff, lds_box);  \
+        case 24: return phases_allow_t<TT, 24>(lds_coeff, lds_box);  \
+        case 32: return phases_allow_t<TT, 32>(lds_coeff, lds_box);  \
+        case 48: return phases_allow_t<TT, 48>(lds_coeff, lds_box);  \
+    }                                                                \
+    return hipErrorInvalidValue
     switch (dt) {
         case GF_F32: GF_PA(float);
         case GF_F16: GF_PA(_Float16);

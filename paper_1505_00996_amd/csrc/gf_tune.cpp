@@ -193,7 +193,7 @@ gf_status gf_tune_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_im
     int found = 0, nres = 0;
     st = GF_OK;
     for (int sched : {GF_BATCH_PHASES, GF_BATCH_QUEUE}) {
-        for (int th : {8, 16, 24}) {
+        for (int th : {8, 16, 24, 32, 48}) {
             const gf_batch_cfg c{sched, th};
             BatchPlan plan;
             if ((st = plan_batch(n, I, p, q, pr, (char *)ws, c, &plan)) != GF_OK) break;

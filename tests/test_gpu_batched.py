@@ -25,7 +25,8 @@ def make(spec, k, dtype):
     return gpuutil.to_device(I, dtype), gpuutil.to_device(p, dtype)
 
 
-@pytest.mark.parametrize("schedule,th", [("phases", 16), ("queue", 16), ("phases", 8), ("queue", 24)])
+@pytest.mark.parametrize("schedule,th", [("phases", 16), ("queue", 16), ("phases", 8), ("queue", 24), ("phases", 32),
+                                         ("phases", 48)])
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
 def test_mixed_batch_matches_oracle_and_solo(dtype, schedule, th):
     import torch
