@@ -199,18 +199,6 @@ gf_status validate(const gf_image *I, const gf_image *p, const gf_image *q,
     return GF_OK;
 }
 
-// Row accesses of `bytes` bytes need the row starts of I and of every q
-// plane aligned to that size (per-image output kernel: 16 bytes; batched
-// kernels: 4 pixels).
-bool vector_ok(const gf_image *I, const gf_image *q, size_t bytes) {
-    const size_t es = elem_size(I->dtype), vb = bytes;
-    auto aligned = [&](const gf_image *im) {
-        return (uintptr_t)im->data % vb == 0 && (im->row_stride * (int64_t)es) % (int64_t)vb == 0 &&
-               (im->c == 1 || (im->plane_stride * (int64_t)es) % (int64_t)vb == 0);
-    };
-    return aligned(I) && aligned(q);
-}
-
 gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
                    const gf_params *pr, void *ws, size_t ws_bytes, hipStream_t st,
                    const TileCfg *tiles, bool p_low, const float *gain) {
@@ -258,14 +246,12 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
     }
     if (e == hipSuccess && color) {
         ProfScope ps(ctx, GF_K_OUTPUT, st, true);
-        const size_t es = I->dtype == GF_F32 ? 4 : 2;
         Detail dt;
         if (gain) {
             dt.p = vP;
             dt.gain = *gain;
         }
-        e = launch_output_color(I->dtype, vI, vQ, mean, g, vector_ok(I, q, 4 * es) && (!gain || vector_ok(p, p, 4 * es)),
-                                st, ps.stamp(), dt);
+        e = launch_output_color(I->dtype, vI, vQ, mean, g, st, ps.stamp(), dt);
         ps.commit(e == hipSuccess);
     } else if (e == hipSuccess) {
         ProfScope ps(ctx, GF_K_OUTPUT, st, true);
@@ -274,8 +260,7 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
             dt.p = vP;
             dt.gain = *gain;
         }
-        e = launch_output(I->dtype, vI, vQ, mean, g, t, vector_ok(I, q, 16) && (!gain || vector_ok(p, p, 16)),
-                          st, ps.stamp(), dt);
+        e = launch_output(I->dtype, vI, vQ, mean, g, t, st, ps.stamp(), dt);
         ps.commit(e == hipSuccess);
     }
     if (e != hipSuccess) return fail(GF_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));

@@ -49,7 +49,6 @@ size_t workspace_bytes(const Geo &g);
 // p_low: p is the low-resolution input of joint upsampling (ceil(h/s) x ceil(w/s)).
 gf_status validate(const gf_image *I, const gf_image *p, const gf_image *q, const gf_params *pr,
                    bool p_low = false);
-bool vector_ok(const gf_image *I, const gf_image *q, size_t bytes);
 gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
                    const gf_params *pr, void *ws, size_t ws_bytes, hipStream_t st,
                    const TileCfg *tiles, bool p_low = false, const float *gain = nullptr);

@@ -112,7 +112,6 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
         d.Qps = q[i].plane_stride;
         d.g = g;
         d.kind = (g.s == 1 || area_pass(g)) ? 0 : ((g.sub == GF_SUB_NEAREST || (g.s & 1)) ? 1 : 2);
-        d.vec = vector_ok(&I[i], &q[i], kOutPx * (I[i].dtype == GF_F32 ? 4 : 2)) ? 1 : 0;
         const int th = plan->th ? plan->th : 8;
         d.ntx_l = (g.Wl + kTileW - 1) / kTileW;
         d.nty_l = (g.Hl + th - 1) / th;

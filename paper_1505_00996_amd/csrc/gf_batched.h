@@ -15,7 +15,6 @@ struct BDesc {
     int64_t Irs, Prs, Pps, Qrs, Qps;
     Geo g;
     int kind;                // subsampling kind (0 identity, 1 nearest, 2 two-tap mean)
-    int vec;                 // 16-byte (or 8-byte) output accesses allowed
     int ntx_l, nty_l;        // low-res tiles: 64 columns x TH rows
     int ntx_o, nty_o;        // output blocks: 256 columns x 32 rows
     unsigned base[3];        // queue index of the image's first task in each phase

@@ -105,8 +105,7 @@ __device__ __forceinline__ void run_output(const BDesc &d, unsigned local, float
     const int yb = y0 + wave_id() * kOutRows, x0 = xw + lane * kOutPx;
     const int nrows = max(0, min(kOutRows, g.H - yb));
     const bool act = x0 < g.W && nrows > 0;
-    const bool in4 = x0 + 3 < g.W;
-    const bool full = d.vec != 0 && in4;
+    const bool full = x0 + 3 < g.W;  // one wide access per row, else element-wise
     const T *I = (const T *)d.I;
     T *Q = (T *)d.Q + (int64_t)c0 * d.Qps;
 
@@ -116,12 +115,9 @@ __device__ __forceinline__ void run_output(const BDesc &d, unsigned local, float
     for (int i = 0; i < kOutRows; ++i) {
         iv[i] = raw4{0, 0, 0, 0};
         if (act && i < nrows) {
-            const T *base = I + (int64_t)(yb + i) * d.Irs, *row = base + x0;
+            const T *row = I + (int64_t)(yb + i) * d.Irs + x0;
             if (full) {
                 iv[i] = ldraw4(row);
-            } else if (in4 && pair_aligned(base)) {
-                const auto lo = ldraw2(row), hi = ldraw2(row + 2);
-                iv[i] = raw4{lo.x, lo.y, hi.x, hi.y};
             } else {
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
@@ -130,12 +126,9 @@ __device__ __forceinline__ void run_output(const BDesc &d, unsigned local, float
         }
     }
     auto store_q = [&](T *plane, int y, f32x4 v) {
-        T *base = plane + (int64_t)y * d.Qrs, *row = base + x0;
+        T *row = plane + (int64_t)y * d.Qrs + x0;
         if (full) {
             st4(row, v);
-        } else if (in4 && pair_aligned(base)) {
-            st2(row, v[0], v[1]);
-            st2(row + 2, v[2], v[3]);
         } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
@@ -295,7 +288,7 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BDesc *__restrict__ 
 template <typename T, int CC, int S>
 __device__ __forceinline__ void out_cc(const BDesc &d, int c0, int yb, int xw) {
     output_rows<T, CC, S>((const T *)d.I, d.Irs, (T *)d.Q + (int64_t)c0 * d.Qps, d.Qrs, d.Qps, d.mean, d.g, c0,
-                          yb, xw, d.vec != 0);
+                          yb, xw);
 }
 
 template <typename T, int TH>

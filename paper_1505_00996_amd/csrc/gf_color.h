@@ -234,15 +234,14 @@ template <typename T, int S, bool EPI = false>
 __device__ __forceinline__ void output_rows_color(const T *__restrict__ I, int64_t Irs, int64_t Ips,
                                                   T *__restrict__ Q, int64_t Qrs, int64_t Qps,
                                                   const float *__restrict__ M, const Geo &g, int yb, int xw,
-                                                  bool vec, const T *__restrict__ P = nullptr, int64_t Prs = 0,
+                                                  const T *__restrict__ P = nullptr, int64_t Prs = 0,
                                                   int64_t Pps = 0, float gain = 0.f) {
     constexpr int ROWS = kColorRows, PX = 4;
     const int lane = threadIdx.x & 63;
     const int x0 = xw + lane * PX;
     const int nrows = min(ROWS, g.H - yb);
     if (x0 >= g.W || nrows <= 0) return;  // no barriers below
-    const bool inpx = x0 + PX - 1 < g.W;
-    const bool full = vec && inpx;
+    const bool full = x0 + PX - 1 < g.W;  // one wide access per row, else element-wise
     typedef PixRow<T, PX> Row;
     Row iv[3][ROWS];
 #pragma unroll
@@ -251,19 +250,16 @@ __device__ __forceinline__ void output_rows_color(const T *__restrict__ I, int64
         for (int i = 0; i < ROWS; ++i) {
             if (i < nrows) {
                 const T *base = I + (int64_t)j * Ips + (int64_t)(yb + i) * Irs;
-                ld_row<T, PX>(iv[j][i], base + x0, full, inpx && pair_aligned(base), g.W - x0);
+                ld_row<T, PX>(iv[j][i], base + x0, full, g.W - x0);
             } else {
                 iv[j][i].zero();
             }
         }
     }
     auto store_q0 = [&](T *plane, int y, const float *v) {
-        T *base = plane + (int64_t)y * Qrs, *row = base + x0;
+        T *row = plane + (int64_t)y * Qrs + x0;
         if (full) {
             stv<PX>(row, v);
-        } else if (inpx && pair_aligned(base)) {
-            st2(row, v[0], v[1]);
-            st2(row + 2, v[2], v[3]);
         } else {
 #pragma unroll
             for (int j = 0; j < PX; ++j)
@@ -273,9 +269,8 @@ __device__ __forceinline__ void output_rows_color(const T *__restrict__ I, int64
     // with EPI, e = q + gain (p - q) from channel c's row of p, then the store
     auto store_q = [&](int c, int y, float *v) {
         if constexpr (EPI) {
-            const T *base = P + (int64_t)c * Pps + (int64_t)y * Prs;
             Row pr;
-            ld_row<T, PX>(pr, base + x0, full, inpx && pair_aligned(base), g.W - x0);
+            ld_row<T, PX>(pr, P + (int64_t)c * Pps + (int64_t)y * Prs + x0, full, g.W - x0);
 #pragma unroll
             for (int j = 0; j < PX; ++j) v[j] = lerp(v[j], pr.at(j), gain);
         }

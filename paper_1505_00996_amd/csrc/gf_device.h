@@ -51,6 +51,19 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
+// The same vectors at element alignment, for accesses to rows of I, p and q,
+// whose starts are only element-aligned.  HSA runs gfx950 with unaligned
+// global accesses enabled, so such an access is still one wide instruction
+// at any element-aligned address (at about 80% of the aligned rate when it
+// straddles a 4-byte boundary, against a quarter or less for element-wise
+// accesses).
+typedef float f32x4e __attribute__((ext_vector_type(4), aligned(4)));
+typedef _Float16 f16x4e __attribute__((ext_vector_type(4), aligned(2)));
+typedef unsigned short u16x4e __attribute__((ext_vector_type(4), aligned(2)));
+typedef float f32x2e __attribute__((ext_vector_type(2), aligned(4)));
+typedef _Float16 f16x2e __attribute__((ext_vector_type(2), aligned(2)));
+typedef unsigned short u16x2e __attribute__((ext_vector_type(2), aligned(2)));
+
 struct bf16 {
     unsigned short bits;
 };
@@ -82,55 +95,45 @@ template <> __device__ __forceinline__ bf16 from_f32<bf16>(float v) { return bf1
 
 template <typename T> __device__ __forceinline__ float ld(const T *p) { return to_f32(*p); }
 
-// Four consecutive elements, 16 bytes (fp32) or 8 bytes (16-bit), aligned.
-__device__ __forceinline__ f32x4 ld4(const float *p) { return *(const f32x4 *)p; }
+// Four consecutive elements, 16 bytes (fp32) or 8 bytes (16-bit), in one
+// access at any element-aligned address.
+__device__ __forceinline__ f32x4 ld4(const float *p) { return *(const f32x4e *)p; }
 __device__ __forceinline__ f32x4 ld4(const _Float16 *p) {
-    f16x4 h = *(const f16x4 *)p;
+    f16x4 h = *(const f16x4e *)p;
     return f32x4{(float)h.x, (float)h.y, (float)h.z, (float)h.w};
 }
 __device__ __forceinline__ f32x4 ld4(const bf16 *p) {
-    u16x4 b = *(const u16x4 *)p;
+    u16x4 b = *(const u16x4e *)p;
     return f32x4{__uint_as_float((unsigned)b.x << 16), __uint_as_float((unsigned)b.y << 16),
                  __uint_as_float((unsigned)b.z << 16), __uint_as_float((unsigned)b.w << 16)};
 }
 
-// Streaming (non-temporal) stores of four outputs.
-__device__ __forceinline__ void st4(float *p, f32x4 v) { __builtin_nontemporal_store(v, (f32x4 *)p); }
+// Streaming (non-temporal) stores of four outputs, one access at any
+// element-aligned address.
+__device__ __forceinline__ void st4(float *p, f32x4 v) {
+    __builtin_nontemporal_store((f32x4e)v, (f32x4e *)p);
+}
 __device__ __forceinline__ void st4(_Float16 *p, f32x4 v) {
-    f16x4 h = {from_f32<_Float16>(v.x), from_f32<_Float16>(v.y), from_f32<_Float16>(v.z),
-               from_f32<_Float16>(v.w)};
-    __builtin_nontemporal_store(h, (f16x4 *)p);
+    f16x4e h = {from_f32<_Float16>(v.x), from_f32<_Float16>(v.y), from_f32<_Float16>(v.z),
+                from_f32<_Float16>(v.w)};
+    __builtin_nontemporal_store(h, (f16x4e *)p);
 }
 __device__ __forceinline__ void st4(bf16 *p, f32x4 v) {
-    u16x4 b = {f32_to_bf16_bits(v.x), f32_to_bf16_bits(v.y), f32_to_bf16_bits(v.z),
-               f32_to_bf16_bits(v.w)};
-    __builtin_nontemporal_store(b, (u16x4 *)p);
+    u16x4e b = {f32_to_bf16_bits(v.x), f32_to_bf16_bits(v.y), f32_to_bf16_bits(v.z),
+                f32_to_bf16_bits(v.w)};
+    __builtin_nontemporal_store(b, (u16x4e *)p);
 }
 template <typename T> __device__ __forceinline__ void st1(T *p, float v) { *p = from_f32<T>(v); }
 
-// Two consecutive elements, aligned to twice the element size (rows whose
-// start is not aligned for four-wide accesses, when it is for two-wide ones).
-__device__ __forceinline__ f32x2 ld2(const float *p) { return *(const f32x2 *)p; }
+// Two consecutive elements in one access at any element-aligned address.
+__device__ __forceinline__ f32x2 ld2(const float *p) { return *(const f32x2e *)p; }
 __device__ __forceinline__ f32x2 ld2(const _Float16 *p) {
-    f16x2 h = *(const f16x2 *)p;
+    f16x2 h = *(const f16x2e *)p;
     return f32x2{(float)h.x, (float)h.y};
 }
 __device__ __forceinline__ f32x2 ld2(const bf16 *p) {
-    u16x2 b = *(const u16x2 *)p;
+    u16x2 b = *(const u16x2e *)p;
     return f32x2{__uint_as_float((unsigned)b.x << 16), __uint_as_float((unsigned)b.y << 16)};
-}
-__device__ __forceinline__ void st2(float *p, float a, float b) {
-    __builtin_nontemporal_store(f32x2{a, b}, (f32x2 *)p);
-}
-__device__ __forceinline__ void st2(_Float16 *p, float a, float b) {
-    __builtin_nontemporal_store(f16x2{from_f32<_Float16>(a), from_f32<_Float16>(b)}, (f16x2 *)p);
-}
-__device__ __forceinline__ void st2(bf16 *p, float a, float b) {
-    __builtin_nontemporal_store(u16x2{f32_to_bf16_bits(a), f32_to_bf16_bits(b)}, (u16x2 *)p);
-}
-// a row start that allows two-wide accesses
-template <typename T> __device__ __forceinline__ bool pair_aligned(const T *row) {
-    return ((uintptr_t)row & (2 * sizeof(T) - 1)) == 0;
 }
 
 // Four samples held in their storage width (half the registers for 16-bit
@@ -139,12 +142,9 @@ template <typename T> struct Raw4;
 template <> struct Raw4<float> { typedef f32x4 type; };
 template <> struct Raw4<_Float16> { typedef f16x4 type; };
 template <> struct Raw4<bf16> { typedef u16x4 type; };
-__device__ __forceinline__ f32x4 ldraw4(const float *p) { return *(const f32x4 *)p; }
-__device__ __forceinline__ f16x4 ldraw4(const _Float16 *p) { return *(const f16x4 *)p; }
-__device__ __forceinline__ u16x4 ldraw4(const bf16 *p) { return *(const u16x4 *)p; }
-__device__ __forceinline__ f32x2 ldraw2(const float *p) { return *(const f32x2 *)p; }
-__device__ __forceinline__ f16x2 ldraw2(const _Float16 *p) { return *(const f16x2 *)p; }
-__device__ __forceinline__ u16x2 ldraw2(const bf16 *p) { return *(const u16x2 *)p; }
+__device__ __forceinline__ f32x4 ldraw4(const float *p) { return *(const f32x4e *)p; }
+__device__ __forceinline__ f16x4 ldraw4(const _Float16 *p) { return *(const f16x4e *)p; }
+__device__ __forceinline__ u16x4 ldraw4(const bf16 *p) { return *(const u16x4e *)p; }
 __device__ __forceinline__ float raw1(const float *p) { return *p; }
 __device__ __forceinline__ _Float16 raw1(const _Float16 *p) { return *p; }
 __device__ __forceinline__ unsigned short raw1(const bf16 *p) { return p->bits; }
@@ -681,6 +681,7 @@ constexpr float cfrac_u(int x, int s) {
 // access.  16-bit (PX = 8): the 8 stored values kept in their storage width
 // (half the registers) and widened, exactly, when used; one 16-byte access.
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8e __attribute__((ext_vector_type(8), aligned(2)));
 template <typename T, int PX>
 struct PixRow {
     float v[PX];
@@ -704,36 +705,22 @@ __device__ __forceinline__ unsigned short raw16(const _Float16 *p) {
     return __builtin_bit_cast(unsigned short, *p);
 }
 __device__ __forceinline__ unsigned short raw16(const bf16 *p) { return p->bits; }
-// one row of PX consecutive elements at row + x0: 16-byte access (full),
-// 2-wide accesses (pairs), or one element at a time up to n (0 past it)
+// one row of PX consecutive elements at `row`: one wide access (full: all
+// PX lie in the image), or one element at a time up to n (0 past it)
 template <typename T, int PX>
-__device__ __forceinline__ void ld_row(PixRow<T, PX> &r, const T *row, bool full, bool pairs, int n) {
+__device__ __forceinline__ void ld_row(PixRow<T, PX> &r, const T *row, bool full, int n) {
     if constexpr (PX == 4) {
         if (full) {
             const f32x4 a = ld4(row);
 #pragma unroll
             for (int j = 0; j < 4; ++j) r.v[j] = a[j];
-        } else if (pairs) {
-#pragma unroll
-            for (int j = 0; j < 4; j += 2) {
-                const f32x2 t = ld2(row + j);
-                r.v[j] = t.x;
-                r.v[j + 1] = t.y;
-            }
         } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j) r.v[j] = j < n ? ld(row + j) : 0.f;
         }
     } else {
         if (full) {
-            r.b = *(const u16x8 *)row;
-        } else if (pairs) {
-#pragma unroll
-            for (int j = 0; j < 8; j += 2) {
-                const u16x2 t = *(const u16x2 *)(row + j);
-                r.b[j] = t.x;
-                r.b[j + 1] = t.y;
-            }
+            r.b = *(const u16x8e *)row;
         } else {
 #pragma unroll
             for (int j = 0; j < 8; ++j) r.b[j] = j < n ? raw16(row + j) : (unsigned short)0;
@@ -752,7 +739,7 @@ __device__ __forceinline__ void stv(T *p, const float *v) {
             if constexpr (std::is_same<T, bf16>::value) b[j] = f32_to_bf16_bits(v[j]);
             else b[j] = __builtin_bit_cast(unsigned short, from_f32<_Float16>(v[j]));
         }
-        __builtin_nontemporal_store(b, (u16x8 *)p);
+        __builtin_nontemporal_store((u16x8e)b, (u16x8e *)p);
     }
 }
 
@@ -766,7 +753,7 @@ __device__ __forceinline__ void stv(T *p, const float *v) {
 template <typename T, int CC, int S, bool EPI = false, int PX = kOutPx>
 __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs, T *__restrict__ Q,
                                             int64_t Qrs, int64_t Qps, const float *__restrict__ M,
-                                            const Geo &g, int c0, int yb, int xw, bool vec,
+                                            const Geo &g, int c0, int yb, int xw,
                                             const T *__restrict__ P = nullptr, int64_t Prs = 0,
                                             int64_t Pps = 0, float gain = 0.f) {
     static_assert(PX == 4 || PX == 8, "4 or 8 pixels per lane");
@@ -775,16 +762,13 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
     const int x0 = xw + lane * PX;
     const int nrows = min(ROWS, g.H - yb);
     if (x0 >= g.W || nrows <= 0) return;  // no barriers below
-    // Per row: 16-byte accesses when every row allows them (vec: row starts
-    // 16-byte aligned), else two-wide ones on rows whose start is aligned
-    // for them (x0 is a multiple of 4), else one element at a time.
-    const bool inpx = x0 + PX - 1 < g.W;
-    const bool full = vec && inpx;
+    // Per row: one wide access per lane (whatever the row start's
+    // alignment), or one element at a time for the lane at the row's end.
+    const bool full = x0 + PX - 1 < g.W;
 
     typedef PixRow<T, PX> Row;
     auto load_row = [&](const T *plane, int64_t rs, int y, Row &r) {
-        const T *base = plane + (int64_t)y * rs;
-        ld_row<T, PX>(r, base + x0, full, inpx && pair_aligned(base), g.W - x0);
+        ld_row<T, PX>(r, plane + (int64_t)y * rs + x0, full, g.W - x0);
     };
     Row iv[ROWS];
 #pragma unroll
@@ -793,12 +777,9 @@ __device__ __forceinline__ void output_rows(const T *__restrict__ I, int64_t Irs
         else iv[i].zero();
     }
     auto store_q = [&](T *plane, int y, const float *v) {
-        T *base = plane + (int64_t)y * Qrs, *row = base + x0;
+        T *row = plane + (int64_t)y * Qrs + x0;
         if (full) {
             stv<PX>(row, v);
-        } else if (inpx && pair_aligned(base)) {
-#pragma unroll
-            for (int j = 0; j < PX; j += 2) st2(row + j, v[j], v[j + 1]);
         } else {
 #pragma unroll
             for (int j = 0; j < PX; ++j)

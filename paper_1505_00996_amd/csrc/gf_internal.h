@@ -95,15 +95,14 @@ hipError_t launch_coeff_lowres_padded(const float *Il, const float *Pl, float *c
 hipError_t launch_box_padded(const float *src, float *dst, const Geo &g, const TileCfg &t, hipStream_t st,
                              const Stamp &ts);
 hipError_t launch_output(gf_dtype dt, const View &I, const View &Q, const float *mean,
-                         const Geo &g, const TileCfg &t, bool vec, hipStream_t st,
+                         const Geo &g, const TileCfg &t, hipStream_t st,
                          const Stamp &ts = Stamp{}, const Detail &detail = Detail{});
 
 // Colour guide (gf_kernels_color.hip): coefficients a_0..a_2, b per channel
 // (4C planes at coef, layout in gf_color.h), from the images or from the
 // low-res FP32 planes of area subsampling (guide Il: 3 planes; p: Pl + c*lps;
 // p_low: p given at low resolution, joint upsampling); output q (or, with a
-// detail epilogue, e) from the box means of those 4C planes (vec: 4-wide
-// row accesses).
+// detail epilogue, e) from the box means of those 4C planes.
 // color_tile_h: the coefficient tile height used for tiles t at radius R
 // (16 or 8; 0 when even 8 rows do not fit in LDS).
 int color_tile_h(const TileCfg &t, int R);
@@ -111,7 +110,7 @@ hipError_t launch_coeff_color(gf_dtype dt, const View &I, const View &P, float *
                               hipStream_t st, const Stamp &ts = Stamp{}, bool p_low = false);
 hipError_t launch_coeff_color_lowres(const float *Il, const float *Pl, float *coef, const Geo &g, const TileCfg &t,
                                      hipStream_t st, const Stamp &ts = Stamp{});
-hipError_t launch_output_color(gf_dtype dt, const View &I, const View &Q, const float *mean, const Geo &g, bool vec,
+hipError_t launch_output_color(gf_dtype dt, const View &I, const View &Q, const float *mean, const Geo &g,
                                hipStream_t st, const Stamp &ts = Stamp{}, const Detail &detail = Detail{});
 
 }  // namespace gf

@@ -27,14 +27,14 @@ template <typename T, int CC, int S, bool EPI>
 __global__ __launch_bounds__(kThreads) void k_output(const T *__restrict__ I, int64_t Irs,
                                                      T *__restrict__ Q, int64_t Qrs, int64_t Qps,
                                                      const float *__restrict__ M, Geo g, int c0,
-                                                     int ntx, int ntiles, int vec, const T *__restrict__ P,
+                                                     int ntx, int ntiles, const T *__restrict__ P,
                                                      int64_t Prs, int64_t Pps, float gain) {
     constexpr int PX = out_px<T>();
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;
     output_rows<T, CC, S, EPI, PX>(I, Irs, Q, Qrs, Qps, M, g, c0,
                                    (tile / ntx) * (4 * kOutRows) + wave_id() * kOutRows,
-                                   (tile % ntx) * (64 * PX), vec != 0, P, Prs, Pps, gain);
+                                   (tile % ntx) * (64 * PX), P, Prs, Pps, gain);
 }
 
 // Area subsampling (step 1 with the block mean): low-res pixel (ly, lx) of
@@ -45,12 +45,12 @@ __global__ __launch_bounds__(kThreads) void k_output(const T *__restrict__ I, in
 // and are converted as they are.  A workgroup covers
 // 4 low-res rows (one per wave) x 64 columns (one per lane) of plane
 // blockIdx.y.  S: compile-time ratio for full blocks (0: g.s at run time);
-// with vec, every row of a full block is read with 2- or 4-wide loads (the
-// host checked that every row of I and p starts aligned for them).
+// every row of a full block is read with 2- or 4-wide loads (one
+// instruction at any element-aligned address).
 template <typename T, int S>
 __global__ __launch_bounds__(kThreads) void k_area(const T *__restrict__ I, int64_t Irs, int64_t Ips,
                                                    const T *__restrict__ P, int64_t Prs, int64_t Pps, int p_low,
-                                                   float *__restrict__ dst, Geo g, int ntx, int vec) {
+                                                   float *__restrict__ dst, Geo g, int ntx) {
     const int lane = threadIdx.x & 63;
     const int ly = (blockIdx.x / ntx) * 4 + wave_id(), lx = (blockIdx.x % ntx) * 64 + lane;
     if (ly >= g.Hl || lx >= g.Wl) return;  // no barriers in this kernel
@@ -67,8 +67,9 @@ __global__ __launch_bounds__(kThreads) void k_area(const T *__restrict__ I, int6
     double acc = 0.0;
     if (S && ny == S && nx == S) {
         double ra[S > 0 ? S : 1];
-        if (vec) {
-            // all loads first, then the sums (in the same order as below)
+        {
+            // all loads first, then the sums (in the same order as the
+            // ragged-block loop below)
             float v[S > 0 ? S : 1][S > 0 ? S : 1];
 #pragma unroll
             for (int i = 0; i < S; ++i) {
@@ -94,14 +95,6 @@ __global__ __launch_bounds__(kThreads) void k_area(const T *__restrict__ I, int6
 #pragma unroll
                 for (int j = 0; j < S; ++j) ra[i] += (double)v[i][j];
             }
-        } else {
-#pragma unroll
-            for (int i = 0; i < S; ++i) {
-                const T *row = src + (int64_t)(y0 + i) * rs + x0;
-                ra[i] = 0.0;
-#pragma unroll
-                for (int j = 0; j < S; ++j) ra[i] += (double)ld(row + j);
-            }
         }
 #pragma unroll
         for (int i = 0; i < S; ++i) acc += ra[i];
@@ -116,25 +109,15 @@ __global__ __launch_bounds__(kThreads) void k_area(const T *__restrict__ I, int6
     *out = (float)(acc / (double)(ny * nx));
 }
 
-// Rows of a view start on a multiple of n elements (n-wide loads allowed).
-template <typename T>
-bool rows_aligned(const View &v, int n, bool planes) {
-    const int64_t b = (int64_t)(n * sizeof(T));
-    return (uintptr_t)v.data % (uintptr_t)b == 0 && (v.rs * (int64_t)sizeof(T)) % b == 0 &&
-           (!planes || (v.ps * (int64_t)sizeof(T)) % b == 0);
-}
-
 template <typename T>
 hipError_t area_t(const View &I, const View &P, bool p_low, float *dst, const Geo &g, hipStream_t st,
                   const Stamp &ts) {
     const int ntx = (g.Wl + 63) / 64, nty = (g.Hl + 3) / 4;
     const dim3 grid(ntx * nty, g.G + g.C), block(kThreads);
     const T *Ip = (const T *)I.data, *Pp = (const T *)P.data;
-    const int n = g.s == 2 ? 2 : 4;  // load width of the S = 2, 4, 8 kernels
-    const int vec = rows_aligned<T>(I, n, g.G > 1) && (p_low || rows_aligned<T>(P, n, g.C > 1));
 #define GF_AREA(SS)                                                                                  \
     launch_k(k_area<T, SS>, grid, block, 0, st, ts.start, ts.stop, Ip, I.rs, I.ps, Pp, P.rs, P.ps, (int)p_low, dst, \
-             g, ntx, vec)
+             g, ntx)
     switch (g.s) {
         case 2: GF_AREA(2); break;
         case 4: GF_AREA(4); break;
@@ -146,8 +129,7 @@ hipError_t area_t(const View &I, const View &P, bool p_low, float *dst, const Ge
 }
 
 template <typename T, int CC, bool EPI>
-hipError_t output_cc(const View &I, const View &Q, const float *mean, const Geo &g, int c0, bool vec,
-                     hipStream_t st, hipEvent_t e0, hipEvent_t e1, const Detail &dt) {
+hipError_t output_cc(const View &I, const View &Q, const float *mean, const Geo &g, int c0, hipStream_t st, hipEvent_t e0, hipEvent_t e1, const Detail &dt) {
     const int tw = 64 * out_px<T>();
     const int ntx = (g.W + tw - 1) / tw;
     const int nty = (g.H + 4 * kOutRows - 1) / (4 * kOutRows);
@@ -158,7 +140,7 @@ hipError_t output_cc(const View &I, const View &Q, const float *mean, const Geo 
     const dim3 grid(grid8(ntiles)), block(kThreads);
 #define GF_OUT(SS)                                                                                       \
     launch_k(k_output<T, CC, SS, EPI>, grid, block, 0, st, e0, e1, Ip, I.rs, Qp, Q.rs, Q.ps, mean, g, c0, ntx, \
-             ntiles, (int)vec, Pp, dt.p.rs, dt.p.ps, dt.gain)
+             ntiles, Pp, dt.p.rs, dt.p.ps, dt.gain)
     switch (g.s) {
         case 1: GF_OUT(1); break;
         case 2: GF_OUT(2); break;
@@ -171,24 +153,22 @@ hipError_t output_cc(const View &I, const View &Q, const float *mean, const Geo 
 }
 
 template <typename T, bool EPI>
-hipError_t output_te(const View &I, const View &Q, const float *mean, const Geo &g, bool vec,
-                     hipStream_t st, const Stamp &ts, const Detail &dt) {
+hipError_t output_te(const View &I, const View &Q, const float *mean, const Geo &g, hipStream_t st, const Stamp &ts, const Detail &dt) {
     for (int c0 = 0; c0 < g.C; c0 += 3) {
         const int cc = g.C - c0 < 3 ? g.C - c0 : 3;
         const hipEvent_t e0 = c0 == 0 ? ts.start : nullptr, e1 = c0 + 3 >= g.C ? ts.stop : nullptr;
-        hipError_t e = cc == 3 ? output_cc<T, 3, EPI>(I, Q, mean, g, c0, vec, st, e0, e1, dt)
-                     : cc == 2 ? output_cc<T, 2, EPI>(I, Q, mean, g, c0, vec, st, e0, e1, dt)
-                               : output_cc<T, 1, EPI>(I, Q, mean, g, c0, vec, st, e0, e1, dt);
+        hipError_t e = cc == 3 ? output_cc<T, 3, EPI>(I, Q, mean, g, c0, st, e0, e1, dt)
+                     : cc == 2 ? output_cc<T, 2, EPI>(I, Q, mean, g, c0, st, e0, e1, dt)
+                               : output_cc<T, 1, EPI>(I, Q, mean, g, c0, st, e0, e1, dt);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 template <typename T>
-hipError_t output_t(const View &I, const View &Q, const float *mean, const Geo &g, bool vec,
-                    hipStream_t st, const Stamp &ts, const Detail &dt) {
-    return dt.p.data ? output_te<T, true>(I, Q, mean, g, vec, st, ts, dt)
-                     : output_te<T, false>(I, Q, mean, g, vec, st, ts, dt);
+hipError_t output_t(const View &I, const View &Q, const float *mean, const Geo &g, hipStream_t st,
+                    const Stamp &ts, const Detail &dt) {
+    return dt.p.data ? output_te<T, true>(I, Q, mean, g, st, ts, dt) : output_te<T, false>(I, Q, mean, g, st, ts, dt);
 }
 
 }  // namespace
@@ -229,11 +209,11 @@ hipError_t launch_box(const float *src, float *dst, const Geo &g, const TileCfg 
 }
 
 hipError_t launch_output(gf_dtype dt, const View &I, const View &Q, const float *mean, const Geo &g,
-                         const TileCfg &, bool vec, hipStream_t st, const Stamp &ts, const Detail &detail) {
+                         const TileCfg &, hipStream_t st, const Stamp &ts, const Detail &detail) {
     switch (dt) {
-        case GF_F32: return output_t<float>(I, Q, mean, g, vec, st, ts, detail);
-        case GF_F16: return output_t<_Float16>(I, Q, mean, g, vec, st, ts, detail);
-        case GF_BF16: return output_t<dev::bf16>(I, Q, mean, g, vec, st, ts, detail);
+        case GF_F32: return output_t<float>(I, Q, mean, g, st, ts, detail);
+        case GF_F16: return output_t<_Float16>(I, Q, mean, g, st, ts, detail);
+        case GF_BF16: return output_t<dev::bf16>(I, Q, mean, g, st, ts, detail);
     }
     return hipErrorInvalidValue;
 }

@@ -27,13 +27,13 @@ template <typename T, int S, bool EPI>
 __global__ __launch_bounds__(kThreads) void k_output_color(const T *__restrict__ I, int64_t Irs, int64_t Ips,
                                                            T *__restrict__ Q, int64_t Qrs, int64_t Qps,
                                                            const float *__restrict__ M, Geo g, int ntx, int ntiles,
-                                                           int vec, const T *__restrict__ P, int64_t Prs,
+                                                           const T *__restrict__ P, int64_t Prs,
                                                            int64_t Pps, float gain) {
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;
     output_rows_color<T, S, EPI>(I, Irs, Ips, Q, Qrs, Qps, M, g,
                                  (tile / ntx) * (4 * kColorRows) + wave_id() * kColorRows, (tile % ntx) * 256,
-                                 vec != 0, P, Prs, Pps, gain);
+                                 P, Prs, Pps, gain);
 }
 
 template <typename T, int K, int KP, int BD>
@@ -76,7 +76,7 @@ hipError_t coeff_color_t(const View &I, const View &P, float *coef, const Geo &g
 }
 
 template <typename T, bool EPI>
-hipError_t output_color_t(const View &I, const View &Q, const float *mean, const Geo &g, bool vec, hipStream_t st,
+hipError_t output_color_t(const View &I, const View &Q, const float *mean, const Geo &g, hipStream_t st,
                           const Stamp &ts, const Detail &dt) {
     const int ntx = (g.W + 255) / 256, nty = (g.H + 4 * kColorRows - 1) / (4 * kColorRows);
     const int ntiles = ntx * nty;
@@ -86,7 +86,7 @@ hipError_t output_color_t(const View &I, const View &Q, const float *mean, const
     const T *Pp = (const T *)dt.p.data;
 #define GF_OC(SS)                                                                                             \
     launch_k(k_output_color<T, SS, EPI>, grid, block, 0, st, ts.start, ts.stop, Ip, I.rs, I.ps, Qp, Q.rs, Q.ps, mean, \
-             g, ntx, ntiles, (int)vec, Pp, dt.p.rs, dt.p.ps, dt.gain)
+             g, ntx, ntiles, Pp, dt.p.rs, dt.p.ps, dt.gain)
     switch (g.s) {
         case 1: GF_OC(1); break;
         case 2: GF_OC(2); break;
@@ -128,18 +128,18 @@ hipError_t launch_coeff_color_lowres(const float *Il, const float *Pl, float *co
 }
 
 template <typename T>
-hipError_t output_color_e(const View &I, const View &Q, const float *mean, const Geo &g, bool vec, hipStream_t st,
+hipError_t output_color_e(const View &I, const View &Q, const float *mean, const Geo &g, hipStream_t st,
                           const Stamp &ts, const Detail &dt) {
-    return dt.p.data ? output_color_t<T, true>(I, Q, mean, g, vec, st, ts, dt)
-                     : output_color_t<T, false>(I, Q, mean, g, vec, st, ts, dt);
+    return dt.p.data ? output_color_t<T, true>(I, Q, mean, g, st, ts, dt)
+                     : output_color_t<T, false>(I, Q, mean, g, st, ts, dt);
 }
 
-hipError_t launch_output_color(gf_dtype dt, const View &I, const View &Q, const float *mean, const Geo &g, bool vec,
+hipError_t launch_output_color(gf_dtype dt, const View &I, const View &Q, const float *mean, const Geo &g,
                                hipStream_t st, const Stamp &ts, const Detail &detail) {
     switch (dt) {
-        case GF_F32: return output_color_e<float>(I, Q, mean, g, vec, st, ts, detail);
-        case GF_F16: return output_color_e<_Float16>(I, Q, mean, g, vec, st, ts, detail);
-        case GF_BF16: return output_color_e<dev::bf16>(I, Q, mean, g, vec, st, ts, detail);
+        case GF_F32: return output_color_e<float>(I, Q, mean, g, st, ts, detail);
+        case GF_F16: return output_color_e<_Float16>(I, Q, mean, g, st, ts, detail);
+        case GF_BF16: return output_color_e<dev::bf16>(I, Q, mean, g, st, ts, detail);
     }
     return hipErrorInvalidValue;
 }
