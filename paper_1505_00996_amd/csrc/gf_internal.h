@@ -104,7 +104,8 @@ hipError_t launch_output(gf_dtype dt, const View &I, const View &Q, const float 
 // p_low: p given at low resolution, joint upsampling); output q (or, with a
 // detail epilogue, e) from the box means of those 4C planes.
 // color_tile_h: the coefficient tile height used for tiles t at radius R
-// (16 or 8; 0 when even 8 rows do not fit in LDS).
+// (16 where it fits unless t pins fewer rows, else 8; 0 when even 8 rows
+// do not fit in LDS).
 int color_tile_h(const TileCfg &t, int R);
 hipError_t launch_coeff_color(gf_dtype dt, const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
                               hipStream_t st, const Stamp &ts = Stamp{}, bool p_low = false);

@@ -16,18 +16,25 @@ pytestmark = pytest.mark.gpu
 gfp = gpuutil.ensure_built()
 
 
-def check(h, w, c, r, s, sub, border, dt, eps=1e-3, seed=0):
+def check(h, w, c, r, s, sub, border, dt, eps=1e-3, seed=0, coeff_th=None):
+    """coeff_th: pin the coefficient tile height (16 rows where they fit by
+    default; 8 when pinned to 8)."""
     import torch
-    print(f"colour case: {h}x{w}x{c} r={r} s={s} {sub} {border} {dt}", flush=True)
+    print(f"colour case: {h}x{w}x{c} r={r} s={s} {sub} {border} {dt} tiles {coeff_th}", flush=True)
     I = synth.colour_guide(h, w, seed=300 + seed + h)
     p = synth.colour_input(I.mean(axis=0, dtype=np.float32), c, seed=400 + seed + w)
     dI, dp = gpuutil.to_device(I, dt), gpuutil.to_device(p, dt)
-    q = gfp.gf_plain(dI, dp, r, eps, border=border) if s == 1 else gfp.gf_fast(dI, dp, r, s, eps, sub, border=border)
+    ctx = gfp.Context(0)
+    if coeff_th is not None:
+        ctx.set_tiles(dI, dp, r, s, eps, dict(coeff_th=coeff_th, box_th=24), sub)
+    q = (gfp.gf_plain(dI, dp, r, eps, border=border, ctx=ctx) if s == 1 else
+         gfp.gf_fast(dI, dp, r, s, eps, sub, border=border, ctx=ctx))
     torch.cuda.synchronize()
     exp = oracle.fast_guided_filter_color(gpuutil.stored_f64(dI), gpuutil.stored_f64(dp), r, s, eps, sub, border)
     got = gpuutil.stored_f64(q)
     assert got.shape == exp.shape
     assert np.all(np.abs(got - exp) <= gpuutil.tolerance(dt, exp)), gpuutil.max_err(got, exp)
+    ctx.close()
     return dI, dp, q
 
 
@@ -52,6 +59,18 @@ CASES = [
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c)))
 def test_color_matches_oracle(case):
     check(*case)
+
+
+@pytest.mark.parametrize("th", [8, 16])
+@pytest.mark.parametrize("case", [(203, 347, 3, 9, 2, "bilinear", "clip", "f32"),
+                                  (150, 151, 2, 16, 1, "nearest", "reflect101", "f32"),
+                                  (300, 400, 3, 16, 4, "area", "clip", "f16"),
+                                  (77, 520, 1, 36, 3, "nearest", "replicate", "f32")],
+                         ids=lambda c: "x".join(map(str, c)))
+def test_color_tile_heights(case, th):
+    """Both coefficient tile heights of the colour guide: 16 rows (the
+    default where they fit) and 8 (pinned), ragged tiles included."""
+    check(*case, coeff_th=th)
 
 
 @pytest.mark.parametrize("eps", [1e-2, 1e-4])
