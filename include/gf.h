@@ -233,8 +233,9 @@ size_t gf_batched_workspace_bytes(int32_t n, const gf_image *I, const gf_image *
  * parameter sets; sizes, c, r, s and eps may differ, the dtype may not) in
  * one batched launch with the context's batch configuration (see
  * gf_batch_cfg; without a context the default).  Each q[k] equals what
- * gf_fast writes for image k with tiles {tile_h, tile_h}.  Descriptor arrays are host memory, read during the
- * call.  workspace: at least gf_batched_workspace_bytes(...) of device memory,
+ * gf_fast writes for image k with the batch's tiles ({tile_h, box tile
+ * height}, see gf_batch_cfg).  Descriptor arrays are host memory, read
+ * during the call.  workspace: at least gf_batched_workspace_bytes(...) of device memory,
  * or NULL for the context's.  Its first two uint32 words are the queue head
  * and an error word: once the launch has completed, a nonzero error word
  * means some tile stopped waiting for the previous phase of its image after
@@ -246,17 +247,19 @@ gf_status gf_fast_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_im
 
 /*
  * Schedules of a batched launch.  Both give every image the bits gf_fast
- * gives it with tiles {tile_h, tile_h}.
+ * gives it with the batch's tiles: {tile_h, 48} under GF_BATCH_PHASES where
+ * 48-row box tiles fit, else {tile_h, tile_h}.
  *   GF_BATCH_PHASES: one grid per phase (coefficient tiles, box-mean tiles,
  *     output blocks) over the tiles of all images: three kernel launches per
  *     batch, each at its own occupancy.
  *   GF_BATCH_QUEUE: one persistent kernel; workgroups take tiles from a
  *     queue ordered phase by phase and wait on per-image phase counters, so
  *     the phases of different images overlap.
- * tile_h: rows of the low-res window-sum tiles: 8, 16, 24, or 32 and 48
+ * tile_h: rows of the low-res coefficient tiles: 8, 16, 24, or 32 and 48
  * with GF_BATCH_PHASES.  A batch takes the tallest height up to tile_h
  * whose tiles fit in LDS at its largest r' (at most 24 under
- * GF_BATCH_QUEUE); 0 means up to 24.
+ * GF_BATCH_QUEUE); 0 means up to 24.  Box-mean tiles take 48 rows under
+ * GF_BATCH_PHASES where they fit, else the same height.
  */
 typedef enum { GF_BATCH_PHASES = 0, GF_BATCH_QUEUE = 1 } gf_batch_schedule;
 

@@ -80,24 +80,35 @@ static const size_t kLdsMax = kLdsLimit;
 
 static bool th_ok(int th) { return th == 8 || th == 16 || th == 24 || th == 32 || th == 48 || th == 64; }
 
-// Tile height: tall tiles amortise the 2r' halo rows, short ones leave room
-// for more workgroups per CU.  The choices follow a sweep of both kernels at
-// r' = 2..32 on a 12 MP image.  At r' <= 4, 24 rows for both (the batched
-// kernels use the same tiles there, so gf_fast and the batch give the same
-// bits).  Coefficients: 32 rows up to r' = 10, then the tallest tile whose
-// region still fits in LDS.  Box means: 48 rows up to r' = 16, then the
-// tallest tile that leaves room for two workgroups per CU.
-static int pick_th(int R, bool coeff) {
-    auto fits = [&](int th, size_t room) {
+// Tile heights: tall tiles amortise the 2r' halo rows, short ones give the
+// grid more workgroups.  The choices follow sweeps of both kernels (r' = 2..32
+// on a 12 MP image; box means also on maps of 128x128 to 1000x750).
+// Coefficients: 24 rows at r' <= 4, 32 up to r' = 10, then the tallest tile
+// whose region still fits in LDS.  Box means at r' <= 4: 48 rows when the
+// box grid keeps at least 1024 workgroups (the 4000x3000 RGB map at s = 4:
+// 15.1 us against 16.0 at 24 rows), else 24 when that gives at least 128, else 8
+// (a 128x128 map: 3.8 us against 4.5 at 24).  Up to r' = 16, 48 rows; then
+// the tallest tile that leaves room for two workgroups per CU.
+static int pick_coeff_th(int R) {
+    auto fits = [&](int th) {
         const TileCfg t{th, th};
-        return coeff ? coeff_staged(t, R) && coeff_lds_bytes(t, R) <= room : box_lds_bytes(t, R) <= room;
+        return coeff_staged(t, R) && coeff_lds_bytes(t, R) <= kLdsMax;
     };
-    if (R <= 4 && fits(24, kLdsMax)) return 24;
-    if (coeff) {
-        if (R <= 10 && fits(32, kLdsMax)) return 32;
-        for (int th : {64, 48, 32, 24, 16})
-            if (fits(th, kLdsMax)) return th;
-        return 8;  // unstaged 8-row tiles
+    if (R <= 4 && fits(24)) return 24;
+    if (R <= 10 && fits(32)) return 32;
+    for (int th : {64, 48, 32, 24, 16})
+        if (fits(th)) return th;
+    return 8;  // unstaged 8-row tiles
+}
+
+static int pick_box_th(const Geo &g) {
+    const int R = g.R;
+    auto fits = [&](int th, size_t room) { return box_lds_bytes(TileCfg{th, th}, R) <= room; };
+    // workgroups of the box grid: tiles of one plane times its 2C planes
+    auto groups = [&](int th) { return (int64_t)((g.Wl + kTileW - 1) / kTileW) * ((g.Hl + th - 1) / th) * 2 * g.C; };
+    if (R <= 4) {
+        if (fits(48, kLdsMax) && groups(48) >= 1024) return 48;
+        return groups(24) >= 128 ? 24 : 8;
     }
     if (R <= 16 && fits(48, kLdsMax)) return 48;
     for (size_t room : {(size_t)80 * 1024, kLdsMax})
@@ -108,8 +119,8 @@ static int pick_th(int R, bool coeff) {
 
 TileCfg default_tiles(const Geo &g) {
     TileCfg t;
-    t.coeff_th = pick_th(g.R, true);
-    t.box_th = pick_th(g.R, false);
+    t.coeff_th = pick_coeff_th(g.R);
+    t.box_th = pick_box_th(g);
     return t;
 }
 

@@ -21,14 +21,22 @@ static size_t round256(size_t v) { return (v + 255) / 256 * 256; }
 // few static words); 0 when none fits (the batch then runs as per-image
 // launches).  The choice depends only on the configuration and the largest
 // radius, so an image gives the same bits alone and in any batch, and the
-// same bits as gf_fast with tiles {th, th}.
+// same bits as gf_fast with tiles {th, thb}.  Box-mean tiles (thb) are 48
+// rows under the phase schedule wherever they fit in LDS (on the 256-image
+// mix the box phase took 446 us at 48 rows against 561 us at 24, while the
+// coefficient phase is fastest at 24), else th.
+static int batch_thb(int sched, int th, int maxR) {
+    if (sched == GF_BATCH_PHASES && box_lds_bytes(TileCfg{th, 48}, maxR) <= kLdsLimit) return 48;
+    return th;
+}
+
 static int batch_th(int sched, int want, int maxR, BatchPlan *plan) {
     // 32 and 48 rows only when asked for, and for the phase schedule only
     // (the queue kernel carries every phase's LDS and registers at once)
     const int cap = std::min(want ? want : 24, sched == GF_BATCH_QUEUE ? 24 : 48);
     for (int th : {48, 32, 24, 16, 8}) {
         if (th > cap) continue;
-        const TileCfg t{th, th};
+        const TileCfg t{th, batch_thb(sched, th, maxR)};
         if (!coeff_staged(t, maxR)) continue;
         const size_t c = coeff_lds_bytes(t, maxR), b = box_lds_bytes(t, maxR);
         if (sched == GF_BATCH_QUEUE) {
@@ -40,14 +48,16 @@ static int batch_th(int sched, int want, int maxR, BatchPlan *plan) {
         }
         plan->lds_coeff = c;
         plan->lds_box = b;
+        plan->thb = t.box_th;
         return th;
     }
     return 0;
 }
 
-int batch_tile_h(const gf_batch_cfg &cfg, int maxR) {
+TileCfg batch_tiles(const gf_batch_cfg &cfg, int maxR) {
     BatchPlan scratch;
-    return batch_th(cfg.schedule, cfg.tile_h, maxR, &scratch);
+    const int th = batch_th(cfg.schedule, cfg.tile_h, maxR, &scratch);
+    return TileCfg{th, th ? scratch.thb : 0};
 }
 
 static bool cfg_ok(const gf_batch_cfg &c) {
@@ -112,13 +122,14 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
         d.Qps = q[i].plane_stride;
         d.g = g;
         d.kind = (g.s == 1 || area_pass(g)) ? 0 : ((g.sub == GF_SUB_NEAREST || (g.s & 1)) ? 1 : 2);
-        const int th = plan->th ? plan->th : 8;
+        const int th = plan->th ? plan->th : 8, thb = plan->th ? plan->thb : 8;
         d.ntx_l = (g.Wl + kTileW - 1) / kTileW;
         d.nty_l = (g.Hl + th - 1) / th;
+        d.nty_b = (g.Hl + thb - 1) / thb;
         d.ntx_o = (g.W + kOutTileW - 1) / kOutTileW;
         d.nty_o = (g.H + 4 * 8 - 1) / (4 * 8);
         d.ntiles[0] = (unsigned)(d.ntx_l * d.nty_l);  // a coefficient task covers every channel
-        d.ntiles[1] = (unsigned)(d.ntx_l * d.nty_l * 2 * g.C);
+        d.ntiles[1] = (unsigned)(d.ntx_l * d.nty_b * 2 * g.C);
         d.ntiles[2] = (unsigned)(d.ntx_o * d.nty_o * ((g.C + 2) / 3));
         // the image's workspace as gf_fast lays it out: a, b planes, their box
         // means right after them (the batched kernels' layout), then any
@@ -170,7 +181,7 @@ static gf_status enqueue_plan(gf_ctx *ctx, const BatchPlan &plan, void *ws, int 
         plan.sched == GF_BATCH_QUEUE
             ? launch_batched(plan.dtype, plan.th, D, plan.n, (unsigned *)base, plan.total, plan.p1, plan.p2,
                              plan.lds, grid, set_lds, st)
-            : launch_phases(plan.dtype, plan.th, D, plan.n, (unsigned *)base, plan.p1, plan.p2, plan.out,
+            : launch_phases(plan.dtype, plan.th, plan.thb, D, plan.n, (unsigned *)base, plan.p1, plan.p2, plan.out,
                             plan.lds_coeff, plan.lds_box, set_lds, st);
     if (e != hipSuccess) return fail(GF_EDEVICE, "batched launch: %s", hipGetErrorString(e));
     return GF_OK;
@@ -309,7 +320,7 @@ gf_status gf_batch_create(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_im
         if (e == hipSuccess)
             e = b->plan.sched == GF_BATCH_QUEUE
                     ? batched_allow_lds(b->plan.dtype, b->plan.th, b->plan.lds)
-                    : phases_allow_lds(b->plan.dtype, b->plan.th, b->plan.lds_coeff, b->plan.lds_box);
+                    : phases_allow_lds(b->plan.dtype, b->plan.th, b->plan.thb, b->plan.lds_coeff, b->plan.lds_box);
         if (e != hipSuccess) {
             delete b;
             return fail(GF_EDEVICE, "descriptor upload: %s", hipGetErrorString(e));

@@ -14,6 +14,7 @@ struct BatchPlan {
     gf_dtype dtype = GF_F32;
     int sched = GF_BATCH_PHASES;
     int th = 0;               // tile height of the window-sum tiles (0: use per-image launches)
+    int thb = 0;              // rows of the box-mean tiles (th, or 48 under the phase schedule)
     size_t lds = 0;           // dynamic LDS of the persistent kernel (queue schedule)
     size_t lds_coeff = 0, lds_box = 0;  // dynamic LDS of the phase kernels
     size_t desc_off = 0;      // byte offset of the descriptor table in the workspace
@@ -33,8 +34,9 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
 gf_batch_cfg ctx_batch_cfg(gf_ctx *ctx);
 bool batch_cfg_ok(const gf_batch_cfg &c);
 
-// Tile height a batch whose largest low-res radius is maxR gets (0: none fits).
-int batch_tile_h(const gf_batch_cfg &cfg, int maxR);
+// Tile heights {coefficients, box means} a batch whose largest low-res
+// radius is maxR gets ({0, 0}: none fits).
+TileCfg batch_tiles(const gf_batch_cfg &cfg, int maxR);
 
 // Upload the descriptor table and enqueue the persistent kernel on st.
 gf_status launch_plan(gf_ctx *ctx, BatchPlan &plan, void *ws, hipStream_t st);

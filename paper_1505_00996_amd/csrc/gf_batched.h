@@ -16,6 +16,7 @@ struct BDesc {
     Geo g;
     int kind;                // subsampling kind (0 identity, 1 nearest, 2 two-tap mean)
     int ntx_l, nty_l;        // low-res tiles: 64 columns x TH rows
+    int nty_b;               // rows of box-mean tiles (64 columns x the plan's box tile height)
     int ntx_o, nty_o;        // output blocks: 256 columns x 32 rows
     unsigned base[3];        // queue index of the image's first task in each phase
     unsigned ntiles[3];      // tasks of each phase: tiles, 2C*tiles, groups*blocks
@@ -54,9 +55,9 @@ hipError_t batched_allow_lds(gf_dtype dt, int th, size_t lds);
 // st (coefficient tiles [0, p1),
 // box tiles [p1, p2), output blocks [p2, total)).  With set_lds the kernels'
 // dynamic-LDS limits are raised first (else phases_allow_lds must have run).
-hipError_t launch_phases(gf_dtype dt, int th, const BDesc *D, int n, unsigned *ctl, unsigned p1, unsigned p2,
+hipError_t launch_phases(gf_dtype dt, int th, int thb, const BDesc *D, int n, unsigned *ctl, unsigned p1, unsigned p2,
                          const OutRanges &out, size_t lds_coeff, size_t lds_box, bool set_lds, hipStream_t st);
-hipError_t phases_allow_lds(gf_dtype dt, int th, size_t lds_coeff, size_t lds_box);
+hipError_t phases_allow_lds(gf_dtype dt, int th, int thb, size_t lds_coeff, size_t lds_box);
 int batched_occupancy(gf_dtype dt, int th, size_t lds);
 
 }  // namespace gf

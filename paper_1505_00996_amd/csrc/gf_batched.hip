@@ -79,7 +79,7 @@ __device__ __forceinline__ void run_coeff(const BDesc &d, unsigned local, void *
 
 template <int TH, bool COH>
 __device__ __forceinline__ void run_box(const BDesc &d, unsigned local, void *lds) {
-    const unsigned per = (unsigned)(d.ntx_l * d.nty_l);
+    const unsigned per = (unsigned)(d.ntx_l * d.nty_b);
     const int m = (int)(local / per), r = (int)(local % per);
     const float *src = d.coef + (int64_t)m * d.g.lps;
     float *dst = d.mean + (int64_t)m * d.g.lps;
@@ -335,16 +335,23 @@ hipError_t allow(Kn k, size_t lds) {
     return hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+// thb: box-mean tile height, TH or 48
 template <typename T, int TH>
-hipError_t phases_t(const BDesc *D, int n, unsigned p1, unsigned p2, const OutRanges &out, size_t lds_coeff,
-                    size_t lds_box, bool set_lds, hipStream_t st) {
+hipError_t phases_t(int thb, const BDesc *D, int n, unsigned p1, unsigned p2, const OutRanges &out,
+                    size_t lds_coeff, size_t lds_box, bool set_lds, hipStream_t st) {
+    if (thb != TH && thb != 48) return hipErrorInvalidValue;
     if (set_lds) {
         (void)allow(k_pcoeff<T, TH>, lds_coeff);
-        (void)allow(k_pbox<TH>, lds_box);
+        (void)(thb == 48 ? allow(k_pbox<48>, lds_box) : allow(k_pbox<TH>, lds_box));
     }
     const dim3 block(kThreads);
     if (p1) hipLaunchKernelGGL((k_pcoeff<T, TH>), dim3(grid8u(p1)), block, lds_coeff, st, D, n, p1);
-    if (p2 > p1) hipLaunchKernelGGL((k_pbox<TH>), dim3(grid8u(p2 - p1)), block, lds_box, st, D, n, p1, p2 - p1);
+    if (p2 > p1) {
+        if (thb == 48)
+            hipLaunchKernelGGL((k_pbox<48>), dim3(grid8u(p2 - p1)), block, lds_box, st, D, n, p1, p2 - p1);
+        else
+            hipLaunchKernelGGL((k_pbox<TH>), dim3(grid8u(p2 - p1)), block, lds_box, st, D, n, p1, p2 - p1);
+    }
     for (int k = 0; k < kRatioClasses; ++k) {
         const unsigned lo = out.lo[k], cnt = out.hi[k] - out.lo[k];
         if (!cnt) continue;
@@ -361,9 +368,10 @@ hipError_t phases_t(const BDesc *D, int n, unsigned p1, unsigned p2, const OutRa
 }
 
 template <typename T, int TH>
-hipError_t phases_allow_t(size_t lds_coeff, size_t lds_box) {
+hipError_t phases_allow_t(int thb, size_t lds_coeff, size_t lds_box) {
     hipError_t e = allow(k_pcoeff<T, TH>, lds_coeff);
-    return e != hipSuccess ? e : allow(k_pbox<TH>, lds_box);
+    if (e != hipSuccess) return e;
+    return thb == 48 ? allow(k_pbox<48>, lds_box) : allow(k_pbox<TH>, lds_box);
 }
 
 // Clears the queue head, the error word and the per-image counters (a kernel
@@ -429,7 +437,7 @@ hipError_t batched_allow_lds(gf_dtype dt, int th, size_t lds) {
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_phases(gf_dtype dt, int th, const BDesc *D, int n, unsigned *ctl, unsigned p1, unsigned p2,
+hipError_t launch_phases(gf_dtype dt, int th, int thb, const BDesc *D, int n, unsigned *ctl, unsigned p1, unsigned p2,
                          const OutRanges &out, size_t lds_coeff, size_t lds_box, bool set_lds, hipStream_t st) {
     // the error word reads 0 after a phase-schedule launch as well
     const int nctl = batch_ctl_words(n);
@@ -438,11 +446,11 @@ hipError_t launch_phases(gf_dtype dt, int th, const BDesc *D, int n, unsigned *c
     if (e != hipSuccess) return e;
 #define GF_P(TT)                                                                                    \
     switch (th) {                                                                                   \
-        case 8: return phases_t<TT, 8>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);         \
-        case 16: return phases_t<TT, 16>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);       \
-        case 24: return phases_t<TT, 24>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);       \
-        case 32: return phases_t<TT, 32>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);       \
-        case 48: return phases_t<TT, 48>(D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);       \
+        case 8: return phases_t<TT, 8>(thb, D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);    \
+        case 16: return phases_t<TT, 16>(thb, D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);  \
+        case 24: return phases_t<TT, 24>(thb, D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);  \
+        case 32: return phases_t<TT, 32>(thb, D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);  \
+        case 48: return phases_t<TT, 48>(thb, D, n, p1, p2, out, lds_coeff, lds_box, set_lds, st);  \
     }                                                                                               \
     return hipErrorInvalidValue
     switch (dt) {
@@ -454,14 +462,14 @@ hipError_t launch_phases(gf_dtype dt, int th, const BDesc *D, int n, unsigned *c
     return hipErrorInvalidValue;
 }
 
-hipError_t phases_allow_lds(gf_dtype dt, int th, size_t lds_coeff, size_t lds_box) {
+hipError_t phases_allow_lds(gf_dtype dt, int th, int thb, size_t lds_coeff, size_t lds_box) {
 #define GF_PA(TT)                                                    \
     switch (th) {                                                    \
-        case 8: return phases_allow_t<TT, 8>(lds_coeff, lds_box);    \
-        case 16: return phases_allow_t<TT, 16>(lds_coeff, lds_box);  \
-        case 24: return phases_allow_t<TT, 24>(lds_coeff, lds_box);  \
-        case 32: return phases_allow_t<TT, 32>(lds_coeff, lds_box);  \
-        case 48: return phases_allow_t<TT, 48>(lds_coeff, lds_box);  \
+        case 8: return phases_allow_t<TT, 8>(thb, lds_coeff, lds_box);    \
+        case 16: return phases_allow_t<TT, 16>(thb, lds_coeff, lds_box);  \
+        case 24: return phases_allow_t<TT, 24>(thb, lds_coeff, lds_box);  \
+        case 32: return phases_allow_t<TT, 32>(thb, lds_coeff, lds_box);  \
+        case 48: return phases_allow_t<TT, 48>(thb, lds_coeff, lds_box);  \
     }                                                                \
     return hipErrorInvalidValue
     switch (dt) {

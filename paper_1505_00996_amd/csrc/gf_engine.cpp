@@ -218,8 +218,8 @@ class Engine {
 
     // Admit queued requests (arrival order) into one batch while the batch's
     // workspace fits in a free arena range, and launch it.  A batch holds
-    // only requests that get the same tile height on their own, so the
-    // batch's tile height is theirs and every result has the bits of the
+    // only requests that get the same tile heights on their own, so the
+    // batch's tile heights are theirs and every result has the bits of the
     // request run alone, whatever it was batched with.
     void admit() {
         while (!queue_.empty() && !free_slots_.empty()) {
@@ -232,8 +232,10 @@ class Engine {
             int th = -1;
             for (uint64_t tk : queue_) {
                 const Request &r = reqs_.at(tk);
-                // a request for the per-image kernels goes alone (tile height "-2")
-                const int rth = r.solo ? -2 : batch_tile_h(cfg, r.R);
+                // a request for the per-image kernels goes alone (key -2); the
+                // others join requests that get the same tile heights alone
+                const TileCfg bt = batch_tiles(cfg, r.R);
+                const int rth = r.solo ? -2 : bt.coeff_th * 256 + bt.box_th;
                 if (th == -2 || (rth == -2 && th != -1)) break;
                 if (th < 0) th = rth;
                 // the batch's own workspace grows by this request's planes and descriptor

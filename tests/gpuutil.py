@@ -39,6 +39,12 @@ def stored_f64(t) -> np.ndarray:
     return t.detach().to("cpu").to(torch.float64).numpy()
 
 
+def batch_tiles(schedule: str, th: int) -> dict:
+    """Tile shapes a batch with tile height th runs (radii small enough for
+    48-row box tiles): box means take 48 rows under the phase schedule."""
+    return dict(coeff_th=th, box_th=48 if schedule == "phases" else th)
+
+
 def max_err(got: np.ndarray, exp: np.ndarray):
     d = np.abs(np.asarray(got, dtype=np.float64) - np.asarray(exp, dtype=np.float64))
     i = int(np.argmax(d))

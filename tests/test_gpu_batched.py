@@ -46,7 +46,7 @@ def test_mixed_batch_matches_oracle_and_solo(dtype, schedule, th):
         tol = gpuutil.tolerance(dtype, exp)
         assert np.all(np.abs(got - exp) <= tol), (k, MIX[k], gpuutil.max_err(got, exp))
         # the same image alone, with the tile shapes the batched kernel uses
-        ctx.set_tiles(dI, dp, r, s, 1e-3, dict(coeff_th=th, box_th=th), sub)
+        ctx.set_tiles(dI, dp, r, s, 1e-3, gpuutil.batch_tiles(schedule, th), sub)
         solo = gfp.gf_fast(dI, dp, r, s, 1e-3, sub, ctx=ctx)
         torch.cuda.synchronize()
         assert torch.equal(solo, q), (k, MIX[k], float((solo.float() - q.float()).abs().max()))
@@ -113,7 +113,7 @@ def test_batch_tuner_picks_a_measured_configuration():
     qs = gfp.gf_fast_batched(Is, ps, prs, ctx=ctx)
     torch.cuda.synchronize()
     for (h, w, c, r, s, sub), dI, dp, q in zip(MIX, Is, ps, qs):
-        ctx.set_tiles(dI, dp, r, s, 1e-3, dict(coeff_th=best["tile_h"], box_th=best["tile_h"]), sub)
+        ctx.set_tiles(dI, dp, r, s, 1e-3, gpuutil.batch_tiles(best["schedule"], best["tile_h"]), sub)
         solo = gfp.gf_fast(dI, dp, r, s, 1e-3, sub, ctx=ctx)
         torch.cuda.synchronize()
         assert torch.equal(solo, q), (h, w, c, r, s, sub, best)

@@ -160,7 +160,7 @@ def batch_vs_solo(specs, dtype, schedule, th=16):
     torch.cuda.synchronize()
     for k, (h, w, c, r, s, sub, border) in enumerate(specs):
         if th:
-            ctx.set_tiles(Is[k], ps[k], r, s, 1e-3, dict(coeff_th=th, box_th=th), sub)
+            ctx.set_tiles(Is[k], ps[k], r, s, 1e-3, gpuutil.batch_tiles(schedule, th), sub)
         solo = gfp.gf_fast(Is[k], ps[k], r, s, 1e-3, sub, ctx=ctx, border=border)
         torch.cuda.synchronize()
         assert torch.equal(qs[k], solo), (k, specs[k])
@@ -205,7 +205,12 @@ def test_served_border_and_area():
         for t in tickets:
             st, _ = ctx.gf_poll(t, 10000)
             assert st == gfp.GF_OK
+        # the batched requests against gf_fast with the batched kernels'
+        # tiles; the area ones ran the per-image kernels with their own
+        pin = gfp.Context(0)
+        pin.set_tiles(dI, dp, 12, 4, 1e-3, gpuutil.batch_tiles("phases", 24))
         for q, (sub, border) in zip(qs, kinds):
-            solo = gfp.gf_fast(dI, dp, 12, 4, 1e-3, sub, border=border)
+            solo = gfp.gf_fast(dI, dp, 12, 4, 1e-3, sub, border=border, ctx=None if sub == "area" else pin)
             torch.cuda.synchronize()
             assert torch.equal(q, solo), (sub, border)
+        pin.close()

@@ -167,7 +167,8 @@ def test_color_tuner_refused():
 
 def test_color_served_like_solo():
     """gf_submit admits a colour-guided request alone (per-image kernels):
-    the result equals gf_fast, also with gray requests queued around it."""
+    the result equals gf_fast, also with gray requests queued around it
+    (those equal gf_fast with the batched kernels' tiles)."""
     import torch
     Ic = gpuutil.to_device(synth.colour_guide(180, 240, seed=61))
     Ig = gpuutil.to_device(synth.photo_guide(180, 240, seed=62))
@@ -179,7 +180,10 @@ def test_color_served_like_solo():
         for t in tickets:
             st, _ = ctx.gf_poll(t, 10000)
             assert st == gfp.GF_OK
+        pin = gfp.Context(0)
+        pin.set_tiles(Ig, p, 8, 4, 1e-2, gpuutil.batch_tiles("phases", 24))
         for I, q in zip(guides, qs):
-            solo = gfp.gf_fast(I, p, 8, 4, 1e-2)
+            solo = gfp.gf_fast(I, p, 8, 4, 1e-2, ctx=pin if I is Ig else None)
             torch.cuda.synchronize()
             assert torch.equal(q, solo)
+        pin.close()

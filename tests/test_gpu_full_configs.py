@@ -4,7 +4,8 @@ oracle (GPU, through the C ABI):
 
 * the 256-image batch (H up to 1536, W up to 2048, either orientation,
   s in {2, 4, 8}, C in {1, 3}, r = round(0.01 max(H, W)), fp16) under both
-  schedules at 24-row tiles, the shape the batch autotuner picks;
+  schedules at 24-row coefficient tiles, the height the batch autotuner
+  picks;
 * requests of 0.25-24 MP (log-uniform area, C in {1, 3}, s = 4, fp16)
   through gf_submit / gf_poll with the benchmark's 4 GiB arena, plus one
   request at the 24 MP maximum.
@@ -32,11 +33,14 @@ def noise_images(torch, specs, seed):
     return Is, ps
 
 
-def check_all(specs, Is, ps, qs):
-    for k, (sp, dI, dp, q) in enumerate(zip(specs, Is, ps, qs)):
+def check_all(specs, Is, ps, *q_lists):
+    """Every output of every image of each list of results (one per run)."""
+    for k, (sp, dI, dp) in enumerate(zip(specs, Is, ps)):
         exp = oracle.fast_guided_filter(gpuutil.stored_f64(dI), gpuutil.stored_f64(dp), sp.r, sp.s, sp.eps)
-        got = gpuutil.stored_f64(q)
-        assert np.all(np.abs(got - exp) <= gpuutil.tolerance("f16", exp)), (k, sp, gpuutil.max_err(got, exp))
+        tol = gpuutil.tolerance("f16", exp)
+        for qs in q_lists:
+            got = gpuutil.stored_f64(qs[k])
+            assert np.all(np.abs(got - exp) <= tol), (k, sp, gpuutil.max_err(got, exp))
         if k % 64 == 63:
             print(f"  {k + 1} of {len(specs)} images checked", flush=True)
 
@@ -55,9 +59,9 @@ def test_full_256_image_batch():
         torch.cuda.synchronize()
         ctx.close()
         print(f"  {schedule}: batch done", flush=True)
-    for k, (a, b) in enumerate(zip(out["phases"], out["queue"])):
-        assert torch.equal(a, b), (k, specs[k])
-    check_all(specs, Is, ps, out["phases"])
+    # the schedules differ in their box-mean tiles (48 rows under phases), so
+    # each is held to the oracle
+    check_all(specs, Is, ps, out["phases"], out["queue"])
 
 
 def test_full_size_requests():
