@@ -82,19 +82,24 @@ static bool th_ok(int th) { return th == 8 || th == 16 || th == 24 || th == 32 |
 
 // Tile heights: tall tiles amortise the 2r' halo rows, short ones give the
 // grid more workgroups.  The choices follow sweeps of both kernels (r' = 2..32
-// on a 12 MP image; box means also on maps of 128x128 to 1000x750).
-// Coefficients: 24 rows at r' <= 4, 32 up to r' = 10, then the tallest tile
-// whose region still fits in LDS.  Box means at r' <= 4: 48 rows when the
-// box grid keeps at least 1024 workgroups (the 4000x3000 RGB map at s = 4:
-// 15.1 us against 16.0 at 24 rows), else 24 when that gives at least 128, else 8
-// (a 128x128 map: 3.8 us against 4.5 at 24).  Up to r' = 16, 48 rows; then
-// the tallest tile that leaves room for two workgroups per CU.
-static int pick_coeff_th(int R) {
+// on a 12 MP image; at r' <= 4 also maps of 128x128 to 1000x750).
+// Coefficients at r' <= 4: 24 rows when that gives at least 192 tiles (the
+// 4000x3000 map at s = 4: 22.2 us against 22.8 at 16 rows), else 16 when
+// that gives at least 128, else 8 (a 128x128 map: 6.5 us against 8.1 at 24
+// rows); up to r' = 10, 32 rows; then the tallest tile whose region still
+// fits in LDS.  Box means at r' <= 4: 48 rows when the box grid keeps at
+// least 1024 workgroups (the 4000x3000 RGB map at s = 4: 15.1 us against 16.0
+// at 24 rows), else 24 when that gives at least 128, else 8 (a 128x128 map:
+// 3.8 us against 4.5 at 24); up to r' = 16, 48 rows; then the tallest tile
+// that leaves room for two workgroups per CU.
+static int pick_coeff_th(const Geo &g) {
+    const int R = g.R;
     auto fits = [&](int th) {
         const TileCfg t{th, th};
         return coeff_staged(t, R) && coeff_lds_bytes(t, R) <= kLdsMax;
     };
-    if (R <= 4 && fits(24)) return 24;
+    auto tiles = [&](int th) { return (int64_t)((g.Wl + kTileW - 1) / kTileW) * ((g.Hl + th - 1) / th); };
+    if (R <= 4 && fits(24)) return tiles(24) >= 192 ? 24 : tiles(16) >= 128 ? 16 : 8;
     if (R <= 10 && fits(32)) return 32;
     for (int th : {64, 48, 32, 24, 16})
         if (fits(th)) return th;
@@ -119,7 +124,7 @@ static int pick_box_th(const Geo &g) {
 
 TileCfg default_tiles(const Geo &g) {
     TileCfg t;
-    t.coeff_th = pick_coeff_th(g.R);
+    t.coeff_th = pick_coeff_th(g);
     t.box_th = pick_box_th(g);
     return t;
 }
