@@ -417,11 +417,12 @@ __device__ __forceinline__ void coeff_from_sums(int n, double Su, double Suu, do
 // KP: how p is sampled -- like I (Algorithm 2), or kSubId when p is given at
 // low resolution already (joint upsampling: its rows are the low-res rows).
 // BD: border class (kClip, kPadded).
+// [cb, ce): the channels of p this tile serves (ce < 0: through C - 1).
 template <typename T, int K, int TH, bool STAGE, bool COH = false, int KP = K, int BD = kClip>
 __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
                                            const T *__restrict__ P, int64_t Prs, int64_t Pps,
                                            float *__restrict__ coef, const Geo &g, int ty0, int tx0,
-                                           void *lds) {
+                                           void *lds, int cb = 0, int ce = -1) {
     constexpr int LC = TH / 4;  // output rows per thread in the column pass
     const int R = g.R, SH = TH + 2 * R, SW = kTileW + 2 * R, SWp = region_stride(R);
     const int plane = SH * kRowW;
@@ -511,7 +512,8 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
         }
     };
 
-    const T *P0 = P;
+    const int cend = ce < 0 ? g.C : ce;
+    const T *P0 = P + (int64_t)cb * Pps;
     const float cP0 = sample<KP>(P0, Prs, ty0, tx0, g);
     auto gV0 = [&](int ry, int rx) { return gsample(KQ{}, P0, Prs, cP0, ry, rx); };
     if (STAGE) {
@@ -546,17 +548,17 @@ __device__ __forceinline__ void coeff_tile(const T *__restrict__ I, int64_t Irs,
     const bool ahead = STAGE && one_fill_batch(SH, SW);
     FillRegs next;
     float cPn = 0.f;
-    for (int c = 0; c < g.C; ++c) {
+    for (int c = cb; c < cend; ++c) {
         const T *Pc = P + (int64_t)c * Pps;
-        const float cP = c ? cPn : cP0;
+        const float cP = c != cb ? cPn : cP0;
         auto gV = [&](int ry, int rx) { return gsample(KQ{}, Pc, Prs, cP, ry, rx); };
         // sV is free: the last row pass that read it ended at a barrier
-        if (STAGE && c) {
+        if (STAGE && c != cb) {
             if (ahead) fill_store(next, sV, SH, SW, SWp);
             else fill_tile(sV, SH, SW, SWp, gV);
         }
         lds_sync();  // sV staged; the previous column pass is done with rA, rB
-        if (c + 1 < g.C) {
+        if (c + 1 < cend) {
             const T *Pn = Pc + Pps;
             cPn = sample<KP>(Pn, Prs, ty0, tx0, g);
             if (ahead) fill_load(next, SH, SW, [&](int ry, int rx) { return gsample(KQ{}, Pn, Prs, cPn, ry, rx); });

@@ -46,6 +46,7 @@ constexpr int kRun = 8;         // consecutive outputs per thread in a row pass
 constexpr int kOutPx = 4;       // full-res pixels per lane in the output kernel
 constexpr int kOutTileW = 64 * kOutPx;  // full-res columns per output tile
 constexpr int kMaxRadius = 64;  // largest low-res radius the LDS tile buffers hold
+constexpr int kCUs = 256;       // compute units of an MI355X (grid-size heuristics)
 
 Geo make_geo(int H, int W, int C, const gf_params &pr, int G = 1);
 // Area subsampling runs as a pass of its own (launch_area) into FP32 planes.

@@ -20,12 +20,14 @@ using namespace dev;
 template <typename T, int K, int KP, int TH, bool STAGE, int BD>
 __global__ __launch_bounds__(kThreads) void k_coeff(const T *__restrict__ I, int64_t Irs,
                                                     const T *__restrict__ P, int64_t Prs, int64_t Pps,
-                                                    float *__restrict__ coef, Geo g, int ntx, int ntiles) {
+                                                    float *__restrict__ coef, Geo g, int ntx, int ntiles, int cpg) {
     extern __shared__ double lds_d[];
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;  // uniform per workgroup: no barrier is skipped by part of it
+    // blockIdx.y: a group of cpg channels of p
+    const int cb = (int)blockIdx.y * cpg;
     coeff_tile<T, K, TH, STAGE, false, KP, BD>(I, Irs, P, Prs, Pps, coef, g, (tile / ntx) * TH,
-                                               (tile % ntx) * kTileW, lds_d);
+                                               (tile % ntx) * kTileW, lds_d, cb, min(g.C, cb + cpg));
 }
 
 template <int TH, int BD>
@@ -65,12 +67,18 @@ hipError_t coeff_tk(const View &I, const View &P, float *coef, const Geo &g, con
     const int ntx = (g.Wl + kTileW - 1) / kTileW, nty = (g.Hl + th - 1) / th;
     const int ntiles = ntx * nty;
     const size_t lds = coeff_lds_bytes(t, g.R);
-    const dim3 grid(grid8(ntiles)), block(kThreads);
+    // With fewer tiles than CUs, one workgroup per tile and channel (each
+    // forms the guide's sums itself; the same bits): the 6000x4000 RGB map at
+    // s = 8 (252 tiles) took 14.8 us against 17.3; with more tiles the extra
+    // guide passes cost more than the shorter chains save (4000x3000 at
+    // s = 4, 512 tiles: 25.1 us against 21.6).
+    const int cpg = ntiles < kCUs ? 1 : g.C;
+    const dim3 grid(grid8(ntiles), (g.C + cpg - 1) / cpg), block(kThreads);
 #define GF_COEFF(TH, STG)                                                                                  \
     {                                                                                                       \
         allow_lds(k_coeff<T, K, KP, TH, STG, BD>, lds);                                                     \
         launch_k(k_coeff<T, K, KP, TH, STG, BD>, grid, block, lds, st, ts.start, ts.stop, Ip, I.rs, Pp, P.rs, \
-                 P.ps, coef, g, ntx, ntiles);                                                               \
+                 P.ps, coef, g, ntx, ntiles, cpg);                                                          \
     }
     if (!staged) {
         GF_COEFF(8, false)  // large r': only the row sums live in LDS
