@@ -476,8 +476,8 @@ def measure_served(gfp, torch, dev, pool=96, seed=7, seconds=2.5):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: every box here has a single MI355X; "
-              "run with --gpus 1 (multi-GPU sharding is described, not built)", file=sys.stderr)
+        print("bench.py measures the path on one GPU only; run it with --gpus 1 "
+              "(sharding over several GPUs is designed, not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
