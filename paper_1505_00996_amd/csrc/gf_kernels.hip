@@ -21,8 +21,8 @@ namespace {
 template <typename T>
 constexpr int out_px() { return sizeof(T) == 2 ? 8 : 4; }
 
-// One workgroup = 4 waves = a (64 PX)-column x 32-row block of q (EPI: of
-// the detail-enhanced e, reading the matching block of p).
+// One workgroup = 4 waves side by side = a (4 x 64 PX)-column x 8-row block
+// of q (EPI: of the detail-enhanced e, reading the matching block of p).
 template <typename T, int CC, int S, bool EPI>
 __global__ __launch_bounds__(kThreads) void k_output(const T *__restrict__ I, int64_t Irs,
                                                      T *__restrict__ Q, int64_t Qrs, int64_t Qps,
@@ -32,9 +32,8 @@ __global__ __launch_bounds__(kThreads) void k_output(const T *__restrict__ I, in
     constexpr int PX = out_px<T>();
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;
-    output_rows<T, CC, S, EPI, PX>(I, Irs, Q, Qrs, Qps, M, g, c0,
-                                   (tile / ntx) * (4 * kOutRows) + wave_id() * kOutRows,
-                                   (tile % ntx) * (64 * PX), P, Prs, Pps, gain);
+    output_rows<T, CC, S, EPI, PX>(I, Irs, Q, Qrs, Qps, M, g, c0, (tile / ntx) * kOutRows,
+                                   ((tile % ntx) * 4 + wave_id()) * (64 * PX), P, Prs, Pps, gain);
 }
 
 // Area subsampling (step 1 with the block mean): low-res pixel (ly, lx) of
@@ -130,9 +129,9 @@ hipError_t area_t(const View &I, const View &P, bool p_low, float *dst, const Ge
 
 template <typename T, int CC, bool EPI>
 hipError_t output_cc(const View &I, const View &Q, const float *mean, const Geo &g, int c0, hipStream_t st, hipEvent_t e0, hipEvent_t e1, const Detail &dt) {
-    const int tw = 64 * out_px<T>();
+    const int tw = 4 * 64 * out_px<T>();
     const int ntx = (g.W + tw - 1) / tw;
-    const int nty = (g.H + 4 * kOutRows - 1) / (4 * kOutRows);
+    const int nty = (g.H + kOutRows - 1) / kOutRows;
     const int ntiles = ntx * nty;
     const T *Ip = (const T *)I.data;
     T *Qp = (T *)Q.data + (int64_t)c0 * Q.ps;
