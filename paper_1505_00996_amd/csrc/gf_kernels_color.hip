@@ -2,7 +2,7 @@
 // guide, and their host launchers:
 //   k_coeff_color  (grid: low-res tiles)            steps 1-4 -> a_0, a_1, a_2, b per channel
 //   k_box          (grid: low-res tiles x 4C maps)  step 5 (the gray path's box tiles)
-//   k_output_color (grid: full-res 256 x 16 blocks) steps 6-7 -> q
+//   k_output_color (grid: full-res 1024 x 4 blocks) steps 6-7 -> q
 // The tile code lives in gf_color.h.
 #include "gf_color.h"
 #include "gf_window_kernels.h"
@@ -21,8 +21,8 @@ __global__ __launch_bounds__(kThreads) void k_coeff_color(const T *__restrict__ 
                                        (tile % ntx) * kTileW, lds_d);
 }
 
-// One workgroup = 4 waves = a 256-column x 16-row block of q (EPI: of the
-// detail-enhanced e, reading the matching block of p).
+// One workgroup = 4 waves side by side = a 1024-column x 4-row block of q
+// (EPI: of the detail-enhanced e, reading the matching block of p).
 template <typename T, int S, bool EPI>
 __global__ __launch_bounds__(kThreads) void k_output_color(const T *__restrict__ I, int64_t Irs, int64_t Ips,
                                                            T *__restrict__ Q, int64_t Qrs, int64_t Qps,
@@ -31,9 +31,8 @@ __global__ __launch_bounds__(kThreads) void k_output_color(const T *__restrict__
                                                            int64_t Pps, float gain) {
     const int tile = xcd_tile(blockIdx.x);
     if (tile >= ntiles) return;
-    output_rows_color<T, S, EPI>(I, Irs, Ips, Q, Qrs, Qps, M, g,
-                                 (tile / ntx) * (4 * kColorRows) + wave_id() * kColorRows, (tile % ntx) * 256,
-                                 P, Prs, Pps, gain);
+    output_rows_color<T, S, EPI>(I, Irs, Ips, Q, Qrs, Qps, M, g, (tile / ntx) * kColorRows,
+                                 ((tile % ntx) * 4 + wave_id()) * 256, P, Prs, Pps, gain);
 }
 
 template <typename T, int K, int KP, int BD>
@@ -78,7 +77,7 @@ hipError_t coeff_color_t(const View &I, const View &P, float *coef, const Geo &g
 template <typename T, bool EPI>
 hipError_t output_color_t(const View &I, const View &Q, const float *mean, const Geo &g, hipStream_t st,
                           const Stamp &ts, const Detail &dt) {
-    const int ntx = (g.W + 255) / 256, nty = (g.H + 4 * kColorRows - 1) / (4 * kColorRows);
+    const int ntx = (g.W + 1023) / 1024, nty = (g.H + kColorRows - 1) / kColorRows;
     const int ntiles = ntx * nty;
     const T *Ip = (const T *)I.data;
     T *Qp = (T *)Q.data;
