@@ -3,10 +3,10 @@
 // launches on the caller's stream:
 //   k_coeff  (grid: low-res tiles)             steps 1-4 -> a, b (all channels)
 //   k_box    (grid: low-res tiles x 2C maps)   step 5    -> mean_a, mean_b
-//   k_output (grid: full-res 256 x 32 blocks)  steps 6-7 -> q
+//   k_output (grid: full-res (4 x 64 PX) x 8 blocks) steps 6-7 -> q
 // Algorithm 1 is the same three launches at s = 1, where subsampling and
 // upsampling are identities.  Area subsampling adds a first launch,
-//   k_area   (grid: low-res 64 x 4 blocks x (G+C) planes)  step 1 -> I', p'
+//   k_area   (grid: low-res 256 x 1 blocks x (G+C) planes)  step 1 -> I', p'
 // after which k_coeff reads the FP32 low-res planes as they are.  The
 // per-tile work lives in gf_device.h; the window-sum kernels and their
 // launchers in gf_window_kernels.h (this file instantiates the
@@ -41,8 +41,8 @@ __global__ __launch_bounds__(kThreads) void k_output(const T *__restrict__ I, in
 // clipped to the image, summed in FP64 row by row and rounded once to FP32.
 // Planes 0..G-1 are the guide's channels (1 gray, 3 colour), planes
 // G..G+C-1 the channels of p; with p_low those are given at low resolution
-// and are converted as they are.  A workgroup covers
-// 4 low-res rows (one per wave) x 64 columns (one per lane) of plane
+// and are converted as they are.  A workgroup covers one low-res row x 256
+// columns (its four waves side by side, one column per lane) of plane
 // blockIdx.y.  S: compile-time ratio for full blocks (0: g.s at run time);
 // every row of a full block is read with 2- or 4-wide loads (one
 // instruction at any element-aligned address).
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kThreads) void k_area(const T *__restrict__ I, int6
                                                    const T *__restrict__ P, int64_t Prs, int64_t Pps, int p_low,
                                                    float *__restrict__ dst, Geo g, int ntx) {
     const int lane = threadIdx.x & 63;
-    const int ly = (blockIdx.x / ntx) * 4 + wave_id(), lx = (blockIdx.x % ntx) * 64 + lane;
+    const int ly = blockIdx.x / ntx, lx = ((blockIdx.x % ntx) * 4 + wave_id()) * 64 + lane;
     if (ly >= g.Hl || lx >= g.Wl) return;  // no barriers in this kernel
     const int k = blockIdx.y;
     float *out = dst + (int64_t)k * g.lps + (int64_t)ly * g.lrs + lx;
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_area(const T *__restrict__ I, int6
 template <typename T>
 hipError_t area_t(const View &I, const View &P, bool p_low, float *dst, const Geo &g, hipStream_t st,
                   const Stamp &ts) {
-    const int ntx = (g.Wl + 63) / 64, nty = (g.Hl + 3) / 4;
+    const int ntx = (g.Wl + 255) / 256, nty = g.Hl;
     const dim3 grid(ntx * nty, g.G + g.C), block(kThreads);
     const T *Ip = (const T *)I.data, *Pp = (const T *)P.data;
 #define GF_AREA(SS)                                                                                  \
