@@ -273,6 +273,20 @@ typedef struct {
  * GF_EINVAL for an unknown schedule or tile height. */
 gf_status gf_ctx_set_batch_cfg(gf_ctx *ctx, const gf_batch_cfg *cfg);
 
+/*
+ * Bound of the waits in GF_BATCH_QUEUE launches made through ctx
+ * (gf_fast_batched, gf_batch_create, gf_submit): a tile polls the counter of
+ * its image's previous phase at most `polls` times (a poll sleeps about 50
+ * ns) before it gives up, sets the batch's error word and skips its work, so
+ * every launch ends even if a dependency never completes.  That image's q is
+ * then incomplete: gf_fast_batched reports it in the workspace's error word,
+ * gf_poll returns GF_EDEVICE for the requests of such a batch.  The default
+ * (polls < 0) is about three seconds; 0 gives up at the first unfinished
+ * dependency.  A prepared batch keeps the limit it was created with.
+ * GF_EINVAL above 2^32 - 1.  The phase schedule has no waits.
+ */
+gf_status gf_ctx_set_wait_limit(gf_ctx *ctx, int64_t polls);
+
 typedef struct {
     gf_batch_cfg cfg;
     double ms; /* mean time of one launch of the whole batch */
@@ -334,6 +348,11 @@ void gf_batch_destroy(gf_batch *batch);
  * Returns GF_OK with *ticket set, GF_ENOMEM if it can never fit the arena,
  * GF_EBUSY if `max_inflight` requests are held, GF_EINVAL for bad arguments.
  * I, p, q must stay valid until gf_poll returns a terminal status.
+ * Ordering: the context's streams do not wait for any stream of the caller.
+ * The work that writes I and p must be complete when gf_submit is called
+ * (for instance, the producing stream synchronised), and q may be read once
+ * gf_poll has returned GF_OK (the library has then seen the batch's
+ * completion event).
  */
 gf_status gf_submit(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
                     const gf_params *params, uint64_t *ticket);

@@ -35,7 +35,7 @@ EXPORTS = ("gf_ctx_create", "gf_ctx_destroy", "gf_last_error", "gf_workspace_byt
            "gf_ctx_profile", "gf_ctx_profile_read", "gf_ctx_set_tiles", "gf_tune",
            "gf_ctx_save_tuning", "gf_ctx_load_tuning", "gf_batch_create", "gf_batch_launch",
            "gf_batch_destroy", "gf_ctx_set_batch_cfg", "gf_tune_batched", "gf_footprint_bytes", "gf_joint_upsample",
-           "gf_detail_enhance", "gf_workspace_bytes_guide")
+           "gf_detail_enhance", "gf_workspace_bytes_guide", "gf_ctx_set_wait_limit")
 KERNELS = ("coeff", "box", "output", "batched", "area")
 
 
@@ -136,6 +136,7 @@ def lib() -> ctypes.CDLL:
             "gf_batch_launch": (ctypes.c_int, [VP, VP]),
             "gf_batch_destroy": (None, [VP]),
             "gf_ctx_set_batch_cfg": (ctypes.c_int, [VP, P(gf_batch_cfg)]),
+            "gf_ctx_set_wait_limit": (ctypes.c_int, [VP, I64]),
             "gf_footprint_bytes": (SZ, [I32, I32, I32, ctypes.c_int, par_p]),
             "gf_tune_batched": (ctypes.c_int, [VP, I32, img_p, img_p, img_p, par_p, VP, SZ, VP, I32,
                                                P(gf_batch_cfg), P(gf_batch_tune_result), I32, P(I32)]),
@@ -217,6 +218,21 @@ def _workspace(nbytes: int, device):
     return ws
 
 
+def _used_on(stream, *tensors):
+    """Tensors allocated here on torch's current stream but written by work
+    enqueued on `stream`: tell torch's caching allocator, so that their
+    blocks are not handed to another allocation before that work is done."""
+    if stream is None:
+        return
+    import torch
+    s = stream if isinstance(stream, torch.cuda.Stream) else torch.cuda.ExternalStream(int(stream))
+    if s.cuda_stream == torch.cuda.current_stream().cuda_stream:
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(s)
+
+
 def _out_like(p, q):
     import torch
     if q is None:
@@ -229,13 +245,16 @@ def gf_fast(I, p, r: int, s: int, eps: float, sub: str = "nearest", q=None, ctx=
     """Algorithm 2 on the GPU: returns q (shape of p).  ``I`` is (H, W), or
     (3, H, W) for a colour guide; ``p`` is (H, W) or (C, H, W); same dtype
     (float32 / float16 / bfloat16)."""
+    own_q = q is None
     q = _out_like(p, q)
     pr = params(r, s, eps, sub, border)
     h, w = I.shape[-2:]
     c = 1 if p.dim() == 2 else p.shape[0]
     need = int(lib().gf_workspace_bytes_guide(h, w, _guide_c(I), c, ctypes.byref(pr)))
-    if workspace is None:
+    own_ws = workspace is None
+    if own_ws:
         workspace = _workspace(need, p.device)
+    _used_on(stream, workspace if own_ws else None, q if own_q else None)
     _check(lib().gf_fast(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p)),
                          ctypes.byref(image(q)), ctypes.byref(pr), ctypes.c_void_p(workspace.data_ptr()),
                          workspace.numel() * workspace.element_size(), _stream(stream)), ctx)
@@ -247,13 +266,16 @@ def gf_joint_upsample(I, p_low, r: int, s: int, eps: float, sub: str = "nearest"
     """Joint upsampling: ``p_low`` (c, ceil(h/s), ceil(w/s)) or 2-D, guided by
     ``I`` (h, w); returns q at full resolution (c, h, w) or (h, w)."""
     h, w = I.shape[-2:]
-    if q is None:
+    own_q = q is None
+    if own_q:
         import torch
         q = torch.empty(p_low.shape[:-2] + (h, w), dtype=p_low.dtype, device=p_low.device)
     pr = params(r, s, eps, sub, border)
     c = 1 if p_low.dim() == 2 else p_low.shape[0]
-    if workspace is None:
+    own_ws = workspace is None
+    if own_ws:
         workspace = _workspace(int(lib().gf_workspace_bytes_guide(h, w, _guide_c(I), c, ctypes.byref(pr))), I.device)
+    _used_on(stream, workspace if own_ws else None, q if own_q else None)
     _check(lib().gf_joint_upsample(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p_low)),
                                    ctypes.byref(image(q)), ctypes.byref(pr), ctypes.c_void_p(workspace.data_ptr()),
                                    workspace.numel() * workspace.element_size(), _stream(stream)), ctx)
@@ -264,12 +286,15 @@ def gf_detail_enhance(I, p, r: int, s: int, eps: float, gain: float, sub: str = 
                       workspace=None, stream=None, border: str = "clip"):
     """Detail enhancement: e = q + gain (p - q) with q the fast filter of p
     (plain at s = 1).  Returns e (shape of p)."""
+    own_e = e is None
     e = _out_like(p, e)
     pr = params(r, s, eps, sub, border)
     h, w = I.shape[-2:]
     c = 1 if p.dim() == 2 else p.shape[0]
-    if workspace is None:
+    own_ws = workspace is None
+    if own_ws:
         workspace = _workspace(int(lib().gf_workspace_bytes_guide(h, w, _guide_c(I), c, ctypes.byref(pr))), p.device)
+    _used_on(stream, workspace if own_ws else None, e if own_e else None)
     _check(lib().gf_detail_enhance(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p)),
                                    ctypes.byref(image(e)), ctypes.byref(pr), float(gain),
                                    ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
@@ -280,13 +305,16 @@ def gf_detail_enhance(I, p, r: int, s: int, eps: float, gain: float, sub: str = 
 def gf_plain(I, p, r: int, eps: float, q=None, ctx=None, workspace=None, stream=None, border: str = "clip"):
     """Algorithm 1 on the GPU (full resolution): returns q (shape of p).
     ``I`` is (H, W), or (3, H, W) for a colour guide."""
+    own_q = q is None
     q = _out_like(p, q)
     pr = params(r, 1, eps, "nearest", border)
     h, w = I.shape[-2:]
     c = 1 if p.dim() == 2 else p.shape[0]
     need = int(lib().gf_workspace_bytes_guide(h, w, _guide_c(I), c, ctypes.byref(pr)))
-    if workspace is None:
+    own_ws = workspace is None
+    if own_ws:
         workspace = _workspace(need, p.device)
+    _used_on(stream, workspace if own_ws else None, q if own_q else None)
     _check(lib().gf_plain(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p)),
                           ctypes.byref(image(q)), int(r), float(eps), pr.border,
                           ctypes.c_void_p(workspace.data_ptr()),
@@ -317,12 +345,15 @@ def batched_workspace_bytes(Is, ps, prs) -> int:
 def gf_fast_batched(Is, ps, prs, qs=None, ctx=None, workspace=None, stream=None):
     """Algorithm 2 for a list of images in one persistent launch.  ``prs`` is
     a list of ``params(r, s, eps, sub)``.  Returns the list of outputs."""
-    if qs is None:
+    own_q = qs is None
+    if own_q:
         qs = [_out_like(p, None) for p in ps]
     n = len(Is)
     aI, ap, aq, apr = _arrays(Is, ps, qs, prs)
-    if workspace is None:
+    own_ws = workspace is None
+    if own_ws:
         workspace = _workspace(lib().gf_batched_workspace_bytes(n, aI, ap, apr), ps[0].device)
+    _used_on(stream, workspace if own_ws else None, *(qs if own_q else ()))
     _check(lib().gf_fast_batched(ctx._h if ctx else None, n, aI, ap, aq, apr,
                                  ctypes.c_void_p(workspace.data_ptr()),
                                  workspace.numel() * workspace.element_size(), _stream(stream)), ctx)
@@ -460,6 +491,11 @@ class Context:
         else:
             c = gf_batch_cfg(SCHEDULES[schedule], int(tile_h))
             _check(lib().gf_ctx_set_batch_cfg(self._h, ctypes.byref(c)), self)
+
+    def set_wait_limit(self, polls: int | None = None):
+        """Polls of the queue schedule's bounded waits before a tile gives up
+        (None: the default of about three seconds)."""
+        _check(lib().gf_ctx_set_wait_limit(self._h, -1 if polls is None else int(polls)), self)
 
     def tune_batched(self, Is, ps, prs, qs=None, workspace=None, reps: int = 3, stream=None):
         """Time every batch schedule and tile height on this batch, keep the

@@ -4,6 +4,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <mutex>
 #include <unordered_map>
 #include <vector>
@@ -23,6 +24,7 @@ struct gf_ctx {
     std::unordered_map<uint64_t, gf::TileCfg> tuned;  // tile shapes picked by gf_tune
     gf::Engine *engine = nullptr;  // request interface (gf_submit / gf_poll)
     gf_batch_cfg batch_cfg{GF_BATCH_PHASES, 0};  // batched launches (gf_ctx_set_batch_cfg / gf_tune_batched)
+    std::atomic<uint32_t> spin_limit{gf::kBatchSpinLimit};  // bounded waits of the queue schedule
     // kernel timing (gf_ctx_profile)
     bool profiling = false;
     struct Mark {

@@ -173,14 +173,14 @@ static int plan_grid(const BatchPlan &plan) {
 }
 
 static gf_status enqueue_plan(gf_ctx *ctx, const BatchPlan &plan, void *ws, int grid, bool set_lds,
-                              hipStream_t st) {
+                              unsigned spin_limit, hipStream_t st) {
     char *base = (char *)ws;
     const BDesc *D = (const BDesc *)(base + plan.desc_off);
     ProfScope ps(ctx, GF_K_BATCHED, st);
     const hipError_t e =
         plan.sched == GF_BATCH_QUEUE
             ? launch_batched(plan.dtype, plan.th, D, plan.n, (unsigned *)base, plan.total, plan.p1, plan.p2,
-                             plan.lds, grid, set_lds, st)
+                             plan.lds, grid, set_lds, spin_limit, st)
             : launch_phases(plan.dtype, plan.th, plan.thb, D, plan.n, (unsigned *)base, plan.p1, plan.p2, plan.out,
                             plan.lds_coeff, plan.lds_box, set_lds, st);
     if (e != hipSuccess) return fail(GF_EDEVICE, "batched launch: %s", hipGetErrorString(e));
@@ -215,7 +215,7 @@ gf_status launch_plan(gf_ctx *ctx, BatchPlan &plan, void *ws, hipStream_t st) {
         if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
     if (e != hipSuccess) return fail(GF_EDEVICE, "descriptor upload: %s", hipGetErrorString(e));
-    return enqueue_plan(ctx, plan, ws, plan_grid(plan), true, st);
+    return enqueue_plan(ctx, plan, ws, plan_grid(plan), true, ctx ? ctx->spin_limit.load() : kBatchSpinLimit, st);
 }
 
 }  // namespace gf
@@ -228,6 +228,7 @@ struct gf_batch {
     BatchPlan plan;
     void *ws = nullptr;
     int grid = 0;
+    unsigned spin_limit = kBatchSpinLimit;  // the context's at creation
     // per-image launches (plan.th == 0): the problems as given
     std::vector<gf_image> I, p, q;
     std::vector<gf_params> pr;
@@ -307,6 +308,7 @@ gf_status gf_batch_create(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_im
     }
     (void)hipGetDevice(&b->device);
     b->ws = ws;
+    if (ctx) b->spin_limit = ctx->spin_limit.load();
     hipStream_t s = (hipStream_t)stream;
     if (b->plan.th == 0) {
         b->I.assign(I, I + n);
@@ -350,10 +352,17 @@ gf_status gf_batch_launch(const gf_batch *b, void *stream) {
         }
         return GF_OK;
     }
-    return enqueue_plan(nullptr, b->plan, b->ws, b->grid, false, s);
+    return enqueue_plan(nullptr, b->plan, b->ws, b->grid, false, b->spin_limit, s);
 }
 
 void gf_batch_destroy(gf_batch *b) { delete b; }
+
+gf_status gf_ctx_set_wait_limit(gf_ctx *ctx, int64_t polls) {
+    if (!ctx) return fail(GF_EINVAL, "ctx is NULL");
+    if (polls > (int64_t)UINT32_MAX) return fail(GF_EINVAL, "wait limit %lld above 2^32 - 1", (long long)polls);
+    ctx->spin_limit = polls < 0 ? kBatchSpinLimit : (uint32_t)polls;
+    return GF_OK;
+}
 
 gf_status gf_ctx_set_batch_cfg(gf_ctx *ctx, const gf_batch_cfg *cfg) {
     if (!ctx) return fail(GF_EINVAL, "ctx is NULL");

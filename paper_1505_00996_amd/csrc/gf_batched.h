@@ -42,13 +42,13 @@ struct OutRanges {
 constexpr int kPatchRows = 18, kPatchCols = 130, kPatchStride = kPatchCols + 1;
 constexpr size_t kOutPatchLds = 2 * kPatchRows * kPatchStride * sizeof(float);
 
-constexpr unsigned kBatchSpinLimit = 1u << 26;  // ~3 s of polling before a wait is declared stuck
-
 // Clears the control words, then launches the persistent kernel.  With
 // set_lds the kernel's dynamic-LDS limit is raised first (otherwise
 // batched_allow_lds must have been called for this dtype, th and size).
+// spin_limit: polls of each bounded wait before the tile gives up.
 hipError_t launch_batched(gf_dtype dt, int th, const BDesc *D, int n, unsigned *ctl, unsigned total,
-                          unsigned p1, unsigned p2, size_t lds, int grid, bool set_lds, hipStream_t st);
+                          unsigned p1, unsigned p2, size_t lds, int grid, bool set_lds, unsigned spin_limit,
+                          hipStream_t st);
 hipError_t batched_allow_lds(gf_dtype dt, int th, size_t lds);
 
 // Phase schedule: clears the control words, then the three phase grids on

@@ -390,10 +390,10 @@ hipError_t allow_t(size_t lds) {
 
 template <typename T, int TH>
 hipError_t launch_t(const BDesc *D, int n, unsigned *ctl, unsigned total, unsigned p1, unsigned p2,
-                    size_t lds, int grid, bool set_lds, hipStream_t st) {
+                    size_t lds, int grid, bool set_lds, unsigned spin_limit, hipStream_t st) {
     if (set_lds) (void)allow_t<T, TH>(lds);
     hipLaunchKernelGGL((k_batched<T, TH>), dim3(grid), dim3(kThreads), lds, st, D, n, ctl, total, p1, p2,
-                       kBatchSpinLimit);
+                       spin_limit);
     return hipGetLastError();
 }
 
@@ -408,15 +408,16 @@ int occupancy_t(size_t lds) {
 }  // namespace
 
 hipError_t launch_batched(gf_dtype dt, int th, const BDesc *D, int n, unsigned *ctl, unsigned total,
-                          unsigned p1, unsigned p2, size_t lds, int grid, bool set_lds, hipStream_t st) {
+                          unsigned p1, unsigned p2, size_t lds, int grid, bool set_lds, unsigned spin_limit,
+                          hipStream_t st) {
     const int nctl = batch_ctl_words(n);
     hipLaunchKernelGGL(k_zero, dim3((nctl + 255) / 256), dim3(256), 0, st, ctl, nctl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-#define GF_B(TT)                                                                           \
-    return th == 8 ? launch_t<TT, 8>(D, n, ctl, total, p1, p2, lds, grid, set_lds, st)     \
-         : th == 16 ? launch_t<TT, 16>(D, n, ctl, total, p1, p2, lds, grid, set_lds, st)   \
-                    : launch_t<TT, 24>(D, n, ctl, total, p1, p2, lds, grid, set_lds, st)
+#define GF_B(TT)                                                                                       \
+    return th == 8 ? launch_t<TT, 8>(D, n, ctl, total, p1, p2, lds, grid, set_lds, spin_limit, st)     \
+         : th == 16 ? launch_t<TT, 16>(D, n, ctl, total, p1, p2, lds, grid, set_lds, spin_limit, st)   \
+                    : launch_t<TT, 24>(D, n, ctl, total, p1, p2, lds, grid, set_lds, spin_limit, st)
     switch (dt) {
         case GF_F32: GF_B(float);
         case GF_F16: GF_B(_Float16);

@@ -47,6 +47,9 @@ constexpr int kOutPx = 4;       // full-res pixels per lane in the output kernel
 constexpr int kOutTileW = 64 * kOutPx;  // full-res columns per output tile
 constexpr int kMaxRadius = 64;  // largest low-res radius the LDS tile buffers hold
 constexpr int kCUs = 256;       // compute units of an MI355X (grid-size heuristics)
+// Polls of the queue schedule's bounded wait before a tile gives up on the
+// previous phase of its image (about three seconds); gf_ctx_set_wait_limit.
+constexpr unsigned kBatchSpinLimit = 1u << 26;
 
 Geo make_geo(int H, int W, int C, const gf_params &pr, int G = 1);
 // Area subsampling runs as a pass of its own (launch_area) into FP32 planes.

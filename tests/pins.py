@@ -432,6 +432,16 @@ def pin_detail_gain_endpoints(orc):
     _close(orc.detail_enhance(c, orc.fast_guided_filter(I, c, 8, 4, 1e-2), 5.0), c, 1e-15, "constant input")
 
 
+def pin_detail_gain5_hand(orc):
+    """The paper's x5 detail on values worked by hand: base q, detail p - q,
+    e = q + 5 (p - q).  (p, q) = (0.75, 0.5) gives 0.5 + 1.25 = 1.75;
+    (0.25, 0.5) gives 0.5 - 1.25 = -0.75; p = q gives q; (0, 0.125) gives
+    0.125 - 0.625 = -0.5.  All dyadic, so the results are exact."""
+    p = np.array([[0.75, 0.25], [0.5, 0.0]])
+    q = np.array([[0.5, 0.5], [0.5, 0.125]])
+    assert np.array_equal(orc.detail_enhance(p, q, 5.0), [[1.75, -0.75], [0.5, -0.5]])
+
+
 # ---------------------------------------------------------------- borders and area subsampling
 
 _NP_PAD = {"replicate": "edge", "reflect101": "reflect"}     # numpy's names for the same extensions

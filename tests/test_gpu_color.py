@@ -2,8 +2,9 @@
 and fast filters against the FP64 oracle, element by element.
 
 Tolerance as for the gray guide: max|q_gpu - q_oracle| <= 1e-5 with FP32
-storage, 2e-3 with 16-bit storage (bf16 outputs with |q| >= 1: half a bf16
-ulp + 1e-4).  The coefficients are solved in FP64 and rounded once to FP32;
+storage; with 16-bit storage 2e-3 (bf16 outputs with |q| >= 1: half a bf16
+ulp + 1e-4) and half an ulp + 1e-5 per element, and the 16-bit q equals the
+FP32 path's q rounded once.  The coefficients are solved in FP64 and rounded once to FP32;
 q = mean_a.I + mean_b is formed in FP32 with one rounding per term."""
 import numpy as np
 import pytest
@@ -34,6 +35,12 @@ def check(h, w, c, r, s, sub, border, dt, eps=1e-3, seed=0, coeff_th=None):
     got = gpuutil.stored_f64(q)
     assert got.shape == exp.shape
     assert np.all(np.abs(got - exp) <= gpuutil.tolerance(dt, exp)), gpuutil.max_err(got, exp)
+    if dt != "f32":  # the 16-bit q is the FP32 path's q rounded once
+        dI32, dp32 = dI.float(), dp.float()
+        q32 = (gfp.gf_plain(dI32, dp32, r, eps, border=border, ctx=ctx) if s == 1 else
+               gfp.gf_fast(dI32, dp32, r, s, eps, sub, border=border, ctx=ctx))
+        torch.cuda.synchronize()
+        gpuutil.split_16bit(q, q32, exp)
     ctx.close()
     return dI, dp, q
 
@@ -135,11 +142,10 @@ def test_color_joint_upsample(s, sub, border, dt):
     assert np.all(np.abs(got - exp) <= gpuutil.tolerance(dt, exp)), gpuutil.max_err(got, exp)
 
 
-@pytest.mark.parametrize("s,dt", [(4, "f32"), (1, "f32"), (8, "bf16")])
+@pytest.mark.parametrize("s,dt", [(4, "f32"), (1, "f32"), (8, "bf16"), (4, "f16")])
 def test_color_detail_enhance(s, dt):
     """e = q + 5 (p - q) with q the colour-guided filter; tolerance as for
-    the gray guide's detail test: |1 - gain| times q's bound plus one rounding
-    of e."""
+    the gray guide's detail test (q kept in FP32, e rounded once)."""
     import torch
     h, w, c, gain = 250, 330, 3, 5.0
     I = synth.colour_guide(h, w, seed=51)
@@ -148,12 +154,10 @@ def test_color_detail_enhance(s, dt):
     e = gfp.gf_detail_enhance(dI, dp, 16, s, 1e-2, gain)
     torch.cuda.synchronize()
     I64, p64 = gpuutil.stored_f64(dI), gpuutil.stored_f64(dp)
-    exp = oracle.detail_enhance(p64, oracle.fast_guided_filter_color(I64, p64, 16, s, 1e-2), gain)
+    q = oracle.fast_guided_filter_color(I64, p64, 16, s, 1e-2)
+    exp = oracle.detail_enhance(p64, q, gain)
     got = gpuutil.stored_f64(e)
-    tq = {"f32": 1e-5, "f16": 2e-3, "bf16": 4e-3}[dt]
-    bits = {"f32": 24, "f16": 11, "bf16": 8}[dt]
-    half_ulp = np.exp2(np.floor(np.log2(np.maximum(np.abs(exp), 1e-30))) - bits)
-    assert np.all(np.abs(got - exp) <= abs(1 - gain) * tq + half_ulp + 1e-7), gpuutil.max_err(got, exp)
+    assert np.all(np.abs(got - exp) <= gpuutil.detail_tolerance(dt, exp, p64, q, gain)), gpuutil.max_err(got, exp)
 
 
 def test_color_tuner_refused():
