@@ -78,6 +78,22 @@ Geo make_geo(int H, int W, int C, const gf_params &pr, int G) {
 
 static const size_t kLdsMax = kLdsLimit;
 
+// Staged coefficient tiles when they fit; otherwise unstaged 8-row tiles.
+bool coeff_staged(const TileCfg &t, int R) { return coeff_tile_lds(t.coeff_th, R, true) <= kLdsLimit; }
+size_t coeff_lds_bytes(const TileCfg &t, int R) {
+    return coeff_staged(t, R) ? coeff_tile_lds(t.coeff_th, R, true) : coeff_tile_lds(8, R, false);
+}
+size_t box_lds_bytes(const TileCfg &t, int R) { return box_tile_lds(t.box_th, R); }
+
+// 16-row tiles where they fit in LDS (6% faster than 8 rows at r' = 4, 38%
+// at r' = 16, although at about 245 VGPRs two waves fit per SIMD against
+// three at 8 rows), 8 rows when the tiles are pinned below 16 or 16 do not
+// fit; 0 when none fits.
+int color_tile_h(const TileCfg &t, int R) {
+    if (t.coeff_th >= 16 && color_tile_lds(16, R) <= kLdsLimit) return 16;
+    return color_tile_lds(8, R) <= kLdsLimit ? 8 : 0;
+}
+
 static bool th_ok(int th) { return th == 8 || th == 16 || th == 24 || th == 32 || th == 48 || th == 64; }
 
 // Tile heights: tall tiles amortise the 2r' halo rows, short ones give the

@@ -134,8 +134,9 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
         // the image's workspace as gf_fast lays it out: a, b planes, their box
         // means right after them (the batched kernels' layout), then any
         // area-subsampled planes
-        d.coef = (float *)(ws_base + off);
-        d.mean = d.coef + (size_t)g.lps * 2 * g.C;
+        // (no addresses when only sizes are asked for: ws_base null)
+        d.coef = ws_base ? (float *)(ws_base + off) : nullptr;
+        d.mean = ws_base ? d.coef + (size_t)g.lps * 2 * g.C : nullptr;
         off += round256(workspace_bytes(g));
         for (int ph = 0; ph < 3; ++ph) {
             d.base[ph] = base[ph];

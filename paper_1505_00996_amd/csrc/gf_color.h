@@ -14,13 +14,6 @@
 namespace gf {
 namespace dev {
 
-// LDS of a colour coefficient tile: two FP64 row-sum planes and four staged
-// FP32 regions (the guide's three channels and one channel of p).
-__host__ __device__ constexpr size_t color_tile_lds(int TH, int R) {
-    return (size_t)2 * (TH + 2 * R) * kRowW * sizeof(double) +
-           (size_t)4 * (TH + 2 * R) * region_stride(R) * sizeof(float);
-}
-
 // x = M^-1 y for the symmetric 3x3 M = [[m00 m01 m02] [m01 m11 m12] [m02 m12 m22]],
 // by its adjugate and determinant (FP64).
 __device__ __forceinline__ void solve3_sym(double m00, double m01, double m02, double m11, double m12,

@@ -281,18 +281,6 @@ __device__ __forceinline__ float sample(const T *__restrict__ img, int64_t rs, i
 // ---------------------------------------------------------------- window sums
 
 constexpr int kFillRows = 8;   // region rows per wave per fill batch
-constexpr int kRowW = 65;      // padded row stride (elements) of the row-sum planes
-
-// LDS bytes of coeff_tile / box_tile for a tile of TH rows at radius R.
-__host__ __device__ constexpr int region_stride(int R) { return (kTileW + 2 * R) | 1; }
-__host__ __device__ constexpr size_t coeff_tile_lds(int TH, int R, bool stage) {
-    return (size_t)2 * (TH + 2 * R) * kRowW * sizeof(double) +
-           (stage ? (size_t)2 * (TH + 2 * R) * region_stride(R) * sizeof(float) : 0);
-}
-__host__ __device__ constexpr size_t box_tile_lds(int TH, int R) {
-    return (size_t)(TH + 2 * R) * kRowW * sizeof(float) +
-           (size_t)(TH + 2 * R) * region_stride(R) * sizeof(float);
-}
 
 // Stage an SH x SW region whose element (ry, rx) is f(ry, rx, c_ry, c_rx):
 // wave w takes rows w, w+4, ...; lanes take columns lane and lane + 64 (and

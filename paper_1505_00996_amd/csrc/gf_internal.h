@@ -55,6 +55,30 @@ Geo make_geo(int H, int W, int C, const gf_params &pr, int G = 1);
 // Area subsampling runs as a pass of its own (launch_area) into FP32 planes.
 inline bool area_pass(const Geo &g) { return g.sub == GF_SUB_AREA && g.s > 1; }
 constexpr size_t kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
+
+// LDS layout of the window-sum tiles (gf_device.h, gf_color.h), needed by
+// the host to pick tile heights: row-sum planes of kRowW elements per row,
+// staged regions of region_stride(R) floats per row (odd, so that lanes on
+// consecutive rows fall in different banks).  constexpr functions serve
+// host and device code alike.
+constexpr int kRowW = 65;
+constexpr int region_stride(int R) { return (kTileW + 2 * R) | 1; }
+// coefficient tile: two FP64 row-sum planes, and with `stage` the guide's
+// and one channel's samples
+constexpr size_t coeff_tile_lds(int TH, int R, bool stage) {
+    return (size_t)2 * (TH + 2 * R) * kRowW * sizeof(double) +
+           (stage ? (size_t)2 * (TH + 2 * R) * region_stride(R) * sizeof(float) : 0);
+}
+// box-mean tile: one FP32 row-sum plane and the staged map region
+constexpr size_t box_tile_lds(int TH, int R) {
+    return (size_t)(TH + 2 * R) * kRowW * sizeof(float) + (size_t)(TH + 2 * R) * region_stride(R) * sizeof(float);
+}
+// colour coefficient tile: two FP64 row-sum planes and four staged regions
+// (the guide's three channels and one channel of p)
+constexpr size_t color_tile_lds(int TH, int R) {
+    return (size_t)2 * (TH + 2 * R) * kRowW * sizeof(double) +
+           (size_t)4 * (TH + 2 * R) * region_stride(R) * sizeof(float);
+}
 bool coeff_staged(const TileCfg &t, int R);
 size_t coeff_lds_bytes(const TileCfg &t, int R);
 size_t box_lds_bytes(const TileCfg &t, int R);

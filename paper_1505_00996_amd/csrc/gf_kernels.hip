@@ -172,13 +172,6 @@ hipError_t output_t(const View &I, const View &Q, const float *mean, const Geo &
 
 }  // namespace
 
-// Staged coefficient tiles when they fit; otherwise unstaged 8-row tiles.
-bool coeff_staged(const TileCfg &t, int R) { return dev::coeff_tile_lds(t.coeff_th, R, true) <= kLdsLimit; }
-size_t coeff_lds_bytes(const TileCfg &t, int R) {
-    return coeff_staged(t, R) ? dev::coeff_tile_lds(t.coeff_th, R, true) : dev::coeff_tile_lds(8, R, false);
-}
-size_t box_lds_bytes(const TileCfg &t, int R) { return dev::box_tile_lds(t.box_th, R); }
-
 hipError_t launch_coeff(gf_dtype dt, const View &I, const View &P, float *coef, const Geo &g,
                         const TileCfg &t, hipStream_t st, const Stamp &ts, bool p_low) {
     if (g.border != GF_BORDER_CLIP) return launch_coeff_padded(dt, I, P, coef, g, t, st, ts, p_low);

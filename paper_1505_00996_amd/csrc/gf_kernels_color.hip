@@ -99,15 +99,6 @@ hipError_t output_color_t(const View &I, const View &Q, const float *mean, const
 
 }  // namespace
 
-// 16-row tiles where they fit in LDS (6% faster than 8 rows at r' = 4, 38%
-// at r' = 16, although at about 245 VGPRs two waves fit per SIMD against
-// three at 8 rows), 8 rows when the tiles are pinned below 16 or 16 do not
-// fit; 0 when none fits.
-int color_tile_h(const TileCfg &t, int R) {
-    if (t.coeff_th >= 16 && dev::color_tile_lds(16, R) <= kLdsLimit) return 16;
-    return dev::color_tile_lds(8, R) <= kLdsLimit ? 8 : 0;
-}
-
 hipError_t launch_coeff_color(gf_dtype dt, const View &I, const View &P, float *coef, const Geo &g, const TileCfg &t,
                               hipStream_t st, const Stamp &ts, bool p_low) {
     const int th = color_tile_h(t, g.R);

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "gf_api_internal.h"
@@ -138,12 +139,16 @@ gf_status gf_ctx_save_tuning(gf_ctx *ctx, const char *path) {
     FILE *f = fopen(path, "w");
     if (!f) return fail(GF_EINVAL, "cannot open %s for writing", path);
     std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    // entries in key order, so the same choices always give the same file
+    std::vector<std::pair<uint64_t, TileCfg>> entries(ctx->tuned.begin(), ctx->tuned.end());
+    std::sort(entries.begin(), entries.end(),
+              [](const std::pair<uint64_t, TileCfg> &a, const std::pair<uint64_t, TileCfg> &b) { return a.first < b.first; });
     fprintf(f, "{\"format\": \"gf-tiles-1\", \"arch\": \"gfx950\", \"entries\": [\n");
     size_t i = 0;
-    for (const auto &kv : ctx->tuned) {
+    for (const auto &kv : entries) {
         const TileCfg &t = kv.second;
         fprintf(f, "{\"key\": %llu, \"coeff_th\": %d, \"box_th\": %d}%s\n",
-                (unsigned long long)kv.first, t.coeff_th, t.box_th, ++i < ctx->tuned.size() ? "," : "");
+                (unsigned long long)kv.first, t.coeff_th, t.box_th, ++i < entries.size() ? "," : "");
     }
     fprintf(f, "]}\n");
     const bool ok = fclose(f) == 0;
