@@ -37,6 +37,8 @@ def check(h, w, c, r, s, sub, border, dt, eps=1e-3, seed=0, coeff_th=None):
     assert np.all(np.abs(got - exp) <= gpuutil.tolerance(dt, exp)), gpuutil.max_err(got, exp)
     if dt != "f32":  # the 16-bit q is the FP32 path's q rounded once
         dI32, dp32 = dI.float(), dp.float()
+        if coeff_th is not None:  # tiles are pinned per storage type: same tiles, same sums
+            ctx.set_tiles(dI32, dp32, r, s, eps, dict(coeff_th=coeff_th, box_th=24), sub)
         q32 = (gfp.gf_plain(dI32, dp32, r, eps, border=border, ctx=ctx) if s == 1 else
                gfp.gf_fast(dI32, dp32, r, s, eps, sub, border=border, ctx=ctx))
         torch.cuda.synchronize()
