@@ -187,6 +187,28 @@ gf_status gf_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q
                   void *hip_stream);
 
 /*
+ * gf_fast for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops and harnesses that forbid hipMalloc.  Same
+ * arguments, shapes, result (bit for bit, with the same tiles) and stream
+ * rules as gf_fast, without a workspace: the low-resolution maps go to a
+ * fixed array of GF_NOALLOC_MAX_BYTES in device memory, one per GPU, held
+ * until the process ends.  A call whose maps need more
+ * (gf_workspace_bytes_guide(...) > GF_NOALLOC_MAX_BYTES) returns GF_ENOMEM
+ * before any HIP call.  The call allocates nothing; the array's device
+ * address is looked up once per device, at gf_ctx_create for the context's
+ * device, else on the first call with that device current (make that first
+ * call, or create the context, outside graph capture).  ctx may be NULL (the
+ * current device, built-in tiles); with a context its device and tuned tiles
+ * are used, but not its profiling.  Every call on one GPU shares that GPU's
+ * array, and nothing in it needs clearing between calls; calls that overlap
+ * on one GPU (on different streams or threads, or replays of graphs that
+ * hold such calls) race on it and must be ordered by the caller.
+ */
+#define GF_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+gf_status gf_fast_noalloc(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q,
+                          const gf_params *params, void *hip_stream);
+
+/*
  * Admission unit of the request interface: the bytes of the context's arena
  * one request of this shape occupies while it is in flight (its low-res maps
  * and its share of the batch's control words and descriptor table).

@@ -35,7 +35,7 @@ EXPORTS = ("gf_ctx_create", "gf_ctx_destroy", "gf_last_error", "gf_workspace_byt
            "gf_ctx_profile", "gf_ctx_profile_read", "gf_ctx_set_tiles", "gf_tune",
            "gf_ctx_save_tuning", "gf_ctx_load_tuning", "gf_batch_create", "gf_batch_launch",
            "gf_batch_destroy", "gf_ctx_set_batch_cfg", "gf_tune_batched", "gf_footprint_bytes", "gf_joint_upsample",
-           "gf_detail_enhance", "gf_workspace_bytes_guide", "gf_ctx_set_wait_limit")
+           "gf_detail_enhance", "gf_workspace_bytes_guide", "gf_ctx_set_wait_limit", "gf_fast_noalloc")
 KERNELS = ("coeff", "box", "output", "batched", "area")
 
 
@@ -119,6 +119,7 @@ def lib() -> ctypes.CDLL:
             "gf_workspace_bytes_guide": (SZ, [I32, I32, I32, I32, par_p]),
             "gf_plain": (ctypes.c_int, [VP, img_p, img_p, img_p, I32, D, ctypes.c_int, VP, SZ, VP]),
             "gf_fast": (ctypes.c_int, [VP, img_p, img_p, img_p, par_p, VP, SZ, VP]),
+            "gf_fast_noalloc": (ctypes.c_int, [VP, img_p, img_p, img_p, par_p, VP]),
             "gf_joint_upsample": (ctypes.c_int, [VP, img_p, img_p, img_p, par_p, VP, SZ, VP]),
             "gf_detail_enhance": (ctypes.c_int, [VP, img_p, img_p, img_p, par_p, D, VP, SZ, VP]),
             "gf_batched_workspace_bytes": (SZ, [I32, img_p, img_p, par_p]),
@@ -258,6 +259,24 @@ def gf_fast(I, p, r: int, s: int, eps: float, sub: str = "nearest", q=None, ctx=
     _check(lib().gf_fast(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p)),
                          ctypes.byref(image(q)), ctypes.byref(pr), ctypes.c_void_p(workspace.data_ptr()),
                          workspace.numel() * workspace.element_size(), _stream(stream)), ctx)
+    return q
+
+
+# Size of the fixed device array gf_fast_noalloc keeps its low-res maps in.
+NOALLOC_MAX_BYTES = 64 << 20
+
+
+def gf_fast_noalloc(I, p, r: int, s: int, eps: float, sub: str = "nearest", q=None, ctx=None, stream=None,
+                    border: str = "clip"):
+    """gf_fast without a workspace: the library keeps the low-res maps in a
+    fixed per-GPU device array (NOALLOC_MAX_BYTES).  With ``q`` given the call
+    allocates nothing; calls that overlap on one GPU race on that array."""
+    own_q = q is None
+    q = _out_like(p, q)
+    _used_on(stream, q if own_q else None)
+    _check(lib().gf_fast_noalloc(ctx._h if ctx else None, ctypes.byref(image(I)), ctypes.byref(image(p)),
+                                 ctypes.byref(image(q)), ctypes.byref(params(r, s, eps, sub, border)),
+                                 _stream(stream)), ctx)
     return q
 
 

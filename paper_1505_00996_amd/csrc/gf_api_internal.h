@@ -79,6 +79,8 @@ bool ctx_tiles(gf_ctx *ctx, const gf_image *I, const gf_image *p, const gf_param
 uint64_t tile_key(gf_dtype dt, int h, int w, int C, int r, int s);
 TileCfg default_tiles(const Geo &g);
 gf_status engine_start(gf_ctx *ctx, size_t arena_bytes, int max_inflight);
+// Looks up the current device's fixed scratch array of gf_fast_noalloc.
+gf_status noalloc_prepare();
 void engine_stop(gf_ctx *ctx);
 
 }  // namespace gf

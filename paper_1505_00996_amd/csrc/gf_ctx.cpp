@@ -104,6 +104,7 @@ gf_status gf_ctx_create(gf_ctx **out, int device, size_t arena_bytes, int max_in
     if (!ctx) return fail(GF_ENOMEM, "out of host memory");
     ctx->device = device;
     gf_status st = ctx_use_device(ctx);
+    if (st == GF_OK) st = noalloc_prepare();
     if (st == GF_OK && arena_bytes > 0) st = engine_start(ctx, arena_bytes, max_inflight ? max_inflight : 64);
     if (st != GF_OK) {
         delete ctx;

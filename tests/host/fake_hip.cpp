@@ -192,5 +192,7 @@ hipError_t phases_allow_lds(gf_dtype, int, int, size_t a, size_t b) {
     return a <= kLdsLimit && b <= kLdsLimit ? hipSuccess : hipErrorInvalidValue;
 }
 int batched_occupancy(gf_dtype, int, size_t) { return 2; }
+// The fixed scratch array of gf_fast_noalloc lives in device code, not built here.
+gf_status noalloc_prepare() { return GF_OK; }
 
 }  // namespace gf

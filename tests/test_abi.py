@@ -233,3 +233,22 @@ def test_joint_upsample_shapes_checked_on_host():
     assert call(img(A_P, 3, 16, 20), pr=bad) == gfp.GF_EINVAL  # s = 0
     # right shapes: validation passes, the tiny workspace is then refused
     assert call(img(A_P, 3, 16, 20)) == gfp.GF_ENOMEM
+
+
+def test_noalloc_host_checks():
+    """gf_fast_noalloc validates like gf_fast and refuses, before any HIP
+    call, a problem whose low-res maps exceed its fixed device array; the
+    binding's size is the header's."""
+    text = open(HEADER).read()
+    m = re.search(r"#define GF_NOALLOC_MAX_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == gfp.NOALLOC_MAX_BYTES
+    I, p, q, pr = good()
+    bad = gfp.params(8, 4, 0.0)
+    assert L.gf_fast_noalloc(None, ctypes.byref(I), ctypes.byref(p), ctypes.byref(q), ctypes.byref(bad),
+                             None) == gfp.GF_EINVAL
+    h, w = 4096, 4096  # 12 FP32 maps of 16 MP at s = 1
+    big = [img(A_I, 1, h, w), img(A_P, 3, h, w), img(A_Q, 3, h, w)]
+    pr1 = gfp.params(8, 1, 1e-3)
+    assert L.gf_workspace_bytes(h, w, 3, ctypes.byref(pr1)) > gfp.NOALLOC_MAX_BYTES
+    assert L.gf_fast_noalloc(None, *[ctypes.byref(x) for x in big], ctypes.byref(pr1), None) == gfp.GF_ENOMEM
+    assert "scratch" in gfp.last_error()
