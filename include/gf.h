@@ -390,6 +390,24 @@ gf_status gf_submit(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image 
 gf_status gf_poll(gf_ctx *ctx, uint64_t ticket, int32_t wait_ms, gf_req_stats *stats);
 
 /*
+ * Fusion of Algorithm 2 step 5 into steps 6-7.  With a gray guide at
+ * s in {2, 4, 8} the box means of a and b can be formed inside the output
+ * pass from a and b (two launches per call instead of three; mean_a and
+ * mean_b never reach device memory) wherever the pass's LDS allows.  The
+ * means are summed in the same order as by the separate box-mean pass with
+ * the same tiles (gf_tiles.box_th), so q is the same, bit for bit, either
+ * way; only the time differs.  GF_FUSE_AUTO (the default) fuses small
+ * one-channel problems (c = 1, low-res maps of at most 65536 pixels), where
+ * the launches are latency-bound; GF_FUSE_ON fuses wherever it applies;
+ * GF_FUSE_OFF never.
+ * The mode covers calls made through ctx (gf_plain, gf_fast,
+ * gf_joint_upsample, gf_detail_enhance, gf_tune); calls without a context,
+ * gf_fast_noalloc included, use GF_FUSE_AUTO.  GF_EINVAL for another mode.
+ */
+typedef enum { GF_FUSE_OFF = 0, GF_FUSE_AUTO = 1, GF_FUSE_ON = 2 } gf_fusion;
+gf_status gf_ctx_set_fusion(gf_ctx *ctx, gf_fusion mode);
+
+/*
  * Kernel timing for measurement.  While enabled on a context, every launch
  * made through it (gf_plain, gf_fast, gf_fast_batched) records a pair of HIP
  * events around each of its kernels on the caller's stream.
@@ -443,7 +461,8 @@ gf_status gf_ctx_set_tiles(gf_ctx *ctx, gf_dtype dtype, int32_t h, int32_t w, in
 
 /*
  * Autotuner: times every candidate shape of the coefficient kernel and of
- * the box-mean kernel on this problem (HIP events on `hip_stream`, `reps`
+ * the box-mean kernel (where the box means are fused, of the fused output
+ * pass, reported as GF_K_OUTPUT) on this problem (HIP events on `hip_stream`, `reps`
  * launches each after one warm-up), keeps the fastest of each for the
  * problem's class on ctx (as gf_ctx_set_tiles would) and returns it in
  * *best (may be NULL).  Synchronises the stream; q's contents are

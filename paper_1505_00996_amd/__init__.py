@@ -35,7 +35,7 @@ EXPORTS = ("gf_ctx_create", "gf_ctx_destroy", "gf_last_error", "gf_workspace_byt
            "gf_ctx_profile", "gf_ctx_profile_read", "gf_ctx_set_tiles", "gf_tune",
            "gf_ctx_save_tuning", "gf_ctx_load_tuning", "gf_batch_create", "gf_batch_launch",
            "gf_batch_destroy", "gf_ctx_set_batch_cfg", "gf_tune_batched", "gf_footprint_bytes", "gf_joint_upsample",
-           "gf_detail_enhance", "gf_workspace_bytes_guide", "gf_ctx_set_wait_limit", "gf_fast_noalloc")
+           "gf_detail_enhance", "gf_workspace_bytes_guide", "gf_ctx_set_wait_limit", "gf_fast_noalloc", "gf_ctx_set_fusion")
 KERNELS = ("coeff", "box", "output", "batched", "area")
 
 
@@ -69,6 +69,9 @@ class gf_tiles(ctypes.Structure):
 class gf_tune_result(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("tiles", gf_tiles), ("ms", ctypes.c_double)]
 
+
+GF_FUSE_OFF, GF_FUSE_AUTO, GF_FUSE_ON = 0, 1, 2
+FUSION = {"off": GF_FUSE_OFF, "auto": GF_FUSE_AUTO, "on": GF_FUSE_ON}
 
 GF_BATCH_PHASES, GF_BATCH_QUEUE = 0, 1
 SCHEDULES = {"phases": GF_BATCH_PHASES, "queue": GF_BATCH_QUEUE}
@@ -138,6 +141,7 @@ def lib() -> ctypes.CDLL:
             "gf_batch_destroy": (None, [VP]),
             "gf_ctx_set_batch_cfg": (ctypes.c_int, [VP, P(gf_batch_cfg)]),
             "gf_ctx_set_wait_limit": (ctypes.c_int, [VP, I64]),
+            "gf_ctx_set_fusion": (ctypes.c_int, [VP, ctypes.c_int]),
             "gf_footprint_bytes": (SZ, [I32, I32, I32, ctypes.c_int, par_p]),
             "gf_tune_batched": (ctypes.c_int, [VP, I32, img_p, img_p, img_p, par_p, VP, SZ, VP, I32,
                                                P(gf_batch_cfg), P(gf_batch_tune_result), I32, P(I32)]),
@@ -501,6 +505,12 @@ class Context:
 
     def load_tuning(self, path: str):
         _check(lib().gf_ctx_load_tuning(self._h, path.encode()), self)
+
+    def set_fusion(self, mode: str = "auto"):
+        """Box means fused into the output pass: "auto" (the default: small
+        problems), "on" (wherever it applies) or "off" (the separate
+        box-mean pass); the same bits either way."""
+        _check(lib().gf_ctx_set_fusion(self._h, FUSION[mode]), self)
 
     def set_batch_cfg(self, schedule: str | None = "phases", tile_h: int = 0):
         """Schedule ("phases" or "queue") and tile height of this context's

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgf.so")
-SOURCES = ["gf_kernels.hip", "gf_kernels_padded.hip", "gf_kernels_color.hip", "gf_batched.hip", "gf_noalloc.hip", "gf_api.cpp", "gf_ctx.cpp", "gf_tune.cpp",
+SOURCES = ["gf_kernels.hip", "gf_kernels_padded.hip", "gf_kernels_color.hip", "gf_kernels_outbox.hip", "gf_batched.hip", "gf_noalloc.hip", "gf_api.cpp", "gf_ctx.cpp", "gf_tune.cpp",
            "gf_batch_host.cpp", "gf_engine.cpp"]
 ARCH = "gfx950"
 

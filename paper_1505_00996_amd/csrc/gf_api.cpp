@@ -138,10 +138,24 @@ static int pick_box_th(const Geo &g) {
     return 8;
 }
 
+int fused_px(const Geo &g, const TileCfg &t, gf_dtype dt) {
+    if (g.G != 1 || !(g.s == 2 || g.s == 4 || g.s == 8) || !th_ok(t.box_th)) return 0;
+    const int LC = t.box_th / 4;
+    // 16-bit rows: eight pixels per lane (16-byte accesses) while the block's
+    // LDS leaves room for four workgroups per CU, else four
+    if (dt != GF_F32 && outbox_lds(g.s, g.R, LC, 8) <= kLdsLimit / 4) return 8;
+    return outbox_lds(g.s, g.R, LC, 4) <= kObLdsMax ? 4 : 0;
+}
+
+bool fuse_pays(const Geo &g) { return g.C == 1 && (int64_t)g.Hl * g.Wl <= kFuseMaxLowres; }
+
 TileCfg default_tiles(const Geo &g) {
     TileCfg t;
     t.coeff_th = pick_coeff_th(g);
-    t.box_th = pick_box_th(g);
+    // box means fused into the output pass: runs of two rows (8-row box
+    // tiles), which compute the fewest rows past a block's patch
+    const TileCfg fused{t.coeff_th, 8};
+    t.box_th = fuse_pays(g) && fused_px(g, fused, GF_F32) ? 8 : pick_box_th(g);
     return t;
 }
 
@@ -267,6 +281,22 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
             e = area_pass(g) ? launch_coeff_lowres(lowres, pl, coef, g, t, st, ps.stamp())
                              : launch_coeff(I->dtype, vI, vP, coef, g, t, st, ps.stamp(), p_low);
         ps.commit(e == hipSuccess);
+    }
+    const int mode = ctx ? ctx->fuse.load() : GF_FUSE_AUTO;
+    const int fpx = !color && (mode == GF_FUSE_ON || (mode == GF_FUSE_AUTO && fuse_pays(g)))
+                        ? fused_px(g, t, I->dtype) : 0;
+    if (e == hipSuccess && fpx) {
+        // box means fused into the output pass
+        ProfScope ps(ctx, GF_K_OUTPUT, st, true);
+        Detail dt;
+        if (gain) {
+            dt.p = vP;
+            dt.gain = *gain;
+        }
+        e = launch_outbox(I->dtype, vI, vQ, coef, g, t, fpx, st, ps.stamp(), dt);
+        ps.commit(e == hipSuccess);
+        if (e != hipSuccess) return fail(GF_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+        return GF_OK;
     }
     if (e == hipSuccess) {
         // the box tiles run over maps = 2 * gb.C planes

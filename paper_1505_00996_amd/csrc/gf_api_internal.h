@@ -25,6 +25,7 @@ struct gf_ctx {
     gf::Engine *engine = nullptr;  // request interface (gf_submit / gf_poll)
     gf_batch_cfg batch_cfg{GF_BATCH_PHASES, 0};  // batched launches (gf_ctx_set_batch_cfg / gf_tune_batched)
     std::atomic<uint32_t> spin_limit{gf::kBatchSpinLimit};  // bounded waits of the queue schedule
+    std::atomic<int> fuse{GF_FUSE_AUTO};  // box means fused into the output pass (gf_ctx_set_fusion)
     // kernel timing (gf_ctx_profile)
     bool profiling = false;
     struct Mark {

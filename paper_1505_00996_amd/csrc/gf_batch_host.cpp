@@ -126,7 +126,8 @@ gf_status plan_batch(int n, const gf_image *I, const gf_image *p, const gf_image
         d.ntx_l = (g.Wl + kTileW - 1) / kTileW;
         d.nty_l = (g.Hl + th - 1) / th;
         d.nty_b = (g.Hl + thb - 1) / thb;
-        d.ntx_o = (g.W + kOutTileW - 1) / kOutTileW;
+        const int ow = 64 * out_px(cfg.schedule, I[0].dtype);
+        d.ntx_o = (g.W + ow - 1) / ow;
         d.nty_o = (g.H + 4 * 8 - 1) / (4 * 8);
         d.ntiles[0] = (unsigned)(d.ntx_l * d.nty_l);  // a coefficient task covers every channel
         d.ntiles[1] = (unsigned)(d.ntx_l * d.nty_b * 2 * g.C);

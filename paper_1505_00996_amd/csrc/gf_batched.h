@@ -17,10 +17,16 @@ struct BDesc {
     int kind;                // subsampling kind (0 identity, 1 nearest, 2 two-tap mean)
     int ntx_l, nty_l;        // low-res tiles: 64 columns x TH rows
     int nty_b;               // rows of box-mean tiles (64 columns x the plan's box tile height)
-    int ntx_o, nty_o;        // output blocks: 256 columns x 32 rows
+    int ntx_o, nty_o;        // output blocks: 64 * out_px(schedule, dtype) columns x 32 rows
     unsigned base[3];        // queue index of the image's first task in each phase
     unsigned ntiles[3];      // tasks of each phase: tiles, 2C*tiles, groups*blocks
 };
+
+// Pixels per lane of the output blocks: the phase schedule's output grids
+// take 16-bit rows eight pixels at a time (one 16-byte access per row, as
+// the per-image kernel does); the queue kernel's output tasks stage a
+// 256-column patch and take four.
+inline int out_px(int schedule, gf_dtype dt) { return schedule == GF_BATCH_PHASES && dt != GF_F32 ? 8 : kOutPx; }
 
 // The control words live at the start of the batch workspace: [0] queue
 // head, [1] error flag, then 2 per image: coefficient tiles done, box tiles

@@ -39,6 +39,19 @@ namespace {
 
 using namespace dev;
 
+// Device pointers read from the descriptor table are generic pointers as far
+// as the compiler knows, and accesses through generic pointers compile to
+// FLAT instructions, which also count against the LDS/scalar wait counter
+// and so serialise with every LDS and scalar access.  The images and planes
+// are global memory: rebuilding the pointer from its address as a global
+// pointer lets the compiler use global loads and stores (a plain cast to the
+// global address space and back is folded away).
+template <typename T>
+__device__ __forceinline__ T *glb(T *p) {
+    typedef __attribute__((address_space(1))) T gT;
+    return (T *)(gT *)(uintptr_t)p;
+}
+
 // Largest d with D[d].base[ph] <= t (images are laid out in queue order).
 __device__ __forceinline__ int find_image(const BDesc *__restrict__ D, int n, int ph, unsigned t) {
     int lo = 0, hi = n - 1;
@@ -55,17 +68,18 @@ __device__ __forceinline__ int find_image(const BDesc *__restrict__ D, int n, in
 // (uniform across the workgroup).
 template <typename T, int TH, bool COH, int BD>
 __device__ __forceinline__ void run_coeff_b(const BDesc &d, int ty0, int tx0, void *lds) {
-    const T *I = (const T *)d.I, *P = (const T *)d.P;
+    const T *I = glb((const T *)d.I), *P = glb((const T *)d.P);
+    float *coef = glb(d.coef);
     switch (d.kind) {
         case kSubId:
-            coeff_tile<T, kSubId, TH, true, COH, kSubId, BD>(I, d.Irs, P, d.Prs, d.Pps, d.coef, d.g, ty0, tx0, lds);
+            coeff_tile<T, kSubId, TH, true, COH, kSubId, BD>(I, d.Irs, P, d.Prs, d.Pps, coef, d.g, ty0, tx0, lds);
             break;
         case kSubNear:
-            coeff_tile<T, kSubNear, TH, true, COH, kSubNear, BD>(I, d.Irs, P, d.Prs, d.Pps, d.coef, d.g, ty0, tx0,
+            coeff_tile<T, kSubNear, TH, true, COH, kSubNear, BD>(I, d.Irs, P, d.Prs, d.Pps, coef, d.g, ty0, tx0,
                                                                  lds);
             break;
         default:
-            coeff_tile<T, kSubLin, TH, true, COH, kSubLin, BD>(I, d.Irs, P, d.Prs, d.Pps, d.coef, d.g, ty0, tx0, lds);
+            coeff_tile<T, kSubLin, TH, true, COH, kSubLin, BD>(I, d.Irs, P, d.Prs, d.Pps, coef, d.g, ty0, tx0, lds);
             break;
     }
 }
@@ -81,8 +95,8 @@ template <int TH, bool COH>
 __device__ __forceinline__ void run_box(const BDesc &d, unsigned local, void *lds) {
     const unsigned per = (unsigned)(d.ntx_l * d.nty_b);
     const int m = (int)(local / per), r = (int)(local % per);
-    const float *src = d.coef + (int64_t)m * d.g.lps;
-    float *dst = d.mean + (int64_t)m * d.g.lps;
+    const float *src = glb(d.coef) + (int64_t)m * d.g.lps;
+    float *dst = glb(d.mean) + (int64_t)m * d.g.lps;
     const int ty0 = (r / d.ntx_l) * TH, tx0 = (r % d.ntx_l) * kTileW;
     if (d.g.border == GF_BORDER_CLIP) box_tile<TH, COH, kClip>(src, dst, d.g, ty0, tx0, lds);
     else box_tile<TH, COH, kPadded>(src, dst, d.g, ty0, tx0, lds);
@@ -106,8 +120,8 @@ __device__ __forceinline__ void run_output(const BDesc &d, unsigned local, float
     const int nrows = max(0, min(kOutRows, g.H - yb));
     const bool act = x0 < g.W && nrows > 0;
     const bool full = x0 + 3 < g.W;  // one wide access per row, else element-wise
-    const T *I = (const T *)d.I;
-    T *Q = (T *)d.Q + (int64_t)c0 * d.Qps;
+    const T *I = glb((const T *)d.I);
+    T *Q = glb((T *)d.Q) + (int64_t)c0 * d.Qps;
 
     typedef typename Raw4<T>::type raw4;
     raw4 iv[kOutRows];
@@ -140,8 +154,8 @@ __device__ __forceinline__ void run_output(const BDesc &d, unsigned local, float
     if (s == 1) {  // uniform over the workgroup: no barriers on this path
         if (!act) return;
         for (int c = 0; c < cc; ++c) {
-            const float *Ma = d.mean + (int64_t)(c0 + c) * g.lps;
-            const float *Mb = d.mean + (int64_t)(g.C + c0 + c) * g.lps;
+            const float *Ma = glb(d.mean) + (int64_t)(c0 + c) * g.lps;
+            const float *Mb = glb(d.mean) + (int64_t)(g.C + c0 + c) * g.lps;
             T *Qc = Q + (int64_t)c * d.Qps;
 #pragma unroll
             for (int i = 0; i < kOutRows; ++i) {
@@ -180,8 +194,8 @@ __device__ __forceinline__ void run_output(const BDesc &d, unsigned local, float
         xb[j] = clampi(l + 1, 0, g.Wl - 1) - px0;
     }
     for (int c = 0; c < cc; ++c) {
-        const float *Ma = d.mean + (int64_t)(c0 + c) * g.lps + (int64_t)py0 * g.lrs + px0;
-        const float *Mb = d.mean + (int64_t)(g.C + c0 + c) * g.lps + (int64_t)py0 * g.lrs + px0;
+        const float *Ma = glb(d.mean) + (int64_t)(c0 + c) * g.lps + (int64_t)py0 * g.lrs + px0;
+        const float *Mb = glb(d.mean) + (int64_t)(g.C + c0 + c) * g.lps + (int64_t)py0 * g.lrs + px0;
         lds_sync();  // the previous channel's patch has been read
         for (int k = threadIdx.x; k < nr * nc; k += kThreads) {
             const int ry = k / nc, rx = k - ry * nc;
@@ -284,11 +298,11 @@ __global__ __launch_bounds__(kThreads) void k_batched(const BDesc *__restrict__ 
 // share its L2.  The kernel boundary orders the phases: plain loads/stores.
 
 // Output block of one image with the per-image kernel's code path (S: the
-// compile-time ratio, 0 = read at run time).
-template <typename T, int CC, int S>
+// compile-time ratio, 0 = read at run time; PX pixels per lane).
+template <typename T, int CC, int S, int PX>
 __device__ __forceinline__ void out_cc(const BDesc &d, int c0, int yb, int xw) {
-    output_rows<T, CC, S>((const T *)d.I, d.Irs, (T *)d.Q + (int64_t)c0 * d.Qps, d.Qrs, d.Qps, d.mean, d.g, c0,
-                          yb, xw);
+    output_rows<T, CC, S, false, PX>(glb((const T *)d.I), d.Irs, glb((T *)d.Q) + (int64_t)c0 * d.Qps, d.Qrs, d.Qps,
+                                     glb(d.mean), d.g, c0, yb, xw);
 }
 
 template <typename T, int TH>
@@ -313,6 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_pbox(const BDesc *__restrict__ D, 
 template <typename T, int S>
 __global__ __launch_bounds__(kThreads) void k_pout(const BDesc *__restrict__ D, int n, unsigned start,
                                                    unsigned count) {
+    constexpr int PX = sizeof(T) == 2 ? 8 : kOutPx;  // out_px(GF_BATCH_PHASES, dtype)
     const unsigned t = (unsigned)xcd_tile((int)blockIdx.x);
     if (t >= count) return;
     const int i = find_image(D, n, 2, start + t);
@@ -321,10 +336,10 @@ __global__ __launch_bounds__(kThreads) void k_pout(const BDesc *__restrict__ D, 
     const unsigned per = (unsigned)(d.ntx_o * d.nty_o);
     const int grp = (int)(local / per), r = (int)(local % per);
     const int c0 = 3 * grp, cc = min(3, d.g.C - c0);
-    const int yb = (r / d.ntx_o) * (4 * kOutRows) + wave_id() * kOutRows, xw = (r % d.ntx_o) * kOutTileW;
-    if (cc == 3) out_cc<T, 3, S>(d, c0, yb, xw);
-    else if (cc == 2) out_cc<T, 2, S>(d, c0, yb, xw);
-    else out_cc<T, 1, S>(d, c0, yb, xw);
+    const int yb = (r / d.ntx_o) * (4 * kOutRows) + wave_id() * kOutRows, xw = (r % d.ntx_o) * (64 * PX);
+    if (cc == 3) out_cc<T, 3, S, PX>(d, c0, yb, xw);
+    else if (cc == 2) out_cc<T, 2, S, PX>(d, c0, yb, xw);
+    else out_cc<T, 1, S, PX>(d, c0, yb, xw);
 }
 
 unsigned grid8u(unsigned n) { return (n + 7u) / 8u * 8u; }

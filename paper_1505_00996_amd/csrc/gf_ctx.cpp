@@ -114,6 +114,14 @@ gf_status gf_ctx_create(gf_ctx **out, int device, size_t arena_bytes, int max_in
     return GF_OK;
 }
 
+gf_status gf_ctx_set_fusion(gf_ctx *ctx, gf_fusion mode) {
+    if (!ctx) return fail(GF_EINVAL, "gf_ctx_set_fusion needs a context");
+    if (mode != GF_FUSE_OFF && mode != GF_FUSE_AUTO && mode != GF_FUSE_ON)
+        return fail(GF_EINVAL, "unknown fusion mode %d", (int)mode);
+    ctx->fuse.store((int)mode);
+    return GF_OK;
+}
+
 gf_status gf_ctx_profile(gf_ctx *ctx, int enable) {
     if (!ctx) return fail(GF_EINVAL, "gf_ctx_profile needs a context");
     std::lock_guard<std::mutex> lk(ctx->prof_mu);

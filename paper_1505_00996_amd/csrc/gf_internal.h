@@ -79,6 +79,23 @@ constexpr size_t color_tile_lds(int TH, int R) {
     return (size_t)2 * (TH + 2 * R) * kRowW * sizeof(double) +
            (size_t)4 * (TH + 2 * R) * region_stride(R) * sizeof(float);
 }
+// Box means fused into the output pass (gf_outbox.h): a block of q is
+// kObRows full-res rows by 64 PX columns.  Low-res rows (columns) that n
+// consecutive full-res rows (columns) at ratio s >= 2 interpolate from: at
+// most ceil((n - 1) / s) + 2; runs of length L starting at multiples of L
+// that cover any np consecutive positions: at most ceil((np - 1) / L) + 1.
+constexpr int kObRows = 32;
+constexpr int ob_patch(int n, int s) { return (n - 1 + s - 1) / s + 2; }
+constexpr int ob_runs(int np, int L) { return (np - 1 + L - 1) / L + 1; }
+constexpr int ob_rows_max(int s, int LC) { return LC * ob_runs(ob_patch(kObRows, s), LC); }
+constexpr int ob_cols_max(int s, int PX) { return kRun * ob_runs(ob_patch(64 * PX, s), kRun); }
+// LDS of a fused block: row sums of a and b over the computed columns for
+// every region row (computed rows + 2R), then the patches of mean_a and
+// mean_b; rows of (computed columns + 1) floats.
+constexpr size_t outbox_lds(int s, int R, int LC, int PX) {
+    return sizeof(float) * (size_t)(ob_cols_max(s, PX) + 1) *
+           (size_t)(2 * (ob_rows_max(s, LC) + 2 * R) + 2 * ob_rows_max(s, LC));
+}
 bool coeff_staged(const TileCfg &t, int R);
 size_t coeff_lds_bytes(const TileCfg &t, int R);
 size_t box_lds_bytes(const TileCfg &t, int R);
@@ -125,6 +142,27 @@ hipError_t launch_box_padded(const float *src, float *dst, const Geo &g, const T
 hipError_t launch_output(gf_dtype dt, const View &I, const View &Q, const float *mean,
                          const Geo &g, const TileCfg &t, hipStream_t st,
                          const Stamp &ts = Stamp{}, const Detail &detail = Detail{});
+
+// Box means fused into the output pass (gf_kernels_outbox.hip), for a gray
+// guide at s in {2, 4, 8}: fused_px gives the pixels per lane of the fused
+// launch for this problem, tiles (the box tile height sets its column runs)
+// and dtype, or 0 when the fused pass does not apply (other ratios, a colour
+// guide, LDS above kObLdsMax).  launch_outbox then replaces launch_box +
+// launch_output, reading a, b (coef: 2C planes) and writing q with the same
+// bits.
+// fuse_pays: the built-in choice (GF_FUSE_AUTO) takes the fused pass for
+// one channel of p on low-res maps of at most kFuseMaxLowres pixels, where
+// the launches are latency-bound and one fewer pays (a 512x512 image at
+// s = 4: 17.5 us against 20.9); with more channels, or on larger maps, the
+// fused pass's halo work and its serial channel loop cost more than the
+// separate pass (512x512 RGB: 28.1 us against 22.0).
+constexpr size_t kObLdsMax = 80 * 1024;
+constexpr int64_t kFuseMaxLowres = 1 << 16;
+int fused_px(const Geo &g, const TileCfg &t, gf_dtype dt);
+bool fuse_pays(const Geo &g);
+hipError_t launch_outbox(gf_dtype dt, const View &I, const View &Q, const float *coef, const Geo &g,
+                         const TileCfg &t, int px, hipStream_t st, const Stamp &ts = Stamp{},
+                         const Detail &detail = Detail{});
 
 // Colour guide (gf_kernels_color.hip): coefficients a_0..a_2, b per channel
 // (4C planes at coef, layout in gf_color.h), from the images or from the

@@ -88,13 +88,22 @@ gf_status gf_tune(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q
         return fail(GF_EDEVICE, "hipEventCreate failed");
     }
     TileCfg chosen = default_tiles(g);
+    // with the box means fused into the output pass, the box tile height
+    // sets the fused pass's column runs: its candidates time that pass
+    const View vQ{q->data, q->row_stride, q->plane_stride};
+    const int mode = ctx->fuse.load();
+    const bool fuse = (mode == GF_FUSE_ON || (mode == GF_FUSE_AUTO && fuse_pays(g))) &&
+                      fused_px(g, chosen, I->dtype) > 0;
     int nres = 0;
     st = GF_OK;
     for (int kernel : {GF_K_COEFF, GF_K_BOX}) {
         double best_ms = 1e30;
         TileCfg best_cfg = chosen;
         for (const TileCfg &c : candidates(g, chosen, kernel)) {
+            const int fpx = kernel == GF_K_BOX && fuse ? fused_px(g, c, I->dtype) : 0;
+            if (kernel == GF_K_BOX && fuse && !fpx) continue;
             auto launch = [&]() -> hipError_t {
+                if (fpx) return launch_outbox(I->dtype, vI, vQ, coef, g, c, fpx, s);
                 if (kernel != GF_K_COEFF) return launch_box(coef, mean, g, c, s);
                 return area_pass(g) ? launch_coeff_lowres(lowres, lowres + g.lps, coef, g, c, s)
                                     : launch_coeff(I->dtype, vI, vP, coef, g, c, s);
@@ -111,7 +120,8 @@ gf_status gf_tune(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *q
                 break;
             }
             const double per = (double)ms / reps;
-            if (results && nres < max_results) results[nres] = gf_tune_result{kernel, to_abi(c), per};
+            if (results && nres < max_results)
+                results[nres] = gf_tune_result{fpx ? GF_K_OUTPUT : kernel, to_abi(c), per};
             ++nres;
             if (per < best_ms) {
                 best_ms = per;

@@ -163,6 +163,10 @@ hipError_t launch_coeff_color_lowres(const float *, const float *, float *, cons
                                      hipStream_t, const Stamp &) {
     return launched();
 }
+hipError_t launch_outbox(gf_dtype, const View &, const View &, const float *, const Geo &, const TileCfg &, int,
+                         hipStream_t, const Stamp &, const Detail &) {
+    return launched();
+}
 hipError_t launch_output_color(gf_dtype, const View &, const View &, const float *, const Geo &, hipStream_t,
                                const Stamp &, const Detail &) {
     return launched();

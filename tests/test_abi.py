@@ -252,3 +252,8 @@ def test_noalloc_host_checks():
     assert L.gf_workspace_bytes(h, w, 3, ctypes.byref(pr1)) > gfp.NOALLOC_MAX_BYTES
     assert L.gf_fast_noalloc(None, *[ctypes.byref(x) for x in big], ctypes.byref(pr1), None) == gfp.GF_ENOMEM
     assert "scratch" in gfp.last_error()
+
+
+def test_fusion_mode_needs_context():
+    assert L.gf_ctx_set_fusion(None, gfp.GF_FUSE_ON) == gfp.GF_EINVAL
+    assert "context" in gfp.last_error()

@@ -32,22 +32,30 @@ def test_every_tile_shape_matches_oracle(h, w, c, r, s, sub):
     ctx.close()
 
 
-def test_tuner_picks_a_candidate_and_persists(tmp_path):
+@pytest.mark.parametrize("fusion", ["off", "on"])
+def test_tuner_picks_a_candidate_and_persists(tmp_path, fusion):
+    """The tuner times the coefficient candidates and the box-mean
+    candidates, or, where the box means are fused into the output pass,
+    that pass's candidates."""
     import torch
     I = synth.photo_guide(300, 400, seed=33)
     p = synth.colour_input(I, 3, seed=34)
     dI, dp = gpuutil.to_device(I), gpuutil.to_device(p)
     ctx = gfp.Context(0)
+    ctx.set_fusion(fusion)
     best, rows = ctx.tune(dI, dp, 16, 4, 1e-3, reps=2)
     assert rows and all(ms > 0 for _, _, ms in rows)
     kernels = {k for k, _, _ in rows}
-    assert kernels == {"coeff", "box"}
-    # the chosen coefficient shape is the fastest coefficient candidate
+    assert kernels == ({"coeff", "box"} if fusion == "off" else {"coeff", "output"})
+    # the chosen shapes are the fastest candidates of each kernel
     fastest = min((ms, t["coeff_th"]) for k, t, ms in rows if k == "coeff")[1]
     assert best["coeff_th"] == fastest
+    fastest_box = min((ms, t["box_th"]) for k, t, ms in rows if k != "coeff")[1]
+    assert best["box_th"] == fastest_box
     path = os.path.join(tmp_path, "tiles.json")
     ctx.save_tuning(path)
     ctx2 = gfp.Context(0)
+    ctx2.set_fusion(fusion)
     ctx2.load_tuning(path)
     q1 = gfp.gf_fast(dI, dp, 16, 4, 1e-3, ctx=ctx)
     q2 = gfp.gf_fast(dI, dp, 16, 4, 1e-3, ctx=ctx2)
