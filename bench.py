@@ -18,6 +18,7 @@ upsample + output pass) from HIP events, and the oracle timed on the host.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -57,6 +58,17 @@ def parse():
                     help="a short run for counter collection: a few fast steps and a copy kernel "
                          "of known size, no oracle")
     return ap.parse_args()
+
+
+def probe_lib():
+    """The bandwidth probes (libgf_bwprobe.so), built first if missing."""
+    import paper_1505_00996_amd.build as gfbuild
+    if not os.path.exists(gfbuild.PROBE_LIB):
+        gfbuild.build_probe()
+    L = ctypes.CDLL(gfbuild.PROBE_LIB)
+    L.gfbw_r1w3.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    L.gfbw_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    return L
 
 
 def lowres(n, s):
@@ -693,6 +705,36 @@ def main():
         "copy_torch_GBs": round(bw(lambda: big2.copy_(big), 2 * big.numel() * 4), 1),
         "fill_torch_GBs": round(bw(lambda: big.fill_(0.5), big.numel() * 4), 1),
     }
+    # Hand-written probes (libgf_bwprobe.so): the output pass's own traffic
+    # (read one 4000x3000 fp32 plane, write three; 16-byte accesses,
+    # non-temporal stores, the output kernel's block shape) over the rotated
+    # input sets, and a 16-byte-vector copy; HIP events on the stream.
+    probe = probe_lib()
+    cs = ctypes.c_void_p(stream.cuda_stream)
+
+    def bw_ev(fn, nbytes, reps=40):
+        fn(0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(reps):
+            fn(i)
+        e1.record()
+        torch.cuda.synchronize()
+        return nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    def r1w3(i):
+        dI, _, q = sets[i % len(sets)]
+        if probe.gfbw_r1w3(ctypes.c_void_p(dI.data_ptr()), ctypes.c_void_p(q.data_ptr()), H, W, cs) != 0:
+            raise RuntimeError("gfbw_r1w3 failed")
+
+    def copy16(i):
+        if probe.gfbw_copy(ctypes.c_void_p(big.data_ptr()), ctypes.c_void_p(big2.data_ptr()),
+                           ctypes.c_int64(big.numel()), cs) != 0:
+            raise RuntimeError("gfbw_copy failed")
+
+    ceilings["read1_write3_probe_GBs"] = round(bw_ev(r1w3, 4 * H * W * 4), 1)
+    ceilings["copy_probe_GBs"] = round(bw_ev(copy16, 2 * big.numel() * 4, reps=20), 1)
     del big, big2, out3
 
     # plain filter kernels (HIP events in the dispatch)
@@ -766,7 +808,8 @@ def main():
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": out_bytes,
-                     "frac_of_copy": round(achieved / ceilings["copy_torch_GBs"], 4)},
+                     "frac_of_copy": round(achieved / ceilings["copy_torch_GBs"], 4),
+                     "frac_of_read1_write3_probe": round(achieved / ceilings["read1_write3_probe_GBs"], 4)},
     }
 
     if not args.no_cpu:

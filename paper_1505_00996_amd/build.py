@@ -15,6 +15,9 @@ LIB = os.path.join(PKG, "libgf.so")
 SOURCES = ["gf_kernels.hip", "gf_kernels_padded.hip", "gf_kernels_color.hip", "gf_kernels_outbox.hip", "gf_batched.hip", "gf_noalloc.hip", "gf_api.cpp", "gf_ctx.cpp", "gf_tune.cpp",
            "gf_batch_host.cpp", "gf_engine.cpp"]
 ARCH = "gfx950"
+# Measurement-only bandwidth probes (bench.py), a library of their own.
+PROBE_SRC = "gf_bwprobe.hip"
+PROBE_LIB = os.path.join(PKG, "libgf_bwprobe.so")
 
 # Packed FP32 instructions are disabled for the device code on purpose.
 HIPFLAGS = [
@@ -95,6 +98,17 @@ def build(out: str = LIB, verbose: bool = False, incremental: bool = False) -> s
     os.replace(tmp, out)
     with open(out + ".sources", "w") as fh:
         fh.write(digest + "\n")
+    if out == LIB:
+        build_probe()
+    return out
+
+
+def build_probe(out: str = PROBE_LIB) -> str:
+    """Compile the bandwidth probes (gf_bwprobe.hip) into their own library."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = out + ".tmp"
+    subprocess.check_call([hipcc, *HIPFLAGS, "-shared", "-o", tmp, os.path.join(CSRC, PROBE_SRC)])
+    os.replace(tmp, out)
     return out
 
 

@@ -249,8 +249,13 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
                    const gf_params *pr, void *ws, size_t ws_bytes, hipStream_t st,
                    const TileCfg *tiles, bool p_low, const float *gain) {
     const Geo g = make_geo(I->h, I->w, p->c, *pr, I->c);
+    const int mode = ctx ? ctx->fuse.load() : GF_FUSE_AUTO;
     // pinned or tuned shapes that do not fit this radius fall back to the built-in choice
-    const TileCfg t = (tiles && tiles_fit(g, *tiles)) ? *tiles : default_tiles(g);
+    TileCfg t = (tiles && tiles_fit(g, *tiles)) ? *tiles : default_tiles(g);
+    // fusion asked for: the built-in box runs for the fused pass (two rows)
+    if (!(tiles && tiles_fit(g, *tiles)) && mode == GF_FUSE_ON && g.G == 1 &&
+        fused_px(g, TileCfg{t.coeff_th, 8}, I->dtype))
+        t.box_th = 8;
     if (!tiles_fit(g, t)) return fail(GF_ENOTSUP, "tile shapes do not fit in LDS for r'=%d", g.R);
     const size_t need = workspace_bytes(g);
     if (!ws) return fail(GF_EINVAL, "no workspace");
@@ -282,7 +287,6 @@ gf_status run_fast(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
                              : launch_coeff(I->dtype, vI, vP, coef, g, t, st, ps.stamp(), p_low);
         ps.commit(e == hipSuccess);
     }
-    const int mode = ctx ? ctx->fuse.load() : GF_FUSE_AUTO;
     const int fpx = !color && (mode == GF_FUSE_ON || (mode == GF_FUSE_AUTO && fuse_pays(g)))
                         ? fused_px(g, t, I->dtype) : 0;
     if (e == hipSuccess && fpx) {

@@ -19,9 +19,12 @@ pytestmark = pytest.mark.gpu
 gfp = gpuutil.ensure_built()
 
 
-def run_pair(dI, dp, r, s, eps, sub, border, tiles=None, call="fast", gain=5.0):
-    """q with fusion on and off (same tiles), and the kernel counts of the
-    fused run."""
+FUSED_TILES = dict(coeff_th=16, box_th=8)
+
+
+def run_pair(dI, dp, r, s, eps, sub, border, tiles=FUSED_TILES, call="fast", gain=5.0):
+    """q with fusion on and off (the same tiles pinned on both contexts), and
+    the kernel counts of the fused run."""
     import torch
     out = []
     counts = None
@@ -119,7 +122,10 @@ def test_fused_detail_and_joint():
         plow = dp[:, 2::4, 2::4].contiguous()
         jf, ju, counts = run_pair(dI, plow, 16, 4, 1e-3, "nearest", "clip", call="joint")
         assert counts["box"] == 0 and bool((jf == ju).all())
-        assert torch.equal(jf, gfp.gf_fast(dI, dp, 16, 4, 1e-3))  # joint of the nearest subsample = fast
+        ctx = gfp.Context(0)  # joint of the nearest subsample = fast, with the same tiles
+        ctx.set_tiles(dI, dp, 16, 4, 1e-3, FUSED_TILES)
+        assert torch.equal(jf, gfp.gf_fast(dI, dp, 16, 4, 1e-3, ctx=ctx))
+        ctx.close()
 
 
 def test_unfused_where_it_does_not_apply():
