@@ -193,10 +193,20 @@ def measure_batched(gfp, torch, dev, n=256, reps=5, seed=6, tune=True):
     ms_graph = (time.perf_counter() - t0) * 1e3 / reps
     del graph
     b.close()
+    ms_queue = None
+    if tune:  # the one-kernel queue schedule (not a tuner candidate by default), for comparison
+        ctx.set_batch_cfg("queue", 24)
+        gfp.gf_fast_batched(Is, ps, prs, qs=qs, ctx=ctx, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            gfp.gf_fast_batched(Is, ps, prs, qs=qs, ctx=ctx, workspace=ws)
+        torch.cuda.synchronize()
+        ms_queue = round((time.perf_counter() - t0) * 1e3 / 3, 3)
     mpix = sum(sp.h * sp.w for sp in specs) / 1e6
     ctx.close()
     return {"images": n, "mpix_per_batch": round(mpix, 1), "ms_per_batch": round(ms, 3),
-            "ms_per_batch_graph": round(ms_graph, 3), "tuned": best,
+            "ms_per_batch_graph": round(ms_graph, 3), "ms_per_batch_queue_schedule_24": ms_queue, "tuned": best,
             "tuner_ms": {f"{c['schedule']}/{c['tile_h']}": round(m, 3) for c, m in tried},
             "value": round(mpix / (ms * 1e-3), 1), "unit": "MPix/s", "dtype": "f16",
             "workload": "256 images, H 256-1536 x W 256-2048 (either orientation), s in {2,4,8}, "
@@ -276,8 +286,9 @@ def measure_16bit(gfp, torch, dev, steps=50, with_oracle=True):
 def measure_small(gfp, torch, dev, calls=300, with_oracle=True):
     """The 512x512 workload (gray guide and input, r = 8, s = 4, eps = 0.01):
     a cache-resident image, so latency rather than bandwidth.  Per-call GPU
-    time from HIP events around each call (median, p99) and host time per
-    call for back-to-back calls."""
+    time from HIP events around each call (median, p99), the same around each
+    replay of the call captured in a HIP graph, the kernels' own durations,
+    and host time per call for back-to-back calls."""
     import numpy as np
     import synth
     I_np, p_np = synth.workload_small()
@@ -286,26 +297,59 @@ def measure_small(gfp, torch, dev, calls=300, with_oracle=True):
     ctx = gfp.Context(0)
     ws = torch.empty(gfp.workspace_bytes(512, 512, 1, 8, 4, 0.01), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
+    # C-ABI arguments built once, so a call is one library call (its host
+    # time is then the library's and HIP's, not the binding's)
+    L = gfp.lib()
+    objs = (gfp.image(dI), gfp.image(dp), gfp.image(q), gfp.params(8, 4, 0.01))
+    args = (ctx._h, *[ctypes.byref(o) for o in objs], ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+            ctypes.c_void_p(stream.cuda_stream))
 
     def call():
-        gfp.gf_fast(dI, dp, 8, 4, 0.01, q=q, ctx=ctx, workspace=ws)
+        rc = L.gf_fast(*args)
+        if rc != 0:
+            raise gfp.GfError(rc, gfp.last_error(ctx))
+
+    def per_call(fn):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return sorted(e0.elapsed_time(e1) * 1e3 for e0, e1 in evs)
+
     for _ in range(20):
         call()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(calls)]
-    for e0, e1 in evs:
-        e0.record(stream)
-        call()
-        e1.record(stream)
-    torch.cuda.synchronize()
-    t = sorted(e0.elapsed_time(e1) * 1e3 for e0, e1 in evs)
+    t = per_call(call)
     t0 = time.perf_counter()
     for _ in range(calls):
         call()
     torch.cuda.synchronize()
     host_us = (time.perf_counter() - t0) * 1e6 / calls
+    # the call captured once into a HIP graph and replayed: GPU time per call
+    # without host launch gaps between its kernels
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gfp.gf_fast(dI, dp, 8, 4, 0.01, q=q, ctx=ctx, workspace=ws)
+    graph.replay()
+    torch.cuda.synchronize()
+    tg = per_call(graph.replay)
+    del graph
+    # the kernels' own durations (events in the dispatches)
+    ctx.profile(True)
+    ctx.profile_read()
+    for _ in range(calls):
+        call()
+    kt = ctx.profile_read()
+    ctx.profile(False)
+    kernel_us = sum(v[0] for v in kt.values()) * 1e3 / calls
+    pick = lambda v, f: round(v[int(f * (len(v) - 1))], 2)
     out = {"workload": "512x512 gray guide and input (rectangles + noise), r=8, s=4, eps=0.01, fp32, nearest",
-           "gpu_us_median": round(t[len(t) // 2], 2), "gpu_us_p99": round(t[int(0.99 * (len(t) - 1))], 2),
+           "gpu_us_median": pick(t, 0.5), "gpu_us_p99": pick(t, 0.99),
+           "graph_us_median": pick(tg, 0.5), "graph_us_p99": pick(tg, 0.99),
+           "kernel_us_per_call": round(kernel_us, 2),
+           "kernels": {k: v[1] // calls for k, v in kt.items() if v[1]},
            "us_per_call_back_to_back": round(host_us, 2), "calls": calls}
     if with_oracle:
         from oracle import oracle

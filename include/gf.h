@@ -316,9 +316,10 @@ typedef struct {
 
 /*
  * Autotuner for batches: times gf_fast_batched on this batch for every
- * schedule and tile height that fits (`reps` launches each, after one
- * warm-up, HIP events on `hip_stream`), sets the fastest as the context's
- * batch configuration and writes it to *best.  Up to max_results timings go
+ * tile height that fits (`reps` launches each, after one warm-up, HIP
+ * events on `hip_stream`), of the phase schedule, or of the queue schedule
+ * when the context's configuration is GF_BATCH_QUEUE, sets the fastest as
+ * the context's batch configuration and writes it to *best.  Up to max_results timings go
  * to results (count in *n_results).  Arguments as gf_fast_batched; q holds
  * the batch's output when it returns.  Synchronises `hip_stream`.
  */

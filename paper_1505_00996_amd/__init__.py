@@ -527,7 +527,8 @@ class Context:
         _check(lib().gf_ctx_set_wait_limit(self._h, -1 if polls is None else int(polls)), self)
 
     def tune_batched(self, Is, ps, prs, qs=None, workspace=None, reps: int = 3, stream=None):
-        """Time every batch schedule and tile height on this batch, keep the
+        """Time every tile height of the phase schedule (of the queue
+        schedule when the context is set to it) on this batch, keep the
         fastest for the context.  Returns (best dict, [(dict, ms), ...])."""
         if qs is None:
             qs = [_out_like(p, None) for p in ps]

@@ -207,7 +207,14 @@ gf_status gf_tune_batched(gf_ctx *ctx, int32_t n, const gf_image *I, const gf_im
     double win_ms = 0.0;
     int found = 0, nres = 0;
     st = GF_OK;
+    // The phase schedule's tile heights are the candidates.  The queue
+    // schedule (one persistent kernel holding every phase's LDS and
+    // registers, so two or three workgroups per CU) is a candidate only when
+    // the context is set to it: on the 256-image mix it took 6.7 ms against
+    // 1.9 ms for the phase grids.
+    const bool queue = saved.schedule == GF_BATCH_QUEUE;
     for (int sched : {GF_BATCH_PHASES, GF_BATCH_QUEUE}) {
+        if ((sched == GF_BATCH_QUEUE) != queue) continue;
         for (int th : {8, 16, 24, 32, 48}) {
             const gf_batch_cfg c{sched, th};
             BatchPlan plan;

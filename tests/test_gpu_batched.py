@@ -99,16 +99,21 @@ def test_batch_rejects_bad_input():
     assert e.value.status == gfp.GF_ENOMEM
 
 
-def test_batch_tuner_picks_a_measured_configuration():
+@pytest.mark.parametrize("schedule", ["phases", "queue"])
+def test_batch_tuner_picks_a_measured_configuration(schedule):
+    """The tuner times the tile heights of the phase schedule, or of the
+    queue schedule when the context is set to it."""
     import torch
     imgs = [make(sp, k, "f16") for k, sp in enumerate(MIX)]
     Is, ps = [a for a, _ in imgs], [b for _, b in imgs]
     prs = [gfp.params(r, s, 1e-3, sub) for (_, _, _, r, s, sub) in MIX]
     ctx = gfp.Context(0)
+    ctx.set_batch_cfg(schedule)
     best, rows = ctx.tune_batched(Is, ps, prs, reps=2)
     assert rows and best in [c for c, _ in rows]
     assert min(rows, key=lambda x: x[1])[0] == best
-    assert {c["schedule"] for c, _ in rows} == {"phases", "queue"}
+    assert {c["schedule"] for c, _ in rows} == {schedule}
+    assert len(rows) >= 3
     # the context now launches batches with the chosen configuration: same bits as solo runs
     qs = gfp.gf_fast_batched(Is, ps, prs, ctx=ctx)
     torch.cuda.synchronize()
