@@ -3,8 +3,6 @@
 //   k_coeff  (grid: low-res tiles)               steps 1-4 -> a, b
 //   k_outbox (grid: full-res 32 x (64 PX) blocks) steps 5-7 -> q
 // instead of k_coeff, k_box, k_output.
-#include <stdlib.h>
-
 #include "gf_outbox.h"
 #include "gf_window_kernels.h"
 
@@ -18,17 +16,13 @@ using namespace dev;
 template <typename T, int S, bool EPI, int PX, int BD>
 __global__ __launch_bounds__(kThreads) void k_outbox(const T *__restrict__ I, int64_t Irs, T *__restrict__ Q,
                                                      int64_t Qrs, int64_t Qps, const float *__restrict__ coef,
-                                                     Geo g, int LC, int ntx, int ntiles, int cpg, int ngrp,
+                                                     Geo g, int LC, int ntx, int ntiles,
                                                      const T *__restrict__ P, int64_t Prs, int64_t Pps, float gain) {
     extern __shared__ double lds_d[];
-    const int id = xcd_tile(blockIdx.x);
-    if (id >= ntiles * ngrp) return;  // uniform per workgroup: no barrier is skipped by part of it
-    // consecutive ids: the channel groups of one block (one XCD, so the
-    // block's guide rows are read from HBM once)
-    const int tile = id / ngrp, cb = (id - tile * ngrp) * cpg;
-    outbox_block<T, S, EPI, PX, BD, false>(I, Irs, Q, Qrs, Qps, coef, g, cb, min(g.C, cb + cpg),
-                                           (tile / ntx) * kObRows, (tile % ntx) * (64 * PX), LC, (float *)lds_d, P,
-                                           Prs, Pps, gain);
+    const int tile = xcd_tile(blockIdx.x);
+    if (tile >= ntiles) return;  // uniform per workgroup: no barrier is skipped by part of it
+    outbox_block<T, S, EPI, PX, BD, false>(I, Irs, Q, Qrs, Qps, coef, g, 0, g.C, (tile / ntx) * kObRows,
+                                           (tile % ntx) * (64 * PX), LC, (float *)lds_d, P, Prs, Pps, gain);
 }
 
 template <typename T, int S, bool EPI, int PX, int BD>
@@ -38,12 +32,9 @@ hipError_t outbox_go(const View &I, const View &Q, const float *coef, const Geo 
     const int ntx = (g.W + tw - 1) / tw, nty = (g.H + kObRows - 1) / kObRows;
     const int ntiles = ntx * nty;
     const size_t lds = outbox_lds(S, g.R, LC, PX);
-    const char *ev = getenv("GF_OB_CPG");
-    const int cpg = ev ? atoi(ev) > 0 ? min(atoi(ev), g.C) : g.C : g.C;
-    const int ngrp = (g.C + cpg - 1) / cpg;
     allow_lds(k_outbox<T, S, EPI, PX, BD>, lds);
-    launch_k(k_outbox<T, S, EPI, PX, BD>, dim3(grid8(ntiles * ngrp)), dim3(kThreads), lds, st, ts.start, ts.stop,
-             (const T *)I.data, I.rs, (T *)Q.data, Q.rs, Q.ps, coef, g, LC, ntx, ntiles, cpg, ngrp,
+    launch_k(k_outbox<T, S, EPI, PX, BD>, dim3(grid8(ntiles)), dim3(kThreads), lds, st, ts.start, ts.stop,
+             (const T *)I.data, I.rs, (T *)Q.data, Q.rs, Q.ps, coef, g, LC, ntx, ntiles,
              EPI ? (const T *)dt.p.data : (const T *)nullptr, dt.p.rs, dt.p.ps, dt.gain);
     return hipGetLastError();
 }
