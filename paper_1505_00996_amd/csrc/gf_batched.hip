@@ -372,11 +372,11 @@ hipError_t phases_t(int thb, const BDesc *D, int n, unsigned p1, unsigned p2, co
         if (!cnt) continue;
         const dim3 grid(grid8u(cnt));
         switch (k) {
-            case 0: hipLaunchKernelGGL((k_pout<T, 1>), grid, block, 0, st, D, n, lo, cnt); break;
-            case 1: hipLaunchKernelGGL((k_pout<T, 2>), grid, block, 0, st, D, n, lo, cnt); break;
-            case 2: hipLaunchKernelGGL((k_pout<T, 4>), grid, block, 0, st, D, n, lo, cnt); break;
-            case 3: hipLaunchKernelGGL((k_pout<T, 8>), grid, block, 0, st, D, n, lo, cnt); break;
-            default: hipLaunchKernelGGL((k_pout<T, 0>), grid, block, 0, st, D, n, lo, cnt); break;
+            case 0: hipLaunchKernelGGL((k_pout<T, 1>), grid, block, kOutResidencyLds, st, D, n, lo, cnt); break;
+            case 1: hipLaunchKernelGGL((k_pout<T, 2>), grid, block, kOutResidencyLds, st, D, n, lo, cnt); break;
+            case 2: hipLaunchKernelGGL((k_pout<T, 4>), grid, block, kOutResidencyLds, st, D, n, lo, cnt); break;
+            case 3: hipLaunchKernelGGL((k_pout<T, 8>), grid, block, kOutResidencyLds, st, D, n, lo, cnt); break;
+            default: hipLaunchKernelGGL((k_pout<T, 0>), grid, block, kOutResidencyLds, st, D, n, lo, cnt); break;
         }
     }
     return hipGetLastError();

@@ -45,6 +45,13 @@ constexpr int kTileW = 64;      // low-res tile width of the window-sum kernels
 constexpr int kRun = 8;         // consecutive outputs per thread in a row pass
 constexpr int kOutPx = 4;       // full-res pixels per lane in the output kernel
 constexpr int kOutTileW = 64 * kOutPx;  // full-res columns per output tile
+// Dynamic LDS that every output-pass launch reserves and never touches: with
+// it at most three workgroups (12 waves) share a CU.  The pass writes HBM
+// faster with fewer waves in flight than its registers allow (four or more):
+// on the 4000x3000 RGB fp32 output pass 37.4 -> 35.3 us at s = 4, 36.2 ->
+// 32.6 at s = 8, 45.1 -> 41.5 at s = 2, 97.5 -> 87.8 at s = 1.  Kernels that
+// their registers already hold to three workgroups per CU are unaffected.
+constexpr size_t kOutResidencyLds = 48 << 10;
 constexpr int kMaxRadius = 64;  // largest low-res radius the LDS tile buffers hold
 constexpr int kCUs = 256;       // compute units of an MI355X (grid-size heuristics)
 // Polls of the queue schedule's bounded wait before a tile gives up on the

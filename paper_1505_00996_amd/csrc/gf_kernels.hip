@@ -138,7 +138,7 @@ hipError_t output_cc(const View &I, const View &Q, const float *mean, const Geo 
     const T *Pp = EPI ? (const T *)dt.p.data + (int64_t)c0 * dt.p.ps : nullptr;
     const dim3 grid(grid8(ntiles)), block(kThreads);
 #define GF_OUT(SS)                                                                                       \
-    launch_k(k_output<T, CC, SS, EPI>, grid, block, 0, st, e0, e1, Ip, I.rs, Qp, Q.rs, Q.ps, mean, g, c0, ntx, \
+    launch_k(k_output<T, CC, SS, EPI>, grid, block, kOutResidencyLds, st, e0, e1, Ip, I.rs, Qp, Q.rs, Q.ps, mean, g, c0, ntx, \
              ntiles, Pp, dt.p.rs, dt.p.ps, dt.gain)
     switch (g.s) {
         case 1: GF_OUT(1); break;
