@@ -253,7 +253,7 @@ def measure_16bit(gfp, torch, dev, steps=50, with_oracle=True):
         out_ms = kt["output"][0] / max(kt["output"][1], 1)
         ob = output_kernel_bytes(h, w, c, s, elem=2)
         # The same steps writing q into rows padded to a multiple of 256 bytes
-        # (12288 instead of 12000): the output pass's non-temporal row stores
+        # (12032 instead of 12000): the output pass's non-temporal row stores
         # are slower when a row starts at an odd multiple of 32 bytes.
         wp = (w * 2 + 255) // 256 * 128
         qpad = [torch.empty((c, h, wp), dtype=dt, device=dev)[:, :, :w] for _ in sets]
