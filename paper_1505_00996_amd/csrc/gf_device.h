@@ -644,12 +644,13 @@ __device__ __forceinline__ void box_tile(const float *__restrict__ S, float *__r
 //
 // A wave covers kOutRows = 8 rows starting at a multiple of 8 and 64 PX
 // full-res columns, PX pixels per lane: 4 for fp32 and 8 for 16-bit storage
-// in the per-image kernel, so that every row access is 16 bytes (the
-// batched kernels use 4).  A lane first loads its 8 x PX guide pixels (all
-// loads in flight together); then, channel by channel, it loads the low-res
-// rows and columns of mean_a, mean_b its pixels interpolate from,
-// interpolates them horizontally once, and for every row finishes the
-// bilinear weights and writes q = a*I + b with non-temporal stores.
+// in the per-image kernel and the batched output grids, so that every row
+// access is 16 bytes (the queue kernel's output blocks use 4).  A lane first
+// loads its 8 x PX guide pixels (all loads in flight together); then,
+// channel by channel, it loads the low-res rows and columns of mean_a,
+// mean_b its pixels interpolate from, interpolates them horizontally once,
+// and for every row finishes the bilinear weights and writes q = a*I + b
+// with non-temporal stores.
 //
 // Upsampling geometry (half-pixel centres): full-res x maps to low-res
 // u = (x + 0.5)/s - 0.5 = (2x + 1 - s) / (2s), taps floor(u), floor(u) + 1
