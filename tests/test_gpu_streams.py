@@ -47,3 +47,34 @@ def test_side_stream_batched_and_plain():
     side.synchronize()
     del junk
     assert torch.equal(qb[0], ref_b[0]) and torch.equal(qb[1], ref_b[1]) and torch.equal(qp, ref_p)
+
+
+def test_consecutive_images_on_two_streams():
+    """Independent images alternated over two streams, each with its own
+    context and workspace (the two-stream throughput that bench.py reports):
+    the kernels of one image run beside the other's, and every output equals
+    the same image filtered alone on the current stream."""
+    import torch
+    imgs = []
+    for k in range(6):
+        I = synth.photo_guide(600 + 40 * k, 800 - 24 * k, seed=31 + k)
+        imgs.append((gpuutil.to_device(I), gpuutil.to_device(synth.colour_input(I, 1 + 2 * (k % 2), seed=41 + k))))
+    refs = [gfp.gf_fast(I, p, 12, 4, 1e-3) for I, p in imgs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ctxs = [gfp.Context(0), gfp.Context(0)]
+    ws = [torch.empty(max(gfp.workspace_bytes(I.shape[-2], I.shape[-1], p.shape[0], 12, 4, 1e-3) for I, p in imgs),
+                      dtype=torch.uint8, device="cuda") for _ in range(2)]
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for rep in range(3):
+        for k, (I, p) in enumerate(imgs):
+            outs.append((k, gfp.gf_fast(I, p, 12, 4, 1e-3, ctx=ctxs[k % 2], workspace=ws[k % 2],
+                                        stream=streams[k % 2])))
+    for st in streams:
+        st.synchronize()
+    for c in ctxs:
+        c.close()
+    bad = [k for k, q in outs if not torch.equal(q, refs[k])]
+    assert not bad, f"images {bad} differ from the one-stream results"
