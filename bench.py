@@ -35,7 +35,7 @@ R_FULL, S, EPS = 16, 4, 1e-3
 HBM_PEAK_GBS = 8000.0
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_output_12mp_fp32_counters.txt")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1505_00996_amd", "csrc", f)
-               for f in ("gf_device.h", "gf_kernels.hip")]
+               for f in ("gf_device.h", "gf_kernels.hip", "gf_internal.h")]
 
 
 def parse():
