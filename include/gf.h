@@ -184,7 +184,7 @@ gf_status gf_plain(gf_ctx *ctx, const gf_image *I, const gf_image *p, gf_image *
  * upsample mean_a, mean_b bilinearly and output q = mean_a .* I + mean_b
  * against the full-resolution I.  Same shapes, ownership and stream rules as
  * gf_plain.  With params->s == 1 it is gf_plain.  Independent images on
- * separate streams (each call with its own context or workspace) overlap on
+ * separate streams (each with its own context and workspace) overlap on
  * the GPU: one image's low-resolution passes run beside another's output
  * pass.  The output pass reserves 48 KB of LDS per workgroup it does not use
  * (at most three of its workgroups per CU), which kernels running beside it
