@@ -324,8 +324,13 @@ __global__ __launch_bounds__(kThreads) void k_pbox(const BDesc *__restrict__ D, 
     run_box<TH, false>(D[i], start + t - D[i].base[1], lds_d);
 }
 
+// fp16 at s = 2 is held to 168 VGPRs (three waves per SIMD instead of two, a
+// few values spilled): the 256-image batch 1.937 -> 1.913 ms, the same bits.
+// (bf16 at s = 2 would spill over a hundred values; the other ratios already
+// fit three.)
 template <typename T, int S>
-__global__ __launch_bounds__(kThreads) void k_pout(const BDesc *__restrict__ D, int n, unsigned start,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
+    std::is_same<T, _Float16>::value && S == 2 ? 3 : 1))) void k_pout(const BDesc *__restrict__ D, int n, unsigned start,
                                                    unsigned count) {
     constexpr int PX = sizeof(T) == 2 ? 8 : kOutPx;  // out_px(GF_BATCH_PHASES, dtype)
     const unsigned t = (unsigned)xcd_tile((int)blockIdx.x);
