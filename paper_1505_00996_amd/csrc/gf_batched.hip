@@ -329,9 +329,9 @@ __global__ __launch_bounds__(kThreads) void k_pbox(const BDesc *__restrict__ D, 
 // (bf16 at s = 2 would spill over a hundred values; the other ratios already
 // fit three.)
 template <typename T, int S>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
-    std::is_same<T, _Float16>::value && S == 2 ? 3 : 1))) void k_pout(const BDesc *__restrict__ D, int n, unsigned start,
-                                                   unsigned count) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(std::is_same<T, _Float16>::value && S == 2 ? 3 : 1)))
+void k_pout(const BDesc *__restrict__ D, int n, unsigned start, unsigned count) {
     constexpr int PX = sizeof(T) == 2 ? 8 : kOutPx;  // out_px(GF_BATCH_PHASES, dtype)
     const unsigned t = (unsigned)xcd_tile((int)blockIdx.x);
     if (t >= count) return;

@@ -323,7 +323,7 @@ __device__ __forceinline__ void output_rows_color(const T *__restrict__ I, int64
             // order are those of combine(), with one map's low-res values and
             // interpolations live at a time.  Fewer registers (4000x3000 RGB
             // fp32 at s = 4: 143 VGPRs against 184, three waves per SIMD against
-            // two): 60.5 -> 56.1 us, fp16 76.0 -> 58.0 us, detail 92.0 -> 80.5
+            // two): 60.5 -> 55.8 us, fp16 76.0 -> 57.5 us, detail 92.0 -> 80.3
             // us; at s = 8 (115 against 136 VGPRs) it was slower, 54.1 against
             // 52.6 us, so s = 8 forms the four maps' values first.
 #pragma unroll 1
